@@ -1,0 +1,175 @@
+"""Reference (oracle) implementation -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow CPU implementation (C, FP64) of the Monte Carlo KS critical-value
+method of Rappos & Robert (2013) for the pure discrete power law, used to check
+the GPU library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package; the product path never
+does.  The C source is ``zpl_oracle.c``; this module builds it with gcc and
+wraps it with ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "zpl_oracle.c"
+_LIB = _HERE / "libzpl_oracle.so"
+
+TABLE_H = 4096
+FLAG_ALL_ONES = 1
+FLAG_TAIL_CAPPED = 2
+FLAG_BISECT = 4
+FLAG_NOCONV = 8
+
+_lib = None
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc (plain -O2, no vector intrinsics)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp%d" % os.getpid())
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", str(_SRC), "-o", str(tmp),
+               "-lquadmath", "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build(force=True)
+        L = C.CDLL(str(_LIB))
+        d, i64, u32, u64 = C.c_double, C.c_int64, C.c_uint32, C.c_uint64
+        P = C.POINTER
+        L.orc_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        L.orc_u53.argtypes = [u32, u32]
+        L.orc_u53.restype = d
+        L.orc_hurwitz3.argtypes = [d, d, P(d)]
+        L.orc_zeta3.argtypes = [d, P(d)]
+        L.orc_cdf.argtypes = [d, i64]
+        L.orc_cdf.restype = d
+        L.orc_cdf_table.argtypes = [d, P(d), C.c_int]
+        L.orc_draw.argtypes = [d, P(d), u64, u32, u32, u32, P(u32)]
+        L.orc_draw.restype = i64
+        L.orc_sample.argtypes = [d, P(d), i64, u64, u32, u32, P(i64), P(u32)]
+        L.orc_mle.argtypes = [d, P(u32)]
+        L.orc_mle.restype = d
+        L.orc_fit.argtypes = [P(i64), i64, P(d), P(d), P(d), P(u32)]
+        L.orc_fit.restype = C.c_int
+        L.orc_simulate.argtypes = [d, i64, u64, u32, i64, i64, P(d), P(d), P(d),
+                                   P(u32), P(u64), P(i64), C.c_int]
+        L.orc_simulate.restype = C.c_int
+        L.orc_quantile.argtypes = [P(d), i64, u32, u32]
+        L.orc_quantile.restype = d
+        L.orc_bootstrap_pvalue.argtypes = [P(i64), i64, i64, u64, u32, P(d), P(d),
+                                           P(d), P(u32), C.c_int]
+        L.orc_bootstrap_pvalue.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def u53(hi: int, lo: int) -> float:
+    return lib().orc_u53(hi, lo)
+
+
+def hurwitz3(s: float, q: float):
+    out = np.zeros(3)
+    lib().orc_hurwitz3(s, q, _ptr(out, C.c_double))
+    return out
+
+
+def zeta3(s: float):
+    out = np.zeros(3)
+    lib().orc_zeta3(s, _ptr(out, C.c_double))
+    return out
+
+
+def cdf(alpha: float, t: int) -> float:
+    return lib().orc_cdf(alpha, int(t))
+
+
+def cdf_table(alpha: float, H: int = TABLE_H) -> np.ndarray:
+    T = np.zeros(H)
+    lib().orc_cdf_table(alpha, _ptr(T, C.c_double), H)
+    return T
+
+
+def sample(alpha: float, n: int, seed: int, stream: int, rep: int):
+    """n draws of one replicate in draw order -> (int64 array, flags)."""
+    T = cdf_table(alpha)
+    x = np.zeros(n, dtype=np.int64)
+    f = C.c_uint32(0)
+    lib().orc_sample(alpha, _ptr(T, C.c_double), n, seed, stream, rep,
+                     _ptr(x, C.c_int64), C.byref(f))
+    return x, f.value
+
+
+def mle(m: float):
+    f = C.c_uint32(0)
+    a = lib().orc_mle(m, C.byref(f))
+    return a, f.value
+
+
+def fit(x) -> dict:
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    S, a, D = C.c_double(), C.c_double(), C.c_double()
+    f = C.c_uint32(0)
+    rc = lib().orc_fit(_ptr(x, C.c_int64), x.size, C.byref(S), C.byref(a), C.byref(D),
+                       C.byref(f))
+    if rc != 0:
+        raise ValueError("oracle fit: invalid dataset (n < 1 or some x < 1)")
+    return {"S": S.value, "alpha_hat": a.value, "D": D.value, "flags": f.value}
+
+
+def simulate(alpha: float, n: int, seed: int, stream: int, rep_lo: int, count: int,
+             nthreads: int = 0) -> dict:
+    D = np.zeros(count)
+    A = np.zeros(count)
+    S = np.zeros(count)
+    F = np.zeros(count, dtype=np.uint32)
+    FP = np.zeros(count, dtype=np.uint64)
+    XM = np.zeros(count, dtype=np.int64)
+    rc = lib().orc_simulate(alpha, n, seed, stream, rep_lo, count,
+                            _ptr(D, C.c_double), _ptr(A, C.c_double), _ptr(S, C.c_double),
+                            _ptr(F, C.c_uint32), _ptr(FP, C.c_uint64), _ptr(XM, C.c_int64),
+                            nthreads)
+    if rc != 0:
+        raise ValueError("oracle simulate: invalid cell")
+    return {"D": D, "alpha_hat": A, "S": S, "flags": F, "fp": FP, "xmax": XM}
+
+
+def quantile(D, num: int, den: int) -> float:
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    return lib().orc_quantile(_ptr(D, C.c_double), D.size, num, den)
+
+
+def bootstrap_pvalue(x, B: int, seed: int, stream: int, nthreads: int = 0) -> dict:
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    a, D, p = C.c_double(), C.c_double(), C.c_double()
+    f = C.c_uint32(0)
+    rc = lib().orc_bootstrap_pvalue(_ptr(x, C.c_int64), x.size, B, seed, stream,
+                                    C.byref(a), C.byref(D), C.byref(p), C.byref(f),
+                                    nthreads)
+    if rc != 0:
+        raise ValueError("oracle bootstrap: invalid input")
+    return {"alpha_hat": a.value, "D": D.value, "p_value": p.value, "flags": f.value}
