@@ -1,0 +1,176 @@
+"""Benchmark: Monte Carlo replicates per second (draw + MLE + KS + quantile
+selection) for the n = 1000 slice of the full critical-value table (9
+exponents 1.5..3.5 x n = 1000 x R = 100,000), batched (one persistent launch)
+vs plain (one launch per cell), plus fit latency.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  A step is one call of zpl_simulate_cells on the whole
+slice: table build, every replicate's draws, histogram, MLE and KS, and the
+per-cell order statistics, with inputs (the cell list) resident; the host
+reads back the quantiles each step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "MC replicates/sec (sample+MLE+KS) batched vs plain at n=1000; p99 fit latency"
+QS = [(9, 10), (95, 100), (99, 100), (999, 1000)]
+
+# Algorithmic VALU work model (ops per draw and per replicate), see the design doc:
+# Philox4x32-10 = 10 rounds x (2 32x32->64 multiplies as 2 ops each + 2
+# three-way xors as 2 ops each) = 80 ops per block of 2 draws; the 53-bit
+# uniform 3 ops; guide lookup + table compare 4 ops; histogram update 2 ops.
+OPS_PER_DRAW = 40 + 3 + 4 + 2
+# MLE (about 5 Newton steps of 17 exp-equivalents x 20 ops) + KS + sums.
+OPS_PER_REPLICATE = 2000
+# VALU lane-op peak: 256 CUs x 64 lanes x 2.4 GHz.
+PEAK_OPS = 256 * 64 * 2.4e9
+
+
+def percentile(v, p):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), p)) if len(v) else None
+
+
+def cpu_baseline(cells, target_s=12.0):
+    """The oracle on a bounded sample of the same cells (all host cores)."""
+    import oracle
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    pilot = 64
+    t0 = time.perf_counter()
+    for (a, n, R, seed, st) in cells:
+        oracle.simulate(a, n, seed, st, 0, pilot, nthreads=cores)
+    tp = time.perf_counter() - t0
+    reps = int(max(pilot, min(20000, pilot * target_s / max(tp, 1e-3))))
+    t0 = time.perf_counter()
+    for (a, n, R, seed, st) in cells:
+        oracle.simulate(a, n, seed, st, 0, reps, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": len(cells) * reps / dt, "unit": "replicates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "first %d replicates of each of the %d cells (%.1f s on %d threads)"
+                      % (reps, len(cells), dt, cores)}
+
+
+def fit_latency(ctx, n_req=200):
+    from inputs import serving_requests
+    reqs = serving_requests(duration_s=1e9, qps=1.0, seed=11)[:n_req]
+    lat = []
+    for (_, x, _, _) in reqs:
+        t0 = time.perf_counter()
+        ctx.fit(x)
+        lat.append((time.perf_counter() - t0) * 1e3)
+    return {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "requests": len(lat),
+            "what": "zpl_fit of a host int64 dataset (n log-uniform 50..1e5), H2D included"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--replicates", type=int, default=100000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the batched timed region (for profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from inputs import table_slice
+    from paper_1305_6738_amd import Context
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    cells = table_slice(n=1000, R=args.replicates)
+    total_R = sum(c[2] for c in cells)
+    ctx = Context(0)
+    d = torch.empty(total_R, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx.set_timing(True)
+
+    for _ in range(args.warmup):
+        ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+    torch.cuda.synchronize()
+    sim_ms, all_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q = ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+        tm = ctx.timing()
+        sim_ms.append(tm["simulate"] + tm["heavy"])
+        all_ms.append(tm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = total_R / (ms_per_step / 1e3)
+
+    # dominant kernel: the persistent simulation launch
+    sim_avg_ms = sum(sim_ms) / len(sim_ms)
+    ops = sum(R * (n * OPS_PER_DRAW + OPS_PER_REPLICATE) for (a, n, R, s, st) in cells)
+    achieved = ops / (sim_avg_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
+                "unit": "Tops/s", "frac": achieved / PEAK_OPS, "traffic": None,
+                "kernel": "k_simulate", "kernel_ms": sim_avg_ms,
+                "ops_per_launch": ops}
+
+    out = {"metric": METRIC, "value": value, "unit": "replicates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "full-table slice n=1000: alpha 1.5..3.5 step 0.25 (9 cells) "
+                                  "x R=%d, seed 42, batched persistent launch" % args.replicates,
+                      "n": 1000, "cells": len(cells), "replicates_per_cell": args.replicates,
+                      "quantiles": ["%d/%d" % qq for qq in QS], "launch": "batched"},
+           "kernel_ms": {k: sum(t[k] for t in all_ms) / len(all_ms) for k in all_ms[0]},
+           "roofline": roofline}
+
+    if not args.no_extras:
+        # plain: one launch per cell
+        nplain = max(3, args.steps // 4)
+        ctx.simulate_cells(cells, quantiles=QS, d_out=d, launch="plain", stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nplain):
+            ctx.simulate_cells(cells, quantiles=QS, d_out=d, launch="plain", stream=stream)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3 / nplain
+        out["plain_value"] = total_R / (plain_ms / 1e3)
+        out["plain_ms_per_step"] = plain_ms
+        out["batched_over_plain"] = value / out["plain_value"]
+        # batched launch replayed from a hipGraph
+        ctx.simulate_cells(cells, quantiles=QS, d_out=d, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.simulate_cells(cells, quantiles=QS, d_out=d, use_graph=True, stream=stream)
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["graph_value"] = total_R / (g_ms / 1e3)
+        out["fit_latency"] = fit_latency(ctx)
+        out["quantiles_first_cell"] = [float(v) for v in q[0]]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cells)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

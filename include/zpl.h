@@ -1,0 +1,176 @@
+/*
+ * zpl.h -- C ABI of libzpl, the MI355X (gfx950) implementation of the Monte
+ * Carlo Kolmogorov-Smirnov method for the discrete power law of
+ * E. Rappos and S. Robert, "Using GPU Simulation to Accurately Fit to the
+ * Power-Law Distribution" (2013), for the pure (untruncated) law with xmin = 1.
+ *
+ * The method (Sect. 1-4 of the paper):
+ *   eq. (1)  p(k) = k^-alpha / zeta(alpha),  k = 1, 2, ...
+ *   eq. (2)  alpha_hat solves zeta'(a)/zeta(a) = -(1/N) sum_i ln x_i   (MLE)
+ *   eq. (3)  D = sup_x |F(x; alpha_hat) - S_N(x)|                      (KS)
+ * Critical values of D depend on N and alpha_hat because alpha is estimated
+ * from the data, so they are obtained by simulation (Sect. 3): draw N values
+ * at alpha, refit alpha by MLE, compute D, repeat, and read order statistics
+ * of the simulated D.  Sect. 4 recommends a bespoke cutoff simulated at the
+ * sample's own (N, alpha_hat); zpl_bootstrap_pvalue computes it as a p-value.
+ *
+ * Conventions this library fixes where the paper leaves a choice:
+ *   - Random numbers: Philox4x32-10 with key = seed (low word first) and
+ *     counter = (j, replicate, stream, 0) for draws 2j and 2j+1 (words 0-1
+ *     and 2-3); tail proposals use counter (i, replicate, stream,
+ *     0x80000000 | attempt).  Every draw is a pure function of (seed,
+ *     stream, replicate, index): results never depend on launch shape.
+ *   - U = ((w_hi:w_lo >> 11) | 1) * 2^-53.  x = min{k <= 4096 : F(k) >= U}
+ *     (the paper's ">=" rule) when U <= F(4096); otherwise x comes from a
+ *     rejection sampler on k >= 4097 conditioned on x < 2^63.
+ *   - If every draw is 1, S = sum ln x is taken as ln 2 (the paper's rule).
+ *   - alpha_hat is solved to full double precision on [1 + 2^-20, 64].
+ *   - Quantile q = num/den of R values is the ascending order statistic at
+ *     0-based index floor(R * num / den) (the paper's integer index rule).
+ *   - p-value = #{b : D_b >= D_obs} / B.
+ *
+ * Memory: "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ * device memory on the context's GPU (e.g. a torch tensor's data_ptr()).  The
+ * caller owns every buffer it passes; the library reads or writes them only
+ * until the call returns (host buffers) or until the given stream reaches the
+ * end of the work the call enqueued (device buffers), and never frees them.
+ * The context owns all scratch memory.  A stream argument is a hipStream_t
+ * (NULL = the null stream); calls that return host results synchronise it.
+ *
+ * Errors: every function returns a zpl_status; nothing is thrown across the
+ * ABI.  On failure zpl_last_error() describes the error (per thread, valid
+ * until the next call on that thread).  A context is not thread-safe: calls
+ * on one context must be serialised by the caller.
+ */
+#ifndef ZPL_H
+#define ZPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t zpl_status;
+#define ZPL_OK 0
+#define ZPL_EINVAL (-1)   /* invalid argument (n < 1, x < 1, alpha <= 1, ...) */
+#define ZPL_ENOMEM (-2)   /* device memory or the context's budget exhausted   */
+#define ZPL_EDEVICE (-3)  /* HIP runtime or kernel error                        */
+#define ZPL_ENOCONV (-4)  /* the MLE solver did not converge (fit only)         */
+#define ZPL_EBUSY (-5)    /* serving: not admissible now, retry later           */
+#define ZPL_ENOTFOUND (-6) /* serving: unknown ticket                          */
+
+/* Per-replicate / per-fit flags. */
+#define ZPL_FLAG_ALL_ONES 1u    /* every value was 1; S replaced by ln 2          */
+#define ZPL_FLAG_TAIL_CAPPED 2u /* a tail proposal >= 2^63 was redrawn            */
+#define ZPL_FLAG_BISECT 4u      /* the MLE solver took a bisection step (info)    */
+#define ZPL_FLAG_NOCONV 8u      /* the MLE solver hit its iteration cap           */
+
+typedef struct zpl_ctx zpl_ctx;
+
+/* One (alpha, n) cell of a critical-value table (Sect. 3, Table 1): R
+ * replicates of n draws at exponent alpha (> 1), random stream (seed,
+ * stream).  Replicate r of the cell is the same whatever else is computed
+ * alongside it.  alpha must lie in [1.01, 64]: closer to 1 the law puts so
+ * much mass at or above 2^63 that the capped tail sampler slows down. */
+typedef struct zpl_cell {
+  double alpha;
+  int64_t n;
+  int64_t replicates;
+  uint64_t seed;
+  uint32_t stream;
+  uint32_t reserved; /* must be 0 */
+} zpl_cell;
+
+/* Launch form of zpl_simulate_cells. */
+#define ZPL_LAUNCH_BATCHED 0 /* one persistent launch over every cell (default) */
+#define ZPL_LAUNCH_PLAIN 1   /* one launch per cell                              */
+
+/* Per-cell execution form (the planner's choice unless forced). */
+#define ZPL_FORM_AUTO 0
+#define ZPL_FORM_LANE 1  /* one replicate per lane                     */
+#define ZPL_FORM_WAVE 2  /* one replicate per wave, finishes per lane  */
+#define ZPL_FORM_HEAVY 3 /* one replicate per wave, global overflow    */
+
+typedef struct zpl_sim_opts {
+  int32_t launch;    /* ZPL_LAUNCH_*                                     */
+  int32_t form;      /* ZPL_FORM_*: force one form for every cell         */
+  int32_t use_graph; /* 1: capture the batched launch in a hipGraph and
+                        replay it when the same cell list is simulated
+                        again                                            */
+  int32_t reserved;  /* must be 0 */
+} zpl_sim_opts;
+
+/* Create a context on HIP device `device`.  mem_budget_bytes caps the
+ * device scratch the context may hold (0 = 64 GiB). */
+zpl_status zpl_create(zpl_ctx **out, int32_t device, uint64_t mem_budget_bytes);
+
+/* Destroy a context and free its device memory.  NULL is ignored. */
+void zpl_destroy(zpl_ctx *ctx);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *zpl_last_error(void);
+
+/* Simulate critical-value cells (Sect. 3 and 4; Table 1 is such a table).
+ *   cells[n_cells]           host; alpha in [1.01, 64], 1 <= n <= 2^31,
+ *                            1 <= replicates <= 2^32.
+ *   q_num[n_q], q_den[n_q]   host; quantile num/den with num < den.
+ *   quantiles                host [n_cells * n_q] (row per cell) or NULL.
+ *   d_out, alpha_hat_out     device [sum of replicates] FP64, or NULL;
+ *   flags_out                device [sum of replicates] uint32, or NULL;
+ *   fingerprint_out          device [sum of replicates] uint64, or NULL:
+ *                            sum over draws of splitmix64's finaliser of the
+ *                            value, mod 2^64 (a multiset checksum).
+ *   Replicate r of cell c is at index (sum of replicates of cells < c) + r.
+ *   opts may be NULL (batched, automatic forms, no graph).
+ * Returns after the stream has finished when quantiles != NULL. */
+zpl_status zpl_simulate_cells(zpl_ctx *ctx, const zpl_cell *cells, int32_t n_cells,
+                              const uint32_t *q_num, const uint32_t *q_den, int32_t n_q,
+                              double *quantiles, double *d_out, double *alpha_hat_out,
+                              uint32_t *flags_out, uint64_t *fingerprint_out,
+                              const zpl_sim_opts *opts, void *stream);
+
+/* Per-kernel timing of simulations (HIP events on the call's stream).
+ * zpl_set_timing(ctx, 1) makes every later non-graph zpl_simulate_cells
+ * record events around its kernels; zpl_get_timing then waits for the last
+ * such call and writes ms4[0..3] = milliseconds spent in the table build,
+ * the lane/wave simulation launches, the heavy/escalation launch and the
+ * quantile selection.  ZPL_EINVAL if no timed call happened. */
+zpl_status zpl_set_timing(zpl_ctx *ctx, int32_t enable);
+zpl_status zpl_get_timing(zpl_ctx *ctx, double *ms4);
+
+/* Fit one dataset (Sect. 4 usage): alpha_hat from eq. (2) and D from eq. (3).
+ *   x[n]  host (x_on_device = 0) or device (1) int64, every x >= 1.
+ *   alpha_hat, D, flags  host outputs.
+ * Returns ZPL_EINVAL for n < 1 or any x < 1, ZPL_ENOCONV (outputs still set)
+ * if the solver hit its iteration cap.  Synchronises the stream. */
+zpl_status zpl_fit(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
+                   double *alpha_hat, double *D, uint32_t *flags, void *stream);
+
+/* Bespoke cutoff of Sect. 4 as a parametric-bootstrap p-value: fit x, then
+ * simulate B replicates of n draws at alpha_hat (random stream (seed,
+ * stream_id)), refit each by MLE (the tables apply only to MLE fits), and
+ * return p = #{b : D_b >= D_obs} / B with alpha_hat, D_obs and the fit's
+ * flags.  Synchronises the stream. */
+zpl_status zpl_bootstrap_pvalue(zpl_ctx *ctx, const int64_t *x, int64_t n,
+                                int32_t x_on_device, int64_t B, uint64_t seed,
+                                uint32_t stream_id, double *alpha_hat, double *D,
+                                double *p_value, uint32_t *flags, void *stream);
+
+/* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, n, seed,
+ * stream_id) in draw order, for checking the sampler bit for bit.
+ *   x_out     device [count * n] int64;  flags_out device [count] uint32
+ *             (ZPL_FLAG_TAIL_CAPPED per replicate).
+ * Asynchronous on `stream`. */
+zpl_status zpl_sample_draws(zpl_ctx *ctx, double alpha, int64_t n, uint64_t seed,
+                            uint32_t stream_id, int64_t rep_lo, int64_t count,
+                            int64_t *x_out, uint32_t *flags_out, void *stream);
+
+/* The FP64 CDF table F(k; alpha), k = 1..4096, the sampler searches.
+ *   T_out  device [4096].  Asynchronous on `stream`. */
+zpl_status zpl_cdf_table(zpl_ctx *ctx, double alpha, double *T_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZPL_H */

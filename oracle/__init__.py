@@ -59,6 +59,8 @@ def lib():
         L.orc_cdf_table.argtypes = [d, P(d), C.c_int]
         L.orc_draw.argtypes = [d, P(d), u64, u32, u32, u32, P(u32)]
         L.orc_draw.restype = i64
+        L.orc_tail_draw.argtypes = [d, u64, u32, u32, u32, P(u32)]
+        L.orc_tail_draw.restype = i64
         L.orc_sample.argtypes = [d, P(d), i64, u64, u32, u32, P(i64), P(u32)]
         L.orc_mle.argtypes = [d, P(u32)]
         L.orc_mle.restype = d
@@ -121,6 +123,12 @@ def sample(alpha: float, n: int, seed: int, stream: int, rep: int):
     f = C.c_uint32(0)
     lib().orc_sample(alpha, _ptr(T, C.c_double), n, seed, stream, rep,
                      _ptr(x, C.c_int64), C.byref(f))
+    return x, f.value
+
+
+def tail_draw(alpha: float, seed: int, stream: int, rep: int, i: int):
+    f = C.c_uint32(0)
+    x = lib().orc_tail_draw(alpha, seed, stream, rep, i, C.byref(f))
     return x, f.value
 
 

@@ -203,7 +203,7 @@ static double tail_g(double beta, double k) {
   return 1.0 / (-k * expm1(-beta * log1p(1.0 / k)));
 }
 
-static int64_t tail_draw(double alpha, uint64_t seed, uint32_t stream,
+int64_t orc_tail_draw(double alpha, uint64_t seed, uint32_t stream,
                          uint32_t rep, uint32_t i, uint32_t *flags) {
   const double beta = alpha - 1.0; /* exact in FP64 for alpha > 1 */
   const double m = (double)(ORC_TABLE_H + 1);
@@ -234,7 +234,7 @@ int64_t orc_draw(double alpha, const double *T, uint64_t seed, uint32_t stream,
   uint32_t w[4];
   orc_philox4x32_10(ctr, key, w);
   double U = (i & 1u) ? orc_u53(w[2], w[3]) : orc_u53(w[0], w[1]);
-  if (U > T[ORC_TABLE_H - 1]) return tail_draw(alpha, seed, stream, rep, i, flags);
+  if (U > T[ORC_TABLE_H - 1]) return orc_tail_draw(alpha, seed, stream, rep, i, flags);
   /* smallest k with T[k] >= U (binary search over the nondecreasing table) */
   int lo = 1, hi = ORC_TABLE_H;
   while (lo < hi) {

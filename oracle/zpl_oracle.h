@@ -55,6 +55,11 @@ void orc_cdf_table(double alpha, double *T, int H);
 int64_t orc_draw(double alpha, const double *T, uint64_t seed, uint32_t stream,
                  uint32_t rep, uint32_t i, uint32_t *flags);
 
+/* The tail sampler alone: the value draw i of replicate `rep` takes when its
+ * uniform exceeds T[H] (rejection on k >= H+1, conditioned on k < 2^63). */
+int64_t orc_tail_draw(double alpha, uint64_t seed, uint32_t stream, uint32_t rep,
+                      uint32_t i, uint32_t *flags);
+
 /* n draws (in draw order) of one replicate. */
 void orc_sample(double alpha, const double *T, int64_t n, uint64_t seed,
                 uint32_t stream, uint32_t rep, int64_t *x, uint32_t *flags);

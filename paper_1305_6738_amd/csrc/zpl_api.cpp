@@ -1,0 +1,692 @@
+// zpl_api.cpp -- host runtime and C ABI of libzpl (see include/zpl.h).
+//
+// The runtime validates calls, plans each cell (execution form, work units),
+// owns the device scratch of a context, enqueues the kernels of
+// zpl_kernels.hip on the caller's stream, and optionally captures the batched
+// launch of a cell list in a hipGraph that later calls replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/zpl.h"
+#include "zpl_kernels.hpp"
+#include "zpl_launch.hpp"
+#include "zpl_math.hpp"
+
+using namespace zpl;
+
+namespace {
+
+thread_local std::string g_err;
+
+zpl_status fail(zpl_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(e_ == hipErrorOutOfMemory ? ZPL_ENOMEM : ZPL_EDEVICE, "%s: %s (%s)", \
+                  #expr, hipGetErrorString(e_), __func__);                            \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Host staging of the ln table for the planner (same values the device uses
+// are not needed here: the planner only estimates tail probabilities).
+struct HostLn {
+  std::vector<double> v;
+  HostLn() : v(kH + 2) {
+    v[0] = 0.0;
+    for (int k = 1; k <= kH + 1; ++k) v[k] = std::log((double)k);
+  }
+};
+const HostLn& host_ln() {
+  static HostLn h;
+  return h;
+}
+
+// Smallest exponent simulated.  Below it the tail law's mass above 2^63 makes
+// the capped rejection sampler take many attempts per draw.  (Fitted
+// exponents are never below about 1.023: mean ln x < ln 2^63.)
+constexpr double kMinAlpha = 1.01;
+
+// P(X > h) under exponent a.
+double tail_prob(double a, int h) {
+  double suf[17];
+  survival_head(a, host_ln().v.data(), suf);
+  const double zt = h >= 16 ? survival_next(a, h, host_ln().v.data()) : suf[h];
+  return zt / suf[0];
+}
+
+}  // namespace
+
+struct zpl_ctx {
+  int device = 0;
+  int n_cu = 256;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  double* ln = nullptr;
+  // scratch, grow-only
+  DevBuf cells, tables, guides, units, hunits, queues, esc, esc_cnt, err, list_v, list_c,
+      heavy, dbuf, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d;
+  // pinned host staging
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  // graph cache (one entry)
+  bool graph_valid = false;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<char> graph_key;
+  uint32_t esc_cap = 0;
+  // optional per-kernel timing of the last non-graph simulation
+  bool timing = false;
+  bool timed = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+zpl_status ensure(zpl_ctx* c, DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return ZPL_OK;
+  if (b.p) {
+    HIP_TRY(hipDeviceSynchronize());  // in-flight work may still use it
+    HIP_TRY(hipFree(b.p));
+    c->used -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  // any cached graph may point at the freed buffer
+  if (c->graph_valid) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_valid = false;
+    c->graph_key.clear();
+  }
+  if (c->used + bytes > c->budget)
+    return fail(ZPL_ENOMEM, "device scratch of %zu bytes exceeds the context budget (%llu of %llu used)",
+                bytes, (unsigned long long)c->used, (unsigned long long)c->budget);
+  HIP_TRY(hipMalloc(&b.p, bytes));
+  b.bytes = bytes;
+  c->used += bytes;
+  return ZPL_OK;
+}
+
+zpl_status ensure_pinned(zpl_ctx* c, size_t bytes) {
+  if (c->pin_bytes >= bytes) return ZPL_OK;
+  HIP_TRY(hipDeviceSynchronize());  // async copies may still read the old area
+  if (c->pin) HIP_TRY(hipHostFree(c->pin));
+  c->pin = nullptr;
+  c->pin_bytes = 0;
+  HIP_TRY(hipHostMalloc(&c->pin, bytes, hipHostMallocDefault));
+  c->pin_bytes = bytes;
+  return ZPL_OK;
+}
+
+#define ZPL_TRY(expr)             \
+  do {                            \
+    zpl_status s_ = (expr);       \
+    if (s_ != ZPL_OK) return s_;  \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Planner: execution form per cell and the unit list.
+// ---------------------------------------------------------------------------
+struct Plan {
+  std::vector<DevCell> cells;
+  std::vector<Unit> units;    // lane and wave units (LPT order)
+  std::vector<Unit> hunits;   // heavy units
+  std::vector<int> cell_unit_begin, cell_unit_end;  // per cell range in `units`
+  int64_t total_R = 0;
+  int64_t max_n = 0;
+};
+
+uint32_t choose_form(double alpha, int64_t n) {
+  if (n <= 65535 && (double)n * tail_prob(alpha, kHLB) <= 2.0) return kModeLane;
+  const double mu = (double)n * tail_prob(alpha, kHW);
+  if (mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)kCW) return kModeWave;
+  return kModeHeavy;
+}
+
+zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P) {
+  P = Plan();
+  P.cells.resize(n_cells);
+  P.cell_unit_begin.assign(n_cells, 0);
+  P.cell_unit_end.assign(n_cells, 0);
+  for (int i = 0; i < n_cells; ++i) {
+    const zpl_cell& z = cells[i];
+    if (!(z.alpha >= kMinAlpha) || !(z.alpha <= 64.0))
+      return fail(ZPL_EINVAL, "cell %d: alpha must be in [1.01, 64], got %g", i, z.alpha);
+    if (z.n < 1 || z.n > ((int64_t)1 << 31))
+      return fail(ZPL_EINVAL, "cell %d: n must be in [1, 2^31], got %lld", i, (long long)z.n);
+    if (z.replicates < 1 || z.replicates > ((int64_t)1 << 32))
+      return fail(ZPL_EINVAL, "cell %d: replicates must be in [1, 2^32], got %lld", i,
+                  (long long)z.replicates);
+    if (z.reserved != 0) return fail(ZPL_EINVAL, "cell %d: reserved field must be 0", i);
+    DevCell& d = P.cells[i];
+    std::memset(&d, 0, sizeof d);
+    d.alpha = z.alpha;
+    d.n = z.n;
+    d.R = z.replicates;
+    d.out_off = P.total_R;
+    d.k0 = (uint32_t)z.seed;
+    d.k1 = (uint32_t)(z.seed >> 32);
+    d.stream = z.stream;
+    uint32_t m;
+    switch (form) {
+      case ZPL_FORM_LANE:
+        m = kModeLane;
+        if (z.n > 65535) return fail(ZPL_EINVAL, "cell %d: lane form needs n <= 65535", i);
+        break;
+      case ZPL_FORM_WAVE: m = kModeWave; break;
+      case ZPL_FORM_HEAVY: m = kModeHeavy; break;
+      default: m = choose_form(z.alpha, z.n);
+    }
+    d.mode = m;
+    P.total_R += z.replicates;
+    P.max_n = std::max(P.max_n, z.n);
+  }
+  // units: 256 replicates (one per lane, or 64 per wave) for lane/wave cells,
+  // 8 replicates for heavy cells
+  std::vector<std::pair<double, Unit>> tmp;
+  for (int i = 0; i < n_cells; ++i) {
+    const DevCell& d = P.cells[i];
+    const int per = d.mode == kModeHeavy ? 8 : kBlock;
+    for (int64_t r = 0; r < d.R; r += per) {
+      Unit u;
+      u.cell = i;
+      u.r0 = r;
+      u.count = (int32_t)std::min<int64_t>(per, d.R - r);
+      if (d.mode == kModeHeavy)
+        P.hunits.push_back(u);
+      else
+        tmp.push_back({(double)d.n * u.count, u});
+    }
+  }
+  // longest units first; ties by cell so a workgroup tends to keep its table
+  std::stable_sort(tmp.begin(), tmp.end(), [](const auto& a, const auto& b) {
+    if (a.first != b.first) return a.first > b.first;
+    return a.second.cell < b.second.cell;
+  });
+  P.units.reserve(tmp.size());
+  for (auto& t : tmp) P.units.push_back(t.second);
+  return ZPL_OK;
+}
+
+// Units of one cell, for plain launches: contiguous by construction below.
+void plain_unit_order(Plan& P) {
+  std::stable_sort(P.units.begin(), P.units.end(),
+                   [](const Unit& a, const Unit& b) { return a.cell < b.cell; });
+  for (size_t k = 0; k < P.units.size(); ++k) {
+    const int c = P.units[k].cell;
+    if (k == 0 || P.units[k - 1].cell != c) P.cell_unit_begin[c] = (int)k;
+    P.cell_unit_end[c] = (int)k + 1;
+  }
+}
+
+int64_t heavy_stride(int64_t max_n) {
+  int64_t p2 = 1;
+  while (p2 < max_n) p2 <<= 1;
+  int64_t half = std::max<int64_t>(p2, 2 * ((int64_t)kHeavyHist + max_n));
+  half = (half + 1) & ~(int64_t)1;
+  return 2 * half;
+}
+
+struct Launch {
+  int sim_grid = 0;
+  int heavy_grid = 0;
+  int64_t hstride = 0;
+};
+
+// Grows every scratch buffer the plan needs.
+zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L) {
+  const int nc = (int)P.cells.size();
+  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell) * nc));
+  ZPL_TRY(ensure(c, c->tables, sizeof(double) * (size_t)kH * nc));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (size_t)kG * nc));
+  ZPL_TRY(ensure(c, c->units, sizeof(Unit) * std::max<size_t>(1, P.units.size())));
+  ZPL_TRY(ensure(c, c->hunits, sizeof(Unit) * std::max<size_t>(1, P.hunits.size())));
+  ZPL_TRY(ensure(c, c->queues, sizeof(uint32_t) * (size_t)(nc + 8)));
+  ZPL_TRY(ensure(c, c->esc_cnt, sizeof(uint32_t) * 4));
+  ZPL_TRY(ensure(c, c->err, sizeof(uint32_t) * 4));
+  // escalation list: generous, escalations are rare by construction
+  const uint32_t esc_cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(P.total_R / 4, 4096),
+                                                       (int64_t)1 << 24);
+  ZPL_TRY(ensure(c, c->esc, sizeof(uint64_t) * esc_cap));
+  c->esc_cap = esc_cap;
+  const int sim_grid =
+      (int)std::min<int64_t>((int64_t)P.units.size(), (int64_t)c->n_cu * 2);
+  L.sim_grid = sim_grid;
+  const size_t nwaves = (size_t)std::max(sim_grid, 1) * kWaves;
+  ZPL_TRY(ensure(c, c->list_v, sizeof(int64_t) * nwaves * kListCap));
+  ZPL_TRY(ensure(c, c->list_c, sizeof(uint32_t) * nwaves * kListCap));
+  L.hstride = heavy_stride(P.max_n);
+  int hg = (int)std::min<int64_t>((int64_t)P.hunits.size() + 64, (int64_t)c->n_cu * 2);
+  // keep the heavy scratch within a quarter of the budget
+  while (hg > 1 && (uint64_t)hg * L.hstride * 8 > c->budget / 4) hg /= 2;
+  L.heavy_grid = hg;
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)hg * L.hstride));
+  if (need_dbuf) ZPL_TRY(ensure(c, c->dbuf, sizeof(double) * (size_t)P.total_R));
+  ZPL_TRY(ensure(c, c->qnum, sizeof(uint32_t) * std::max(n_q, 1)));
+  ZPL_TRY(ensure(c, c->qden, sizeof(uint32_t) * std::max(n_q, 1)));
+  ZPL_TRY(ensure(c, c->qout, sizeof(double) * std::max(nc * n_q, 1)));
+  return ZPL_OK;
+}
+
+// Enqueue everything after the plan upload: counters, tables, simulation,
+// heavy pass, selection.  Kernel launches only (graph-capturable).
+zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, Outputs out,
+                       const double* Dsel, int n_q, hipStream_t s, bool timed) {
+  const int nc = (int)P.cells.size();
+  auto mark = [&](int k) -> hipError_t {
+    return timed ? hipEventRecord(c->ev[k], s) : hipSuccess;
+  };
+  DevCell* dcells = (DevCell*)c->cells.p;
+  uint32_t* queues = (uint32_t*)c->queues.p;
+  HIP_TRY(launch_fill_u32(queues, nc + 8, 0u, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)c->esc_cnt.p, 4, 0u, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)c->err.p, 4, 0u, s));
+  HIP_TRY(mark(0));
+  HIP_TRY(launch_tables(dcells, nc, (double*)c->tables.p, (uint16_t*)c->guides.p, c->ln, s));
+  HIP_TRY(mark(1));
+  const Unit* units = (const Unit*)c->units.p;
+  uint32_t* escc = (uint32_t*)c->esc_cnt.p;
+  if (launch == ZPL_LAUNCH_PLAIN) {
+    for (int i = 0; i < nc; ++i) {
+      const int b = P.cell_unit_begin[i], e = P.cell_unit_end[i];
+      if (e <= b) continue;
+      const int grid = std::min(e - b, c->n_cu * 2);
+      HIP_TRY(launch_simulate(grid, dcells, (const double*)c->tables.p,
+                              (const uint16_t*)c->guides.p, c->ln, units + b, e - b,
+                              queues + 8 + i, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
+                              (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p,
+                              (uint32_t*)c->err.p, s));
+    }
+  } else {
+    HIP_TRY(launch_simulate(L.sim_grid, dcells, (const double*)c->tables.p,
+                            (const uint16_t*)c->guides.p, c->ln, units, (int)P.units.size(),
+                            queues + 0, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
+                            (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p,
+                            (uint32_t*)c->err.p, s));
+  }
+  HIP_TRY(mark(2));
+  HIP_TRY(launch_heavy(L.heavy_grid, dcells, (const double*)c->tables.p,
+                       (const uint16_t*)c->guides.p, c->ln, (const Unit*)c->hunits.p,
+                       (int)P.hunits.size(), (const uint64_t*)c->esc.p, escc, c->esc_cap,
+                       queues + 2, out, (int64_t*)c->heavy.p, L.hstride, s));
+  HIP_TRY(mark(3));
+  if (n_q > 0 && Dsel)
+    HIP_TRY(launch_select(Dsel, dcells, nc, n_q, (const uint32_t*)c->qnum.p,
+                          (const uint32_t*)c->qden.p, (double*)c->qout.p, s));
+  HIP_TRY(mark(4));
+  return ZPL_OK;
+}
+
+zpl_status check_err_word(zpl_ctx* c, hipStream_t s) {
+  uint32_t e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, c->err.p, sizeof e, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (e & kErrEscOverflow)
+    return fail(ZPL_ENOMEM, "escalation list overflow (too many replicates exceeded their form's capacity)");
+  return ZPL_OK;
+}
+
+// Simulation of a plan with outputs; shared by zpl_simulate_cells and the
+// bootstrap.  quantiles may be NULL.
+zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint32_t* q_num,
+                     const uint32_t* q_den, int n_q, double* quantiles, Outputs out,
+                     const zpl_sim_opts* opts, hipStream_t s) {
+  zpl_sim_opts o = {ZPL_LAUNCH_BATCHED, ZPL_FORM_AUTO, 0, 0};
+  if (opts) o = *opts;
+  if (o.launch != ZPL_LAUNCH_BATCHED && o.launch != ZPL_LAUNCH_PLAIN)
+    return fail(ZPL_EINVAL, "opts.launch must be ZPL_LAUNCH_BATCHED or ZPL_LAUNCH_PLAIN");
+  if (o.form < ZPL_FORM_AUTO || o.form > ZPL_FORM_HEAVY)
+    return fail(ZPL_EINVAL, "opts.form out of range");
+  if (o.reserved != 0) return fail(ZPL_EINVAL, "opts.reserved must be 0");
+  if (n_q < 0 || (n_q > 0 && (!q_num || !q_den)))
+    return fail(ZPL_EINVAL, "quantile arrays missing");
+  for (int i = 0; i < n_q; ++i)
+    if (q_den[i] == 0 || q_num[i] >= q_den[i])
+      return fail(ZPL_EINVAL, "quantile %d: need num < den (got %u/%u)", i, q_num[i], q_den[i]);
+  Plan P;
+  ZPL_TRY(make_plan(cells, n_cells, o.form, P));
+  if (o.launch == ZPL_LAUNCH_PLAIN) plain_unit_order(P);
+  const bool need_sel = quantiles && n_q > 0;
+  const bool need_dbuf = need_sel && out.D == nullptr;
+  Launch L;
+  ZPL_TRY(prepare(c, P, n_q, need_dbuf, L));
+  if (need_dbuf) out.D = (double*)c->dbuf.p;
+  // graph key: everything the captured launches depend on
+  std::vector<char> key;
+  auto put = [&](const void* p, size_t b) {
+    const char* q = (const char*)p;
+    key.insert(key.end(), q, q + b);
+  };
+  put(&o, sizeof o);
+  put(&n_cells, sizeof n_cells);
+  put(cells, sizeof(zpl_cell) * (size_t)n_cells);
+  put(&n_q, sizeof n_q);
+  if (n_q) {
+    put(q_num, sizeof(uint32_t) * n_q);
+    put(q_den, sizeof(uint32_t) * n_q);
+  }
+  put(&out, sizeof out);
+  put(&s, sizeof s);
+  const bool replay = o.use_graph && o.launch == ZPL_LAUNCH_BATCHED && c->graph_valid &&
+                      c->graph_key == key;
+  if (!replay) {
+    // upload the plan
+    const size_t bc = sizeof(DevCell) * P.cells.size(), bu = sizeof(Unit) * P.units.size(),
+                 bh = sizeof(Unit) * P.hunits.size(), bq = sizeof(uint32_t) * (size_t)n_q;
+    ZPL_TRY(ensure_pinned(c, bc + bu + bh + 2 * bq + 64));
+    HIP_TRY(hipStreamSynchronize(s));  // the staging area may still be in use
+    char* pin = (char*)c->pin;
+    std::memcpy(pin, P.cells.data(), bc);
+    std::memcpy(pin + bc, P.units.data(), bu);
+    std::memcpy(pin + bc + bu, P.hunits.data(), bh);
+    if (n_q) {
+      std::memcpy(pin + bc + bu + bh, q_num, bq);
+      std::memcpy(pin + bc + bu + bh + bq, q_den, bq);
+    }
+    HIP_TRY(hipMemcpyAsync(c->cells.p, pin, bc, hipMemcpyHostToDevice, s));
+    if (bu) HIP_TRY(hipMemcpyAsync(c->units.p, pin + bc, bu, hipMemcpyHostToDevice, s));
+    if (bh) HIP_TRY(hipMemcpyAsync(c->hunits.p, pin + bc + bu, bh, hipMemcpyHostToDevice, s));
+    if (n_q) {
+      HIP_TRY(hipMemcpyAsync(c->qnum.p, pin + bc + bu + bh, bq, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(c->qden.p, pin + bc + bu + bh + bq, bq, hipMemcpyHostToDevice, s));
+    }
+  }
+  const double* Dsel = need_sel ? out.D : nullptr;
+  if (o.use_graph && o.launch == ZPL_LAUNCH_BATCHED) {
+    if (!replay) {
+      if (c->graph_valid) {
+        (void)hipGraphExecDestroy(c->graph_exec);
+        c->graph_valid = false;
+      }
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      zpl_status st = enqueue_run(c, P, o.launch, L, out, Dsel, need_sel ? n_q : 0, s, false);
+      hipError_t ce = hipStreamEndCapture(s, &g);
+      if (st != ZPL_OK) {
+        if (ce == hipSuccess) (void)hipGraphDestroy(g);
+        return st;
+      }
+      HIP_TRY(ce);
+      hipError_t ie = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_TRY(ie);
+      c->graph_valid = true;
+      c->graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, s));
+    c->timed = false;
+  } else {
+    if (c->timing && !c->ev[0])
+      for (hipEvent_t& e : c->ev) HIP_TRY(hipEventCreate(&e));
+    ZPL_TRY(enqueue_run(c, P, o.launch, L, out, Dsel, need_sel ? n_q : 0, s, c->timing));
+    c->timed = c->timing;
+  }
+  if (need_sel) {
+    HIP_TRY(hipMemcpyAsync(quantiles, c->qout.p, sizeof(double) * (size_t)n_cells * n_q,
+                           hipMemcpyDeviceToHost, s));
+    ZPL_TRY(check_err_word(c, s));
+  }
+  return ZPL_OK;
+}
+
+zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, double* ahat,
+                      double* D, uint32_t* flags, uint32_t* status) {
+  const int64_t stride = heavy_stride(n);
+  ZPL_TRY(ensure(c, c->fit_ptrs, sizeof(int64_t*)));
+  ZPL_TRY(ensure(c, c->fit_ns, sizeof(int64_t)));
+  ZPL_TRY(ensure(c, c->fit_out, sizeof(double) * 2 + sizeof(uint32_t) * 2));
+  ZPL_TRY(ensure(c, c->fit_st, sizeof(uint32_t) * 2));
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)stride));
+  ZPL_TRY(ensure_pinned(c, 64));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t* pin = (int64_t*)c->pin;
+  pin[0] = (int64_t)(intptr_t)xd;
+  pin[1] = n;
+  HIP_TRY(hipMemcpyAsync(c->fit_ptrs.p, &pin[0], sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->fit_ns.p, &pin[1], sizeof(int64_t), hipMemcpyHostToDevice, s));
+  double* o = (double*)c->fit_out.p;
+  uint32_t* of = (uint32_t*)(o + 2);
+  HIP_TRY(launch_fit(1, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, 1,
+                     c->ln, (int64_t*)c->heavy.p, stride, o, o + 1, of,
+                     (uint32_t*)c->fit_st.p, s));
+  char* hp = (char*)c->pin + 16;
+  HIP_TRY(hipMemcpyAsync(hp, o, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hp + 16, of, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hp + 20, c->fit_st.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(ahat, hp, sizeof(double));
+  std::memcpy(D, hp + 8, sizeof(double));
+  std::memcpy(flags, hp + 16, sizeof(uint32_t));
+  std::memcpy(status, hp + 20, sizeof(uint32_t));
+  return ZPL_OK;
+}
+
+zpl_status stage_x(zpl_ctx* c, const int64_t* x, int64_t n, int32_t on_dev, hipStream_t s,
+                   const int64_t** xd) {
+  if (on_dev) {
+    *xd = x;
+    return ZPL_OK;
+  }
+  ZPL_TRY(ensure(c, c->fit_x, sizeof(int64_t) * (size_t)n));
+  HIP_TRY(hipMemcpyAsync(c->fit_x.p, x, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  *xd = (const int64_t*)c->fit_x.p;
+  return ZPL_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* zpl_last_error(void) { return g_err.c_str(); }
+
+zpl_status zpl_create(zpl_ctx** out, int32_t device, uint64_t mem_budget_bytes) {
+  g_err.clear();
+  if (!out) return fail(ZPL_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev)
+    return fail(ZPL_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  zpl_ctx* c = new zpl_ctx();
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->budget = mem_budget_bytes ? mem_budget_bytes : (64ull << 30);
+  hipError_t e = hipMalloc(&c->ln, sizeof(double) * (kH + 2));
+  if (e != hipSuccess) {
+    delete c;
+    return fail(ZPL_ENOMEM, "hipMalloc(ln): %s", hipGetErrorString(e));
+  }
+  e = launch_ln_table(c->ln, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(c->ln);
+    delete c;
+    return fail(ZPL_EDEVICE, "ln table: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return ZPL_OK;
+}
+
+void zpl_destroy(zpl_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->graph_valid) (void)hipGraphExecDestroy(c->graph_exec);
+  DevBuf* bufs[] = {&c->cells, &c->tables, &c->guides, &c->units, &c->hunits, &c->queues,
+                    &c->esc, &c->esc_cnt, &c->err, &c->list_v, &c->list_c, &c->heavy,
+                    &c->dbuf, &c->qnum, &c->qden, &c->qout, &c->fit_x, &c->fit_ptrs,
+                    &c->fit_ns, &c->fit_out, &c->fit_st, &c->count, &c->boot_d};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->ln) (void)hipFree(c->ln);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->pin) (void)hipHostFree(c->pin);
+  delete c;
+}
+
+zpl_status zpl_simulate_cells(zpl_ctx* c, const zpl_cell* cells, int32_t n_cells,
+                              const uint32_t* q_num, const uint32_t* q_den, int32_t n_q,
+                              double* quantiles, double* d_out, double* alpha_hat_out,
+                              uint32_t* flags_out, uint64_t* fingerprint_out,
+                              const zpl_sim_opts* opts, void* stream) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  if (n_cells < 1 || !cells) return fail(ZPL_EINVAL, "need at least one cell");
+  HIP_TRY(hipSetDevice(c->device));
+  Outputs out{d_out, alpha_hat_out, flags_out, fingerprint_out, nullptr};
+  return run_cells(c, cells, n_cells, q_num, q_den, quantiles ? n_q : 0, quantiles, out, opts,
+                   (hipStream_t)stream);
+}
+
+zpl_status zpl_set_timing(zpl_ctx* c, int32_t enable) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  c->timing = enable != 0;
+  return ZPL_OK;
+}
+
+zpl_status zpl_get_timing(zpl_ctx* c, double* ms4) {
+  g_err.clear();
+  if (!c || !ms4) return fail(ZPL_EINVAL, "NULL argument");
+  if (!c->timed) return fail(ZPL_EINVAL, "no timed simulation since timing was enabled");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipEventSynchronize(c->ev[4]));
+  for (int k = 0; k < 4; ++k) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+    ms4[k] = (double)ms;
+  }
+  return ZPL_OK;
+}
+
+zpl_status zpl_fit(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                   double* alpha_hat, double* D, uint32_t* flags, void* stream) {
+  g_err.clear();
+  if (!c || !x || !alpha_hat || !D || !flags) return fail(ZPL_EINVAL, "NULL argument");
+  if (n < 1 || n > ((int64_t)1 << 31)) return fail(ZPL_EINVAL, "n must be in [1, 2^31]");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t* xd;
+  ZPL_TRY(stage_x(c, x, n, x_on_device, s, &xd));
+  uint32_t st = 0;
+  ZPL_TRY(fit_device(c, xd, n, s, alpha_hat, D, flags, &st));
+  if (st & kErrBadValue) return fail(ZPL_EINVAL, "every x must be >= 1");
+  if (*flags & ZPL_FLAG_NOCONV) return fail(ZPL_ENOCONV, "MLE iteration cap reached");
+  return ZPL_OK;
+}
+
+zpl_status zpl_bootstrap_pvalue(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                                int64_t B, uint64_t seed, uint32_t stream_id,
+                                double* alpha_hat, double* D, double* p_value,
+                                uint32_t* flags, void* stream) {
+  g_err.clear();
+  if (!c || !x || !alpha_hat || !D || !p_value || !flags)
+    return fail(ZPL_EINVAL, "NULL argument");
+  if (B < 1 || B > ((int64_t)1 << 32)) return fail(ZPL_EINVAL, "B must be in [1, 2^32]");
+  zpl_status st = zpl_fit(c, x, n, x_on_device, alpha_hat, D, flags, stream);
+  if (st != ZPL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  zpl_cell cell = {*alpha_hat, n, B, seed, stream_id, 0};
+  ZPL_TRY(ensure(c, c->boot_d, sizeof(double) * (size_t)B + 64));
+  ZPL_TRY(ensure(c, c->count, sizeof(unsigned long long) + sizeof(double)));
+  Outputs out{(double*)c->boot_d.p, nullptr, nullptr, nullptr, nullptr};
+  ZPL_TRY(run_cells(c, &cell, 1, nullptr, nullptr, 0, nullptr, out, nullptr, s));
+  // D_obs to the device, count D_b >= D_obs
+  ZPL_TRY(ensure_pinned(c, 64));
+  HIP_TRY(hipStreamSynchronize(s));
+  double* pd = (double*)c->pin;
+  pd[0] = *D;
+  unsigned long long* cnt = (unsigned long long*)c->count.p;
+  double* dobs = (double*)(cnt + 1);
+  HIP_TRY(hipMemcpyAsync(dobs, pd, sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)cnt, 2, 0u, s));
+  HIP_TRY(launch_count_ge((const double*)c->boot_d.p, B, dobs, cnt, s));
+  unsigned long long* hc = (unsigned long long*)((char*)c->pin + 8);
+  HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof *hc, hipMemcpyDeviceToHost, s));
+  ZPL_TRY(check_err_word(c, s));
+  *p_value = (double)*hc / (double)B;
+  return ZPL_OK;
+}
+
+zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
+                            uint32_t stream_id, int64_t rep_lo, int64_t count,
+                            int64_t* x_out, uint32_t* flags_out, void* stream) {
+  g_err.clear();
+  if (!c || !x_out || !flags_out) return fail(ZPL_EINVAL, "NULL argument");
+  if (!(alpha >= kMinAlpha) || !(alpha <= 64.0))
+    return fail(ZPL_EINVAL, "alpha must be in [1.01, 64]");
+  if (n < 1 || count < 1 || rep_lo < 0 || rep_lo + count > ((int64_t)1 << 32) ||
+      n > ((int64_t)1 << 31))
+    return fail(ZPL_EINVAL, "bad n / replicate range");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  zpl_cell z = {alpha, n, count, seed, stream_id, 0};
+  Plan P;
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
+  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
+  ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * kG));
+  ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
+  HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
+                        c->ln, s));
+  HIP_TRY(launch_fill_u32(flags_out, (int)count, 0u, s));
+  HIP_TRY(launch_draws((const DevCell*)c->cells.p, (const double*)c->tables.p,
+                       (const uint16_t*)c->guides.p, rep_lo, count, x_out, flags_out,
+                       count * n, s));
+  return ZPL_OK;
+}
+
+zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, double* T_out, void* stream) {
+  g_err.clear();
+  if (!c || !T_out) return fail(ZPL_EINVAL, "NULL argument");
+  if (!(alpha >= kMinAlpha) || !(alpha <= 64.0))
+    return fail(ZPL_EINVAL, "alpha must be in [1.01, 64]");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  zpl_cell z = {alpha, 1, 1, 0, 0, 0};
+  Plan P;
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
+  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
+  ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * kG));
+  ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
+  HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
+                        c->ln, s));
+  HIP_TRY(hipMemcpyAsync(T_out, c->tables.p, sizeof(double) * kH, hipMemcpyDeviceToDevice, s));
+  return ZPL_OK;
+}
+
+}  // extern "C"

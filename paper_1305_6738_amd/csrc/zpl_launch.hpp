@@ -1,0 +1,36 @@
+// zpl_launch.hpp -- host launchers of the kernels in zpl_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "zpl_kernels.hpp"
+
+namespace zpl {
+
+hipError_t launch_ln_table(double* ln, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t s);
+hipError_t launch_tables(DevCell* cells, int n_cells, double* tables, uint16_t* guides,
+                         const double* ln, hipStream_t s);
+hipError_t launch_simulate(int grid, const DevCell* cells, const double* tables,
+                           const uint16_t* guides, const double* ln, const Unit* units,
+                           int n_units, uint32_t* queue, Outputs out, uint64_t* esc_list,
+                           uint32_t* esc_count, uint32_t esc_cap, int64_t* list_v,
+                           uint32_t* list_c, uint32_t* err, hipStream_t s);
+hipError_t launch_heavy(int grid, const DevCell* cells, const double* tables,
+                        const uint16_t* guides, const double* ln, const Unit* units,
+                        int n_units, const uint64_t* esc_list, const uint32_t* esc_count,
+                        uint32_t esc_cap, uint32_t* queues, Outputs out, int64_t* scratch,
+                        int64_t stride, hipStream_t s);
+hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int n_sets,
+                      const double* ln, int64_t* scratch, int64_t stride, double* ahat,
+                      double* D, uint32_t* flags, uint32_t* status, hipStream_t s);
+hipError_t launch_select(const double* D, const DevCell* cells, int n_cells, int n_q,
+                         const uint32_t* qnum, const uint32_t* qden, double* qout,
+                         hipStream_t s);
+hipError_t launch_count_ge(const double* Db, int64_t B, const double* Dobs,
+                           unsigned long long* count, hipStream_t s);
+hipError_t launch_draws(const DevCell* cell, const double* table, const uint16_t* guide,
+                        int64_t rep_lo, int64_t count, int64_t* x, uint32_t* flags,
+                        int64_t total, hipStream_t s);
+
+}  // namespace zpl

@@ -1,0 +1,421 @@
+// zpl_math.hpp -- scalar arithmetic of the Zipf/KS Monte Carlo path.
+//
+// Everything here is plain scalar FP64/integer code marked __host__ __device__
+// so that one definition serves every GPU kernel (lane, wave and heavy paths
+// and the dataset fit), and can also be compiled for the host to test its
+// logic on a CPU.  The library is built with -ffp-contract=off: every fused
+// multiply-add is an explicit fma(), so a given input produces the same bits
+// in whichever kernel the function is inlined.  That is what makes a replicate
+// give bit-identical (alpha_hat, D) in every execution mode, and makes ties
+// between a bootstrap replicate and the observed statistic exact.
+//
+// Reference: E. Rappos and S. Robert, "Using GPU Simulation to Accurately Fit
+// to the Power-Law Distribution" (2013).  Eq. (1): p(k) = k^-a / zeta(a);
+// eq. (2): zeta'(a)/zeta(a) = -(1/N) sum ln x_i; eq. (3): K = sup|F* - S|.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ZPL_HD __host__ __device__ __forceinline__
+
+namespace zpl {
+
+// CDF table length: values 1..kH are drawn by table search, larger ones by
+// the rejection tail.  Part of the sampling contract (samples depend on it).
+constexpr int kH = 4096;
+// First value of the tail.
+constexpr double kTailM = 4097.0;
+// Philox counter word 3 for tail proposals: kTailDomain | attempt.
+constexpr uint32_t kTailDomain = 0x80000000u;
+
+constexpr uint32_t kFlagAllOnes = 1u;
+constexpr uint32_t kFlagTailCapped = 2u;
+constexpr uint32_t kFlagBisect = 4u;
+constexpr uint32_t kFlagNoConv = 8u;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each round
+// multiplies counter words 0 and 2 by the two round constants (32x32->64),
+// mixes the high halves with words 1, 3 and the key, and the key is bumped by
+// the two Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+ZPL_HD Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                            uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// Odd multiple of 2^-53 in (0,1) from the 64-bit word hi:lo.
+ZPL_HD double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t m = ((((uint64_t)hi) << 32 | (uint64_t)lo) >> 11) | 1ull;
+  return (double)m * 0x1p-53;
+}
+
+// splitmix64's output finaliser; summed over draws it is a fingerprint of the
+// multiset of drawn values (used only to check histograms bit for bit).
+ZPL_HD uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Hurwitz zeta by Euler-Maclaurin with no direct terms, valid for q >= 17:
+//   zeta(s,q) = q^-s [ q/(s-1) + 1/2 + sum_{i=1..8} c_i (s)_{2i-1} q^-(2i-1) ]
+// with c_i = B_2i/(2i)! and (s)_m the rising factorial.  The Bernoulli series
+// is evaluated innermost-first (smallest terms first).
+// ---------------------------------------------------------------------------
+ZPL_HD double em_series(double s, double inv_q) {
+  const double c1 = 1.0 / 12.0, c2 = -1.0 / 720.0, c3 = 1.0 / 30240.0,
+               c4 = -1.0 / 1209600.0, c5 = 1.0 / 47900160.0,
+               c6 = -691.0 / 1307674368000.0, c7 = 1.0 / 74724249600.0,
+               c8 = -3617.0 / 10670622842880000.0;
+  const double iq2 = inv_q * inv_q;
+  double acc = c8;
+  acc = fma(acc * ((s + 13.0) * (s + 14.0)), iq2, c7);
+  acc = fma(acc * ((s + 11.0) * (s + 12.0)), iq2, c6);
+  acc = fma(acc * ((s + 9.0) * (s + 10.0)), iq2, c5);
+  acc = fma(acc * ((s + 7.0) * (s + 8.0)), iq2, c4);
+  acc = fma(acc * ((s + 5.0) * (s + 6.0)), iq2, c3);
+  acc = fma(acc * ((s + 3.0) * (s + 4.0)), iq2, c2);
+  acc = fma(acc * ((s + 1.0) * (s + 2.0)), iq2, c1);
+  return acc * (s * inv_q);
+}
+
+// q^-s = exp(-s ln q) with the product s ln q kept exact (p + e), so the
+// product's rounding (up to s ln q ulps of relative error) is not amplified.
+ZPL_HD double pow_neg(double s, double lnq) {
+  const double p = s * lnq;
+  const double e = fma(s, lnq, -p);
+  const double r = exp(-p);
+  return fma(-e, r, r);
+}
+
+// zeta(s, q) for q >= 17; lnq = ln q.
+ZPL_HD double hurwitz_tail(double s, double q, double lnq) {
+  const double qs = pow_neg(s, lnq);
+  return qs * (q / (s - 1.0) + 0.5 + em_series(s, 1.0 / q));
+}
+
+// zeta(s), zeta'(s), zeta''(s): direct terms k = 1..16 (ln k from `ln`, the
+// library's table of natural logs) plus the Euler-Maclaurin tail at 17 and
+// its first two s-derivatives.  Summed smallest-first in a fixed order.
+struct Z3 {
+  double z0, z1, z2;
+};
+
+ZPL_HD Z3 zeta3(double s, const double* __restrict__ ln) {
+  const double q = 17.0;
+  const double L = ln[17];
+  const double iq = 1.0 / q, iq2 = iq * iq;
+  // Q(s) = q/(s-1) + 1/2 + sum_i c_i P_i(s) q^-(2i-1), P_i = (s)_{2i-1}
+  const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
+                       1.0 / 30240.0,      -1.0 / 1209600.0,
+                       1.0 / 47900160.0,   -691.0 / 1307674368000.0,
+                       1.0 / 74724249600.0, -3617.0 / 10670622842880000.0};
+  double t0[8], t1[8], t2[8];
+  double P = s, sg1 = 1.0 / s, sg2 = 1.0 / (s * s), E = iq;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double ce = c[i] * E;
+    t0[i] = ce * P;
+    t1[i] = ce * (P * sg1);
+    t2[i] = ce * (P * fma(sg1, sg1, -sg2));
+    const double u = s + (double)(2 * i + 1), v = s + (double)(2 * i + 2);
+    P *= u * v;
+    sg1 += 1.0 / u + 1.0 / v;
+    sg2 += 1.0 / (u * u) + 1.0 / (v * v);
+    E *= iq2;
+  }
+  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0;
+#pragma unroll
+  for (int i = 7; i >= 0; --i) {
+    Q0 += t0[i];
+    Q1 += t1[i];
+    Q2 += t2[i];
+  }
+  const double sm1 = s - 1.0, ism1 = 1.0 / sm1;
+  Q0 += 0.5;
+  Q0 += q * ism1;
+  Q1 += -q * ism1 * ism1;
+  Q2 += 2.0 * q * ism1 * ism1 * ism1;
+  const double qs = pow_neg(s, L);
+  // d/ds [q^-s Q] = q^-s (Q' - L Q); d2/ds2 = q^-s (Q'' - 2 L Q' + L^2 Q)
+  double z0 = qs * Q0;
+  double z1 = qs * fma(-L, Q0, Q1);
+  double z2 = qs * fma(L * L, Q0, fma(-2.0 * L, Q1, Q2));
+#pragma unroll
+  for (int k = 16; k >= 2; --k) {
+    const double lk = ln[k];
+    const double t = pow_neg(s, lk);
+    z0 += t;
+    z1 = fma(-lk, t, z1);
+    z2 = fma(lk * lk, t, z2);
+  }
+  z0 += 1.0;
+  return Z3{z0, z1, z2};
+}
+
+// ---------------------------------------------------------------------------
+// MLE, eq. (2): solve mu(a) := -zeta'(a)/zeta(a) = m, m = S/n.  mu decreases
+// strictly (mu' = -Var[ln X]), so the root is unique.  Newton-Raphson is run
+// on ln mu(a) - ln m (nearly linear in a for large a), inside a bracket
+// [1 + 2^-20, 64] that shrinks with the sign of mu - m; a step leaving the
+// bracket becomes a bisection.  Stops when |step| <= 2^-50 a.
+// ---------------------------------------------------------------------------
+ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags) {
+  double lo = 1.0 + 0x1p-20, hi = 64.0;
+  // initial guess: mu ~ 1/(a-1) - gamma near a = 1; mu ~ ln2 2^-a for large a
+  double a1 = 1.0 + 1.0 / (m + 0.5772156649015329);
+  double a2 = log2(ln[2] / m);
+  double a = a1 > a2 ? a1 : a2;
+  if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+  const double lm = log(m);
+  for (int it = 0; it < 100; ++it) {
+    const Z3 z = zeta3(a, ln);
+    const double mu = -z.z1 / z.z0;
+    if (mu == m) return a;
+    if (mu > m)
+      lo = a;
+    else
+      hi = a;
+    const double var = fma(-mu, mu, z.z2 / z.z0);
+    double an = a + (log(mu) - lm) * (mu / var);
+    if (!(an > lo && an < hi)) {
+      an = 0.5 * (lo + hi);
+      *flags |= kFlagBisect;
+    }
+    if (fabs(an - a) <= 0x1p-50 * a) return an;
+    a = an;
+  }
+  *flags |= kFlagNoConv;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Unnormalised survival zeta(a, t+1) = sum_{k > t} k^-a, so that
+// F(t; a) = 1 - zeta(a,t+1)/zeta(a) (eq. 1 summed).  suf[t], t = 0..16, holds
+// it for small t (suf[0] = zeta(a)); larger t use hurwitz_tail.
+// ---------------------------------------------------------------------------
+ZPL_HD void survival_head(double a, const double* __restrict__ ln, double suf[17]) {
+  suf[16] = hurwitz_tail(a, 17.0, ln[17]);
+#pragma unroll
+  for (int t = 15; t >= 1; --t) suf[t] = suf[t + 1] + pow_neg(a, ln[t + 1]);
+  suf[0] = suf[1] + 1.0;
+}
+
+// ln of an integer value: from the table for v <= kH + 1, else computed.
+ZPL_HD double ln_value(int64_t v, const double* __restrict__ ln) {
+  return v <= (int64_t)(kH + 1) ? ln[v] : log((double)v);
+}
+
+// zeta(a, v) for an integer v >= 17, i.e. the unnormalised survival at v-1.
+ZPL_HD double survival_at(double a, int64_t v, const double* __restrict__ ln) {
+  return hurwitz_tail(a, (double)v, ln_value(v, ln));
+}
+
+// zeta(a, v+1) for an integer 16 <= v < 2^63 (v + 1 may not fit in int64).
+ZPL_HD double survival_next(double a, int64_t v, const double* __restrict__ ln) {
+  if (v < (int64_t)kH + 1) return hurwitz_tail(a, (double)(v + 1), ln[v + 1]);
+  const double q = (double)v + 1.0;
+  return hurwitz_tail(a, q, log(q));
+}
+
+// ---------------------------------------------------------------------------
+// Exact accumulation of S = sum ln x.  ln x >= ln 2 > 1/2 for x >= 2, so every
+// FP64 ln x is an integer multiple of 2^-53 and ln x * 2^53 is an exact
+// integer below 2^59.  Summing those integers in 128 bits is exact in any
+// order, which makes S independent of how draws are split across lanes.
+// ---------------------------------------------------------------------------
+struct U128 {
+  uint64_t lo, hi;
+};
+
+ZPL_HD void u128_add(U128& a, uint64_t lo, uint64_t hi) {
+  const uint64_t s = a.lo + lo;
+  a.hi += hi + (s < lo ? 1u : 0u);
+  a.lo = s;
+}
+
+// c * L (c < 2^32, L < 2^60) added exactly.
+ZPL_HD void u128_add_mul(U128& a, uint64_t c, uint64_t L) {
+  const uint64_t ll = (L & 0xffffffffull) * c;
+  const uint64_t lh = (L >> 32) * c;  // < 2^60
+  // c*L = lh * 2^32 + ll
+  u128_add(a, ll, 0);
+  u128_add(a, lh << 32, lh >> 32);
+}
+
+ZPL_HD uint64_t ln_fixed(int64_t v, const double* __restrict__ ln) {
+  return v <= 1 ? 0ull : (uint64_t)(ln_value(v, ln) * 0x1p53);
+}
+
+// Deterministic FP64 value of a 128-bit fixed-point sum (unit 2^-53).
+ZPL_HD double u128_to_S(const U128& a) {
+  double v = (a.hi == 0) ? (double)a.lo : fma((double)a.hi, 0x1p64, (double)a.lo);
+  return v * 0x1p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic (Dekker; Bailey's QD formulation) for the exact
+// integer floor in the tail sampler.
+// ---------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+
+ZPL_HD DD two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  const double e = (a - (s - bb)) + (b - bb);
+  return DD{s, e};
+}
+ZPL_HD DD quick_two_sum(double a, double b) {
+  const double s = a + b;
+  return DD{s, b - (s - a)};
+}
+ZPL_HD DD two_prod(double a, double b) {
+  const double p = a * b;
+  return DD{p, fma(a, b, -p)};
+}
+ZPL_HD DD dd_add(DD a, DD b) {
+  DD s = two_sum(a.hi, b.hi);
+  DD t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = quick_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
+ZPL_HD DD dd_mul(DD a, DD b) {
+  DD p = two_prod(a.hi, b.hi);
+  p.lo = fma(a.hi, b.lo, p.lo);
+  p.lo = fma(a.lo, b.hi, p.lo);
+  return quick_two_sum(p.hi, p.lo);
+}
+ZPL_HD DD dd_mul_d(DD a, double b) {
+  DD p = two_prod(a.hi, b);
+  p.lo = fma(a.lo, b, p.lo);
+  return quick_two_sum(p.hi, p.lo);
+}
+ZPL_HD DD dd_div_d(DD a, double b) {
+  const double q1 = a.hi / b;
+  DD r = dd_add(a, dd_mul_d(DD{q1, 0.0}, -b));
+  const double q2 = r.hi / b;
+  r = dd_add(r, dd_mul_d(DD{q2, 0.0}, -b));
+  const double q3 = r.hi / b;
+  DD q = quick_two_sum(q1, q2);
+  return dd_add(q, DD{q3, 0.0});
+}
+
+// exp of a double-double: a = k ln2 + r, r scaled by 2^-10, Taylor series to
+// the 11th power, then ten squarings of (1 + x) kept as x -> 2x + x^2.
+ZPL_HD DD dd_exp(DD a) {
+  const DD ln2 = {0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56};
+  const double k = rint(a.hi / ln2.hi);
+  DD r = dd_add(a, dd_mul_d(ln2, -k));
+  r.hi *= 0x1p-10;
+  r.lo *= 0x1p-10;
+  // x = r + r^2/2! + ... + r^11/11!  (|r| < 3.4e-4)
+  DD term = r, x = r;
+  for (int j = 2; j <= 11; ++j) {
+    term = dd_div_d(dd_mul(term, r), (double)j);
+    x = dd_add(x, term);
+  }
+  for (int j = 0; j < 10; ++j) x = dd_add(dd_mul_d(x, 2.0), dd_mul(x, x));
+  DD e = dd_add(DD{1.0, 0.0}, x);
+  return DD{ldexp(e.hi, (int)k), ldexp(e.lo, (int)k)};
+}
+
+// ln of a positive double as a double-double: one Newton step on exp.
+ZPL_HD DD dd_log(double v) {
+  const double y = log(v);
+  // y1 = y + v exp(-y) - 1
+  const DD e = dd_exp(DD{-y, 0.0});
+  const DD t = dd_add(dd_mul_d(e, v), DD{-1.0, 0.0});
+  return dd_add(DD{y, 0.0}, t);
+}
+
+// ---------------------------------------------------------------------------
+// Tail sampler for U > T[kH].  Target on k >= m = kH + 1: p(k) ~ k^-a.
+// Proposal X = floor(Y), Y = m V^(-1/beta) (Pareto, beta = a - 1), so
+// P(X = k) ~ k^-beta - (k+1)^-beta; the ratio target/proposal is proportional
+// to g(k) = 1 / (k (1 - (1+1/k)^-beta)), decreasing in k, so X is accepted
+// when W g(m) <= g(X).  Y >= 2^63 is redrawn (law conditioned on x < 2^63).
+// X is the exact floor of the real-number Y: FP64 decides it unless Y is
+// within a relative 2^-44 of an integer (or of 2^63) or above 2^52, where
+// the floor is taken from a double-double evaluation of Y.
+// ---------------------------------------------------------------------------
+ZPL_HD double tail_g(double beta, double k) {
+  return 1.0 / (-k * expm1(-beta * log1p(1.0 / k)));
+}
+
+ZPL_HD int64_t dd_floor(DD y) {
+  const double f = floor(y.hi);
+  // callers guarantee y < 2^63; y.hi may still round up to 2^63
+  if (f >= 0x1p63) return (int64_t)0x7fffffffffffffffll;
+  if (f == y.hi) {
+    // y.hi is an integer (always so above 2^52): floor(y) = y.hi + floor(y.lo),
+    // |y.lo| <= ulp(y.hi)/2 <= 2^9
+    return (int64_t)f + (int64_t)floor(y.lo);
+  }
+  // y.hi < 2^52 is not an integer and |y.lo| < 1/2
+  int64_t X = (int64_t)f;
+  const double frac = (y.hi - f) + y.lo;
+  if (frac < 0.0) X -= 1;
+  if (frac >= 1.0) X += 1;
+  return X;
+}
+
+// Returns the accepted draw; ORs kFlagTailCapped into *flags if a proposal at
+// or above 2^63 was rejected.
+ZPL_HD int64_t tail_draw(double beta, double gm, uint32_t k0, uint32_t k1,
+                         uint32_t i, uint32_t rep, uint32_t stream, uint32_t* flags) {
+  const double two63 = 0x1p63;
+  for (uint32_t attempt = 0; attempt < 0x7fffffffu; ++attempt) {
+    const Words4 w = philox4x32_10(i, rep, stream, kTailDomain | attempt, k0, k1);
+    const double V = u53(w.w0, w.w1);
+    const double W = u53(w.w2, w.w3);
+    const double z = -log(V) / beta;
+    const double y = kTailM * exp(z);
+    int64_t X;
+    if (y >= two63 * (1.0 + 0x1p-40)) {
+      *flags |= kFlagTailCapped;
+      continue;
+    }
+    const double fy = floor(y);
+    const double tol = y * 0x1p-44;
+    if (y < 0x1p52 && y < two63 * (1.0 - 0x1p-40) && (y - fy) > tol &&
+        (fy + 1.0 - y) > tol) {
+      X = (int64_t)fy;
+    } else {
+      const DD zd = dd_div_d(dd_log(V), -beta);
+      const DD Y = dd_mul_d(dd_exp(zd), kTailM);
+      if (Y.hi > two63 || (Y.hi == two63 && Y.lo >= 0.0)) {
+        *flags |= kFlagTailCapped;
+        continue;
+      }
+      X = dd_floor(Y);
+    }
+    if (W * gm <= tail_g(beta, (double)X)) return X;
+  }
+  return (int64_t)kTailM;
+}
+
+}  // namespace zpl

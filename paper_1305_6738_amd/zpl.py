@@ -1,0 +1,229 @@
+"""ctypes binding of libzpl (include/zpl.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels.  PyTorch is
+used only to hold device memory (tensor.data_ptr()) and to name HIP streams
+(torch.cuda.Stream.cuda_stream).  If the library is not built this module
+raises on use: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from pathlib import Path
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libzpl.so"
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+FLAG_ALL_ONES, FLAG_TAIL_CAPPED, FLAG_BISECT, FLAG_NOCONV = 1, 2, 4, 8
+LAUNCH_BATCHED, LAUNCH_PLAIN = 0, 1
+FORM_AUTO, FORM_LANE, FORM_WAVE, FORM_HEAVY = 0, 1, 2, 3
+_FORMS = {"auto": FORM_AUTO, "lane": FORM_LANE, "wave": FORM_WAVE, "heavy": FORM_HEAVY}
+_LAUNCH = {"batched": LAUNCH_BATCHED, "plain": LAUNCH_PLAIN}
+TABLE_H = 4096
+
+
+class ZplError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("zpl error %d: %s" % (status, msg))
+        self.status = status
+
+
+class Cell(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("n", C.c_int64), ("replicates", C.c_int64),
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class SimOpts(C.Structure):
+    _fields_ = [("launch", C.c_int32), ("form", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(
+                "libzpl.so is not built (run __graft_entry__.build() or "
+                "python -m paper_1305_6738_amd._build); there is no CPU fallback")
+        L = C.CDLL(str(LIB_PATH))
+        vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+        P = C.POINTER
+        L.zpl_create.argtypes = [P(vp), i32, u64]
+        L.zpl_create.restype = i32
+        L.zpl_destroy.argtypes = [vp]
+        L.zpl_destroy.restype = None
+        L.zpl_last_error.argtypes = []
+        L.zpl_last_error.restype = C.c_char_p
+        L.zpl_simulate_cells.argtypes = [vp, P(Cell), i32, P(u32), P(u32), i32, P(d), vp, vp,
+                                         vp, vp, P(SimOpts), vp]
+        L.zpl_simulate_cells.restype = i32
+        L.zpl_set_timing.argtypes = [vp, i32]
+        L.zpl_set_timing.restype = i32
+        L.zpl_get_timing.argtypes = [vp, P(d)]
+        L.zpl_get_timing.restype = i32
+        L.zpl_fit.argtypes = [vp, vp, i64, i32, P(d), P(d), P(u32), vp]
+        L.zpl_fit.restype = i32
+        L.zpl_bootstrap_pvalue.argtypes = [vp, vp, i64, i32, i64, u64, u32, P(d), P(d), P(d),
+                                           P(u32), vp]
+        L.zpl_bootstrap_pvalue.restype = i32
+        L.zpl_sample_draws.argtypes = [vp, d, i64, u64, u32, i64, i64, vp, vp, vp]
+        L.zpl_sample_draws.restype = i32
+        L.zpl_cdf_table.argtypes = [vp, d, vp, vp]
+        L.zpl_cdf_table.restype = i32
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list:
+    return ["zpl_create", "zpl_destroy", "zpl_last_error", "zpl_simulate_cells",
+            "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
+            "zpl_sample_draws", "zpl_cdf_table"]
+
+
+def _check(st: int):
+    if st != OK:
+        raise ZplError(st, lib().zpl_last_error().decode())
+
+
+def _dptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("device buffers must be CUDA (HIP) tensors")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+@dataclass
+class CellSpec:
+    alpha: float
+    n: int
+    replicates: int
+    seed: int = 0
+    stream: int = 0
+
+
+def _cells(cells: Sequence) -> C.Array:
+    arr = (Cell * len(cells))()
+    for i, c in enumerate(cells):
+        if isinstance(c, dict):
+            c = CellSpec(**c)
+        elif not isinstance(c, CellSpec):
+            c = CellSpec(*c)
+        arr[i] = Cell(float(c.alpha), int(c.n), int(c.replicates), int(c.seed), int(c.stream), 0)
+    return arr
+
+
+class Context:
+    """One libzpl context on one HIP device."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        h = C.c_void_p()
+        _check(lib().zpl_create(C.byref(h), int(device), int(mem_budget_bytes)))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().zpl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- zpl_simulate_cells -------------------------------------------------
+    def simulate_cells(self, cells: Sequence, quantiles: Iterable = ((9, 10), (95, 100), (99, 100)),
+                       d_out=None, alpha_hat_out=None, flags_out=None, fingerprint_out=None,
+                       launch: str = "batched", form: str = "auto", use_graph: bool = False,
+                       stream=None) -> Optional[np.ndarray]:
+        cs = _cells(cells)
+        q = list(quantiles) if quantiles is not None else []
+        nq = len(q)
+        qn = (C.c_uint32 * max(nq, 1))(*[a for a, _ in q])
+        qd = (C.c_uint32 * max(nq, 1))(*[b for _, b in q])
+        out = np.zeros((len(cs), max(nq, 1)))
+        opts = SimOpts(_LAUNCH[launch], _FORMS[form], 1 if use_graph else 0, 0)
+        _check(lib().zpl_simulate_cells(
+            self._h, cs, len(cs), qn, qd, nq,
+            out.ctypes.data_as(C.POINTER(C.c_double)) if nq else None,
+            _dptr(d_out), _dptr(alpha_hat_out), _dptr(flags_out), _dptr(fingerprint_out),
+            C.byref(opts), _stream(stream)))
+        return out[:, :nq] if nq else None
+
+    # -- timing ---------------------------------------------------------------
+    def set_timing(self, enable: bool = True):
+        _check(lib().zpl_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """Milliseconds per kernel group of the last timed simulation."""
+        ms = (C.c_double * 4)()
+        _check(lib().zpl_get_timing(self._h, ms))
+        return {"tables": ms[0], "simulate": ms[1], "heavy": ms[2], "select": ms[3]}
+
+    # -- zpl_fit ------------------------------------------------------------
+    def fit(self, x, stream=None) -> dict:
+        ptr, n, on_dev, keep = _xarg(x)
+        a, D, f = C.c_double(), C.c_double(), C.c_uint32()
+        st = lib().zpl_fit(self._h, ptr, n, on_dev, C.byref(a), C.byref(D), C.byref(f),
+                           _stream(stream))
+        del keep
+        if st not in (OK, ENOCONV):
+            _check(st)
+        return {"alpha_hat": a.value, "D": D.value, "flags": f.value, "status": st}
+
+    # -- zpl_bootstrap_pvalue -----------------------------------------------
+    def bootstrap_pvalue(self, x, B: int, seed: int, stream_id: int = 0, stream=None) -> dict:
+        ptr, n, on_dev, keep = _xarg(x)
+        a, D, p, f = C.c_double(), C.c_double(), C.c_double(), C.c_uint32()
+        st = lib().zpl_bootstrap_pvalue(self._h, ptr, n, on_dev, int(B), int(seed),
+                                        int(stream_id), C.byref(a), C.byref(D), C.byref(p),
+                                        C.byref(f), _stream(stream))
+        del keep
+        _check(st)
+        return {"alpha_hat": a.value, "D": D.value, "p_value": p.value, "flags": f.value}
+
+    # -- zpl_sample_draws / zpl_cdf_table -----------------------------------
+    def sample_draws(self, alpha: float, n: int, seed: int, stream_id: int, rep_lo: int,
+                     count: int, x_out, flags_out, stream=None):
+        _check(lib().zpl_sample_draws(self._h, float(alpha), int(n), int(seed), int(stream_id),
+                                      int(rep_lo), int(count), _dptr(x_out), _dptr(flags_out),
+                                      _stream(stream)))
+
+    def cdf_table(self, alpha: float, T_out, stream=None):
+        _check(lib().zpl_cdf_table(self._h, float(alpha), _dptr(T_out), _stream(stream)))
+
+
+def _xarg(x):
+    """(pointer, n, on_device, keepalive) for an int64 dataset."""
+    if getattr(x, "is_cuda", False):
+        import torch
+        if x.dtype != torch.int64:
+            raise ValueError("x must be int64")
+        x = x.contiguous()
+        return C.c_void_p(x.data_ptr()), int(x.numel()), 1, x
+    a = np.ascontiguousarray(np.asarray(x), dtype=np.int64)
+    return C.c_void_p(a.ctypes.data), int(a.size), 0, a

@@ -1,0 +1,237 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: drawn integers, histograms (multiset fingerprints) and flags bit-exact on
+the same Philox stream; alpha_hat within 1e-10 relative; D within 1e-12
+absolute; quantiles identical to the oracle's order statistic of the same D
+array, and within 1e-12 of the oracle's own.  Sizes span several work units
+and ragged tails; full-size configurations are checked on sampled replicates.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+QS = [(9, 10), (95, 100), (99, 100), (999, 1000)]
+KEEP_FLAGS = 1 | 2  # ALL_ONES | TAIL_CAPPED (BISECT is solver-path information)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_6738_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def run_cells(ctx, cells, **kw):
+    R = sum(c[2] for c in cells)
+    d = torch.zeros(R, dtype=torch.float64, device="cuda")
+    a = torch.zeros(R, dtype=torch.float64, device="cuda")
+    f = torch.zeros(R, dtype=torch.int32, device="cuda")
+    fp = torch.zeros(R, dtype=torch.int64, device="cuda")
+    q = ctx.simulate_cells(cells, quantiles=QS, d_out=d, alpha_hat_out=a, flags_out=f,
+                           fingerprint_out=fp, **kw)
+    torch.cuda.synchronize()
+    return {"q": q, "D": d.cpu().numpy(), "alpha_hat": a.cpu().numpy(),
+            "flags": f.cpu().numpy().view(np.uint32), "fp": fp.cpu().numpy().view(np.uint64)}
+
+
+def compare_cell(orc, g, lo, cell, reps=None):
+    """Compare GPU outputs g[lo + r] with the oracle for replicates `reps`."""
+    alpha, n, R, seed, stream = cell
+    if reps is None:
+        ref = orc.simulate(alpha, n, seed, stream, 0, R)
+        idx = np.arange(R)
+    else:
+        idx = np.asarray(sorted(set(int(r) for r in reps)))
+        parts = [orc.simulate(alpha, n, seed, stream, int(r), 1) for r in idx]
+        ref = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    gi = lo + idx
+    mism = np.nonzero(g["fp"][gi] != ref["fp"])[0]
+    assert mism.size == 0, "histogram fingerprints differ at replicates %s" % idx[mism[:10]]
+    assert np.array_equal(g["flags"][gi] & KEEP_FLAGS, ref["flags"] & KEEP_FLAGS)
+    rel = np.abs(g["alpha_hat"][gi] - ref["alpha_hat"]) / ref["alpha_hat"]
+    assert rel.max() < 1e-10, rel.max()
+    dd = np.abs(g["D"][gi] - ref["D"])
+    assert dd.max() < 1e-12, dd.max()
+    return ref
+
+
+def test_cdf_table_matches_oracle(ctx, orc):
+    for alpha in [1.2, 1.5, 2.5, 3.5, 10.0]:
+        say("table alpha", alpha)
+        T = torch.zeros(4096, dtype=torch.float64, device="cuda")
+        ctx.cdf_table(alpha, T)
+        torch.cuda.synchronize()
+        d = np.abs(T.cpu().numpy() - orc.cdf_table(alpha))
+        assert d.max() <= 8 * 2.0 ** -53, (alpha, d.max())
+
+
+@pytest.mark.parametrize("alpha,n,count", [(2.5, 257, 4), (1.5, 300, 4), (1.2, 500, 6),
+                                           (3.5, 33, 3), (1.01, 64, 2)])
+def test_draws_bit_exact(ctx, orc, alpha, n, count):
+    say("draws", alpha, n, count)
+    seed, stream, rep_lo = 0x5eed_0000_1234, 11, 7
+    x = torch.zeros(count * n, dtype=torch.int64, device="cuda")
+    f = torch.zeros(count, dtype=torch.int32, device="cuda")
+    ctx.sample_draws(alpha, n, seed, stream, rep_lo, count, x, f)
+    torch.cuda.synchronize()
+    xs = x.cpu().numpy().reshape(count, n)
+    fs = f.cpu().numpy().view(np.uint32)
+    for r in range(count):
+        want, wf = orc.sample(alpha, n, seed, stream, rep_lo + r)
+        bad = np.nonzero(xs[r] != want)[0]
+        assert bad.size == 0, ("replicate", rep_lo + r, "draws", bad[:5], xs[r][bad[:5]],
+                               want[bad[:5]])
+        assert fs[r] == wf
+
+
+@pytest.mark.parametrize("form", ["auto", "lane", "wave", "heavy"])
+def test_simulate_small_cells_all_forms(ctx, orc, form):
+    """Several cells (ragged R, odd n, n = 1 and 2, heavy tail) in one launch."""
+    cells = [(2.5, 100, 700, 42, 0), (1.5, 37, 300, 42, 1), (3.5, 1, 65, 7, 2),
+             (2.0, 2, 129, 7, 3), (1.2, 200, 70, 9, 4), (1.75, 513, 90, 9, 5)]
+    if form == "lane":
+        cells = [c for c in cells]
+    say("simulate small", form)
+    g = run_cells(ctx, cells, form=form)
+    lo = 0
+    for ci, cell in enumerate(cells):
+        compare_cell(orc, g, lo, cell)
+        D = g["D"][lo:lo + cell[2]]
+        for qi, (a, b) in enumerate(QS):
+            assert g["q"][ci, qi] == orc.quantile(D, a, b)
+        lo += cell[2]
+
+
+def test_forms_and_launches_bit_identical(ctx):
+    """Same replicate, same bits: lane / wave / heavy forms, plain vs batched
+    launches and hipGraph replay all give identical outputs."""
+    cells = [(2.5, 300, 600, 3, 0), (1.75, 90, 257, 3, 1), (3.0, 12, 300, 5, 2)]
+    say("invariance")
+    base = run_cells(ctx, cells, form="lane")
+    for kw in [dict(form="wave"), dict(form="heavy"), dict(launch="plain"),
+               dict(use_graph=True), dict(use_graph=True)]:
+        say("  vs", kw)
+        g = run_cells(ctx, cells, **kw)
+        for k in ("D", "alpha_hat", "flags", "fp"):
+            assert np.array_equal(g[k], base[k]), (kw, k)
+        assert np.array_equal(g["q"], base["q"])
+
+
+def test_cell_order_invariance(ctx):
+    cells = [(2.5, 50, 300, 1, 0), (2.0, 70, 200, 1, 1)]
+    say("cell order")
+    a = run_cells(ctx, cells)
+    b = run_cells(ctx, cells[::-1])
+    assert np.array_equal(a["D"][:300], b["D"][200:])
+    assert np.array_equal(a["D"][300:], b["D"][:200])
+
+
+def test_config_single_cell_full(ctx, orc):
+    """alpha=2.5, n=100, R=10,000, seed 42: every replicate vs the oracle."""
+    cell = (2.5, 100, 10000, 42, 0)
+    say("C1 full")
+    g = run_cells(ctx, [cell])
+    ref = compare_cell(orc, g, 0, cell)
+    for qi, (a, b) in enumerate(QS):
+        assert g["q"][0, qi] == orc.quantile(g["D"], a, b)
+        assert abs(g["q"][0, qi] - orc.quantile(ref["D"], a, b)) < 1e-12
+
+
+def test_config_table_n1000_sampled(ctx, orc):
+    """The n = 1000 slice of the full table (9 alphas x R = 100,000) in one
+    batched launch; 40 sampled replicates per cell vs the oracle, plus the
+    quantile rule on the GPU's own D arrays."""
+    alphas = [1.5 + 0.25 * i for i in range(9)]
+    cells = [(a, 1000, 100000, 42, 10 * i + 6) for i, a in enumerate(alphas)]
+    say("C2 n=1000 slice")
+    g = run_cells(ctx, cells)
+    rng = np.random.default_rng(0)
+    lo = 0
+    for ci, cell in enumerate(cells):
+        reps = list(rng.integers(0, cell[2], 38)) + [0, cell[2] - 1]
+        compare_cell(orc, g, lo, cell, reps)
+        D = g["D"][lo:lo + cell[2]]
+        for qi, (a, b) in enumerate(QS):
+            assert g["q"][ci, qi] == orc.quantile(D, a, b)
+        lo += cell[2]
+
+
+def test_heavy_tail_sampled(ctx, orc):
+    """alpha in {1.2, 1.3, 1.4, 1.5}, n = 10,000 (R reduced to 2,000 here):
+    sampled replicates, including the capped tail and the overflow path."""
+    cells = [(a, 10000, 2000, 42, 40 + i) for i, a in enumerate([1.2, 1.3, 1.4, 1.5])]
+    say("heavy tail")
+    g = run_cells(ctx, cells)
+    rng = np.random.default_rng(1)
+    lo = 0
+    for cell in cells:
+        reps = list(rng.integers(0, cell[2], 12)) + [cell[2] - 1]
+        compare_cell(orc, g, lo, cell, reps)
+        lo += cell[2]
+    assert np.any(g["flags"] & 2)  # some replicate met the 2^63 cap at alpha = 1.2
+
+
+def test_fit_matches_oracle(ctx, orc):
+    rng = np.random.default_rng(7)
+    sets = [np.ones(10, np.int64), np.ones(1, np.int64), np.array([1, 2], np.int64),
+            np.array([5], np.int64), rng.zipf(2.2, 5000).astype(np.int64),
+            np.minimum(rng.zipf(1.3, 20000), 2 ** 62).astype(np.int64),
+            np.array([1, 1, 3, 2 ** 62, 17, 4097, 4096, 4098], np.int64)]
+    for x in sets:
+        say("fit n", x.size)
+        for dev in (False, True):
+            xin = torch.from_numpy(x).cuda() if dev else x
+            r = ctx.fit(xin)
+            o = orc.fit(x)
+            assert abs(r["alpha_hat"] - o["alpha_hat"]) <= 1e-10 * o["alpha_hat"]
+            assert abs(r["D"] - o["D"]) < 1e-12
+            assert (r["flags"] & 1) == (o["flags"] & 1)
+
+
+def test_fit_equals_simulated_replicate_bits(ctx, orc):
+    """The dataset fit and the simulation kernels share their arithmetic: the
+    oracle's draws of a replicate, fitted on the GPU, give the GPU
+    simulation's alpha_hat and D for that replicate bit for bit."""
+    cell = (2.2, 400, 50, 9, 3)
+    g = run_cells(ctx, [cell])
+    for r in [0, 17, 49]:
+        x, _ = orc.sample(cell[0], cell[1], cell[3], cell[4], r)
+        f = ctx.fit(x)
+        assert f["alpha_hat"] == g["alpha_hat"][r] and f["D"] == g["D"][r]
+
+
+def test_bootstrap_matches_oracle(ctx, orc):
+    rng = np.random.default_rng(9)
+    for x in [rng.zipf(2.5, 300).astype(np.int64), np.ones(12, np.int64),
+              (np.round(rng.lognormal(1.0, 1.0, 400)) + 1).astype(np.int64)]:
+        say("bootstrap n", x.size)
+        r = ctx.bootstrap_pvalue(x, 2500, 77, 5)
+        o = orc.bootstrap_pvalue(x, 2500, 77, 5)
+        assert abs(r["alpha_hat"] - o["alpha_hat"]) <= 1e-10 * o["alpha_hat"]
+        assert abs(r["D"] - o["D"]) < 1e-12
+        assert r["p_value"] == o["p_value"]
+
+
+def test_invalid_arguments_raise(ctx):
+    from paper_1305_6738_amd import ZplError
+    with pytest.raises(ZplError):
+        ctx.simulate_cells([(1.0, 10, 10, 0, 0)])
+    with pytest.raises(ZplError):
+        ctx.simulate_cells([(2.0, 0, 10, 0, 0)])
+    with pytest.raises(ZplError):
+        ctx.simulate_cells([(2.0, 10, 10, 0, 0)], quantiles=[(10, 10)])
+    with pytest.raises(ZplError):
+        ctx.fit(np.array([1, 0, 2], np.int64))

@@ -1,0 +1,143 @@
+"""CPU checks of the library's scalar arithmetic (zpl_math.hpp compiled for
+the host) against the oracle and mpmath: Philox, the exact tail floor with
+its double-double path, the CDF table, zeta and the MLE.  These validate the
+logic the kernels inline; GPU parity is checked separately."""
+import ctypes as C
+import math
+import shutil
+import subprocess
+from pathlib import Path
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+HERE = Path(__file__).resolve().parent
+
+
+@pytest.fixture(scope="module")
+def hm(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not Path(hipcc).exists():
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("hm") / "libhm.so"
+    subprocess.run([hipcc, "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    str(HERE / "hostprobe" / "hostmath.cpp"), "-o", str(out)],
+                   check=True, capture_output=True)
+    L = C.CDLL(str(out))
+    P = C.POINTER
+    L.hm_philox.argtypes = [P(C.c_uint32)] * 3
+    L.hm_tail.argtypes = [C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                          P(C.c_uint32)]
+    L.hm_tail.restype = C.c_int64
+    L.hm_mle.argtypes = [C.c_double, P(C.c_uint32)]
+    L.hm_mle.restype = C.c_double
+    L.hm_zeta3.argtypes = [C.c_double, P(C.c_double)]
+    L.hm_table.argtypes = [C.c_double, P(C.c_double)]
+    L.hm_survival.argtypes = [C.c_double, C.c_int64]
+    L.hm_survival.restype = C.c_double
+    L.hm_S.argtypes = [P(C.c_int64), C.c_int64]
+    L.hm_S.restype = C.c_double
+    L.hm_dd_exp_log.argtypes = [C.c_double, P(C.c_double)]
+    return L
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def test_philox_same_as_oracle(hm, orc):
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        c = rng.integers(0, 2**32, 4).astype(np.uint32)
+        k = rng.integers(0, 2**32, 2).astype(np.uint32)
+        out = np.zeros(4, np.uint32)
+        hm.hm_philox(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+        assert np.array_equal(out, orc.philox(c, k))
+
+
+@pytest.mark.parametrize("alpha", [1.2, 1.3, 1.5, 2.5, 3.5])
+def test_tail_draws_bit_exact_vs_oracle(hm, orc, alpha):
+    """The library's tail sampler (FP64 with a double-double floor near
+    integers and above 2^52) returns the oracle's quad-precision floor, for
+    every draw index (the tail stream does not depend on the body uniform)."""
+    seed, stream = 0xfeedbeef12345, 3
+    big = 0
+    for rep in range(3):
+        for i in range(1500):
+            f1 = C.c_uint32(0)
+            x_h = hm.hm_tail(alpha, seed, stream, rep, i, C.byref(f1))
+            x_o, f_o = orc.tail_draw(alpha, seed, stream, rep, i)
+            assert x_h == x_o, (alpha, rep, i, x_h, x_o)
+            assert f1.value == f_o
+            big += x_h > 2 ** 52
+    if alpha == 1.2:
+        assert big > 5  # the double-double path above 2^52 was exercised
+
+
+def test_dd_exp_log_precision(hm):
+    out = np.zeros(4)
+    for v in [2.0 ** -53, 1e-300, 0.3, 0.999999, 1.5, 7.0, 40.0, 700.0]:
+        hm.hm_dd_exp_log(v, _p(out, C.c_double))
+        with mp.workdps(60):
+            L = mp.log(mp.mpf(v))
+            got = mp.mpf(out[0]) + mp.mpf(out[1])
+            # near v = 1 the double-double log is accurate in absolute terms
+            assert abs(got - L) <= abs(L) * mp.mpf(2) ** -100 + mp.mpf(2) ** -104
+            if v < 700:
+                E = mp.exp(mp.mpf(v))
+                got = mp.mpf(out[2]) + mp.mpf(out[3])
+                assert abs(got - E) <= E * mp.mpf(2) ** -100
+
+
+@pytest.mark.parametrize("alpha,ulps", [(1.05, 12), (1.2, 4), (1.5, 2), (2.5, 2), (3.5, 1),
+                                        (8.0, 1)])
+def test_table_within_ulps_of_oracle(hm, orc, alpha, ulps):
+    """Both sides round T[k] = 1 - zeta(a,k+1)/zeta(a) independently; the gap
+    (in units of 2^-53) grows as alpha -> 1 where zeta(a) ~ 1/(a-1)."""
+    T = np.zeros(4096)
+    hm.hm_table(alpha, _p(T, C.c_double))
+    To = orc.cdf_table(alpha)
+    assert np.max(np.abs(T - To)) <= ulps * 2.0 ** -53
+    assert np.all(np.diff(T) >= 0)
+
+
+@pytest.mark.parametrize("s", [1.0 + 2 ** -20, 1.01, 1.5, 2.0, 2.5, 3.9, 8.0, 16.6, 40.0, 64.0])
+def test_zeta3_vs_oracle(hm, orc, s):
+    out = np.zeros(3)
+    hm.hm_zeta3(s, _p(out, C.c_double))
+    ref = orc.zeta3(s)
+    tol = 1e-15 * max(1.0, s)
+    assert np.all(np.abs(out - ref) <= tol * np.abs(ref)), (out, ref)
+
+
+def test_survival_vs_oracle(hm, orc):
+    for a in [1.2, 2.5, 3.5]:
+        for v in [0, 1, 5, 15, 16, 17, 100, 4095, 4096, 4097, 10 ** 6, 10 ** 15, 2 ** 63 - 1]:
+            got = hm.hm_survival(a, v)
+            with mp.workdps(60):
+                want = float(mp.zeta(a, mp.mpf(v) + 1))
+            # relative error ~ a * ulp(ln v): up to ~1e-14 near v = 2^63
+            assert abs(got - want) <= 2e-14 * abs(want) + 1e-300, (a, v, got, want)
+
+
+@pytest.mark.parametrize("m", [43.0, 5.0, 1.3, 0.57, 0.2, 0.0693, 0.01, 6.9e-6, 1e-9])
+def test_mle_vs_oracle(hm, orc, m):
+    f = C.c_uint32(0)
+    a = hm.hm_mle(m, C.byref(f))
+    ao, _ = orc.mle(m)
+    assert abs(a - ao) <= 2e-14 * ao
+    assert not (f.value & 8)
+
+
+def test_exact_S_order_independent(hm):
+    rng = np.random.default_rng(0)
+    x = rng.zipf(1.4, size=5000).astype(np.int64)
+    x = np.minimum(x, 2 ** 62)
+    s1 = hm.hm_S(_p(x, C.c_int64), x.size)
+    y = x[rng.permutation(x.size)].copy()
+    s2 = hm.hm_S(_p(y, C.c_int64), y.size)
+    assert s1 == s2
+    want = math.fsum(np.log(x.astype(np.float64)))
+    assert abs(s1 - want) <= 4e-16 * want
