@@ -36,6 +36,10 @@ OPS_PER_REPLICATE = 2000
 PEAK_OPS = 256 * 64 * 2.4e9
 
 
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def percentile(v, p):
     import numpy as np
     return float(np.percentile(np.asarray(v), p)) if len(v) else None
@@ -67,7 +71,7 @@ def cpu_baseline(cells, target_s=12.0):
 
 def fit_latency(ctx, n_req=200):
     from inputs import serving_requests
-    reqs = serving_requests(duration_s=1e9, qps=1.0, seed=11)[:n_req]
+    reqs = serving_requests(duration_s=1e9, qps=1.0, seed=11, max_requests=n_req)
     lat = []
     for (_, x, _, _) in reqs:
         t0 = time.perf_counter()
@@ -109,6 +113,7 @@ def main(argv=None):
     for _ in range(args.warmup):
         ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
     torch.cuda.synchronize()
+    progress("warmup done (%d steps)" % args.warmup)
     sim_ms, all_ms = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -120,6 +125,7 @@ def main(argv=None):
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = total_R / (ms_per_step / 1e3)
+    progress("timed region: %.3f ms/step, %.4g replicates/s" % (ms_per_step, value))
 
     # dominant kernel: the persistent simulation launch
     sim_avg_ms = sum(sim_ms) / len(sim_ms)
@@ -154,6 +160,7 @@ def main(argv=None):
         out["plain_value"] = total_R / (plain_ms / 1e3)
         out["plain_ms_per_step"] = plain_ms
         out["batched_over_plain"] = value / out["plain_value"]
+        progress("plain: %.3f ms/step" % plain_ms)
         # batched launch replayed from a hipGraph
         ctx.simulate_cells(cells, quantiles=QS, d_out=d, use_graph=True, stream=stream)
         torch.cuda.synchronize()
@@ -163,10 +170,13 @@ def main(argv=None):
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - t0) * 1e3 / args.steps
         out["graph_value"] = total_R / (g_ms / 1e3)
+        progress("graph replay: %.3f ms/step" % g_ms)
         out["fit_latency"] = fit_latency(ctx)
+        progress("fit latency done")
         out["quantiles_first_cell"] = [float(v) for v in q[0]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cells)
+        progress("cpu baseline done")
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0

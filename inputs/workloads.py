@@ -43,7 +43,8 @@ def heavy_tail(R: int = 100000, n: int = 10000):
 
 
 def serving_requests(duration_s: float = 60.0, qps: float = 200.0, seed: int = 7,
-                     n_lo: int = 50, n_hi: int = 100000, zipf_frac: float = 0.9):
+                     n_lo: int = 50, n_hi: int = 100000, zipf_frac: float = 0.9,
+                     max_requests: int = 1 << 30):
     """Poisson arrivals; each request an int64 dataset with n log-uniform on
     [n_lo, n_hi]: with probability zipf_frac a Zipf(alpha) sample (numpy's
     generator, alpha uniform on [1.5, 3.5]), otherwise round(lognormal(1, 1)) + 1.
@@ -51,7 +52,7 @@ def serving_requests(duration_s: float = 60.0, qps: float = 200.0, seed: int = 7
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     t = 0.0
-    while True:
+    while len(out) < max_requests:
         t += rng.exponential(1.0 / qps)
         if t >= duration_s:
             break

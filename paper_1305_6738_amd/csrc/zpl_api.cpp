@@ -95,6 +95,7 @@ struct zpl_ctx {
   std::vector<char> graph_key;
   uint32_t esc_cap = 0;
   // optional per-kernel timing of the last non-graph simulation
+  hipStream_t cap_stream = nullptr;  // graphs are captured here (never the null stream)
   bool timing = false;
   bool timed = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -418,10 +419,14 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
         (void)hipGraphExecDestroy(c->graph_exec);
         c->graph_valid = false;
       }
+      // the plan upload above must be complete before a replay on any stream
+      HIP_TRY(hipStreamSynchronize(s));
+      if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       hipGraph_t g;
-      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      zpl_status st = enqueue_run(c, P, o.launch, L, out, Dsel, need_sel ? n_q : 0, s, false);
-      hipError_t ce = hipStreamEndCapture(s, &g);
+      HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      zpl_status st =
+          enqueue_run(c, P, o.launch, L, out, Dsel, need_sel ? n_q : 0, c->cap_stream, false);
+      hipError_t ce = hipStreamEndCapture(c->cap_stream, &g);
       if (st != ZPL_OK) {
         if (ce == hipSuccess) (void)hipGraphDestroy(g);
         return st;
@@ -547,6 +552,7 @@ void zpl_destroy(zpl_ctx* c) {
   if (c->ln) (void)hipFree(c->ln);
   for (hipEvent_t e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->pin) (void)hipHostFree(c->pin);
   delete c;
 }
