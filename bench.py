@@ -81,6 +81,41 @@ def fit_latency(ctx, n_req=200):
             "what": "zpl_fit of a host int64 dataset (n log-uniform 50..1e5), H2D included"}
 
 
+def serving(ctx, qps=200.0, seconds=10.0, B=2500):
+    """Poisson request stream served with continuous batching (zpl_serve_*):
+    each request fits its dataset and returns a B-replicate bootstrap p-value.
+    Latency is measured by the library from submit to results ready."""
+    from inputs import serving_requests
+    reqs = serving_requests(duration_s=seconds, qps=qps, seed=7)
+    ctx.serve_start(mem_budget_bytes=8 << 30)
+    tickets = []
+    t0 = time.perf_counter()
+    try:
+        for k, (ta, x, _, _) in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            tickets.append(ctx.serve_submit(x, B, seed=k, stream_id=k))
+        lat, qms, bs, bad = [], [], [], 0
+        for t in tickets:
+            r = ctx.serve_poll(t, wait_ms=120000)
+            if r is None or r["status"] != 0:
+                bad += 1
+                continue
+            lat.append(r["latency_ms"])
+            qms.append(r["queue_ms"])
+            bs.append(r["batch_size"])
+        elapsed = time.perf_counter() - t0
+    finally:
+        ctx.serve_stop()
+    return {"qps_offered": qps, "requests": len(tickets), "failed": bad,
+            "sustained_qps": len(tickets) / elapsed, "B": B,
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "queue_p50_ms": percentile(qms, 50), "mean_batch": sum(bs) / max(len(bs), 1),
+            "what": "Poisson 200/s, n log-uniform 50..1e5 (90% Zipf, 10% lognormal), "
+                    "fit + B=2500 bootstrap per request, continuous batching"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +125,7 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true",
                     help="only the batched timed region (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -173,6 +209,10 @@ def main(argv=None):
         progress("graph replay: %.3f ms/step" % g_ms)
         out["fit_latency"] = fit_latency(ctx)
         progress("fit latency done")
+        if args.serve_seconds > 0:
+            out["serving"] = serving(ctx, seconds=args.serve_seconds)
+            progress("serving: p50 %.2f ms p99 %.2f ms" % (out["serving"]["p50_ms"],
+                                                          out["serving"]["p99_ms"]))
         out["quantiles_first_cell"] = [float(v) for v in q[0]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cells)

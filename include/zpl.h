@@ -157,6 +157,55 @@ zpl_status zpl_bootstrap_pvalue(zpl_ctx *ctx, const int64_t *x, int64_t n,
                                 uint32_t stream_id, double *alpha_hat, double *D,
                                 double *p_value, uint32_t *flags, void *stream);
 
+/* --------------------------------------------------------------------------
+ * Serving: parametric-bootstrap requests (zpl_bootstrap_pvalue's computation)
+ * under continuous batching.  A scheduler thread admits queued requests while
+ * their device memory fits mem_budget_bytes, fits all admitted datasets in
+ * one launch and runs all of their bootstraps as the cells of one batched
+ * simulation; requests submitted meanwhile join the next iteration.  A
+ * request's result is bit-identical to zpl_bootstrap_pvalue on the same
+ * (x, B, seed, stream_id), whatever it is batched with.
+ * ------------------------------------------------------------------------ */
+typedef struct zpl_serve_opts {
+  uint64_t mem_budget_bytes; /* device memory per iteration (0 = 8 GiB)        */
+  int32_t max_batch;         /* requests per iteration (0 = 256)               */
+  int32_t max_queue;         /* queued requests before submit says BUSY (0 = 65536) */
+  int32_t reserved;          /* must be 0                                      */
+  int32_t reserved2;         /* must be 0                                      */
+} zpl_serve_opts;
+
+typedef struct zpl_serve_result {
+  int32_t done;        /* 0: still queued or running; 1: fields below valid     */
+  zpl_status status;   /* ZPL_OK, ZPL_EINVAL (some x < 1), ZPL_ENOMEM (request
+                          alone exceeds the budget), ZPL_EDEVICE              */
+  double alpha_hat;    /* eq. (2)                                             */
+  double D;            /* eq. (3)                                             */
+  double p_value;      /* #{b : D_b >= D} / B                                 */
+  uint32_t flags;      /* fit flags (ZPL_FLAG_*)                               */
+  int32_t batch_size;  /* requests in the iteration that served this one       */
+  double queue_ms;     /* submit -> start of its iteration                     */
+  double latency_ms;   /* submit -> results ready                              */
+} zpl_serve_result;
+
+/* Start the scheduler on this context (opts may be NULL).  The scheduler
+ * uses its own internal context and stream; the caller may keep using ctx. */
+zpl_status zpl_serve_start(zpl_ctx *ctx, const zpl_serve_opts *opts);
+
+/* Queue one request: x[n] host int64 (copied before return), B bootstrap
+ * replicates, random stream (seed, stream_id).  *ticket identifies it.
+ * ZPL_EBUSY when max_queue requests are already waiting. */
+zpl_status zpl_serve_submit(zpl_ctx *ctx, const int64_t *x, int64_t n, int64_t B,
+                            uint64_t seed, uint32_t stream_id, uint64_t *ticket);
+
+/* Result of a request, waiting up to wait_ms for it (0 = do not wait).  A
+ * completed result is returned once; the ticket is then released.
+ * ZPL_ENOTFOUND for unknown or already released tickets. */
+zpl_status zpl_serve_poll(zpl_ctx *ctx, uint64_t ticket, int32_t wait_ms,
+                          zpl_serve_result *res);
+
+/* Finish the queued requests and stop the scheduler. */
+zpl_status zpl_serve_stop(zpl_ctx *ctx);
+
 /* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, n, seed,
  * stream_id) in draw order, for checking the sampler bit for bit.
  *   x_out     device [count * n] int64;  flags_out device [count] uint32

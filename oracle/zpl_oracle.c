@@ -276,7 +276,8 @@ double orc_mle(double m, uint32_t *flags) {
       hi = a;
     double gp = -(z[2] / z[0] - r1 * r1);
     double an = a - g / gp;
-    if (!(an > lo && an < hi)) {
+    /* closed bracket: a converged Newton step may land exactly on lo or hi */
+    if (!(an >= lo && an <= hi)) {
       an = 0.5 * (lo + hi);
       *flags |= ORC_FLAG_BISECT;
     }

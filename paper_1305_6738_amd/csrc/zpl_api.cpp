@@ -7,7 +7,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -77,7 +83,10 @@ double tail_prob(double a, int h) {
 
 }  // namespace
 
+struct Server;
+
 struct zpl_ctx {
+  Server* server = nullptr;
   int device = 0;
   int n_cu = 256;
   uint64_t budget = 0;
@@ -85,7 +94,7 @@ struct zpl_ctx {
   double* ln = nullptr;
   // scratch, grow-only
   DevBuf cells, tables, guides, units, hunits, queues, esc, esc_cnt, err, list_v, list_c,
-      heavy, dbuf, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d;
+      wslots, heavy, dbuf, gather, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d;
   // pinned host staging
   void* pin = nullptr;
   size_t pin_bytes = 0;
@@ -202,8 +211,8 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P) {
     P.total_R += z.replicates;
     P.max_n = std::max(P.max_n, z.n);
   }
-  // units: 256 replicates (one per lane, or 64 per wave) for lane/wave cells,
-  // 8 replicates for heavy cells
+  // units: kBlock replicates (one per lane, or 64 per wave) for lane/wave
+  // cells, 8 replicates (2 per wave) for heavy cells
   std::vector<std::pair<double, Unit>> tmp;
   for (int i = 0; i < n_cells; ++i) {
     const DevCell& d = P.cells[i];
@@ -252,6 +261,7 @@ struct Launch {
   int sim_grid = 0;
   int heavy_grid = 0;
   int64_t hstride = 0;
+  int64_t gcap = 0;
 };
 
 // Grows every scratch buffer the plan needs.
@@ -259,7 +269,7 @@ zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L
   const int nc = (int)P.cells.size();
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell) * nc));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * (size_t)kH * nc));
-  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (size_t)kG * nc));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (size_t)(kGuide + 1) * nc));
   ZPL_TRY(ensure(c, c->units, sizeof(Unit) * std::max<size_t>(1, P.units.size())));
   ZPL_TRY(ensure(c, c->hunits, sizeof(Unit) * std::max<size_t>(1, P.hunits.size())));
   ZPL_TRY(ensure(c, c->queues, sizeof(uint32_t) * (size_t)(nc + 8)));
@@ -271,21 +281,27 @@ zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L
   ZPL_TRY(ensure(c, c->esc, sizeof(uint64_t) * esc_cap));
   c->esc_cap = esc_cap;
   const int sim_grid =
-      (int)std::min<int64_t>((int64_t)P.units.size(), (int64_t)c->n_cu * 2);
+      (int)std::min<int64_t>((int64_t)P.units.size(), (int64_t)c->n_cu);
   L.sim_grid = sim_grid;
   const size_t nwaves = (size_t)std::max(sim_grid, 1) * kWaves;
   ZPL_TRY(ensure(c, c->list_v, sizeof(int64_t) * nwaves * kListCap));
   ZPL_TRY(ensure(c, c->list_c, sizeof(uint32_t) * nwaves * kListCap));
+  ZPL_TRY(ensure(c, c->wslots, (size_t)kWaveSlotBytes * 64 * nwaves));
   L.hstride = heavy_stride(P.max_n);
   int hg = (int)std::min<int64_t>((int64_t)P.hunits.size() + 64, (int64_t)c->n_cu * 2);
-  // keep the heavy scratch within a quarter of the budget
-  while (hg > 1 && (uint64_t)hg * L.hstride * 8 > c->budget / 4) hg /= 2;
+  // keep the heavy scratch (one area per wave) within a quarter of the budget
+  while (hg > 1 && (uint64_t)hg * kHeavyWaves * L.hstride * 8 > c->budget / 4) hg /= 2;
   L.heavy_grid = hg;
-  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)hg * L.hstride));
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)hg * kHeavyWaves * L.hstride));
   if (need_dbuf) ZPL_TRY(ensure(c, c->dbuf, sizeof(double) * (size_t)P.total_R));
   ZPL_TRY(ensure(c, c->qnum, sizeof(uint32_t) * std::max(n_q, 1)));
   ZPL_TRY(ensure(c, c->qden, sizeof(uint32_t) * std::max(n_q, 1)));
   ZPL_TRY(ensure(c, c->qout, sizeof(double) * std::max(nc * n_q, 1)));
+  // bracket gather: at most ~12% of a cell's replicates fall in a bracket
+  int64_t maxR = 1;
+  for (const DevCell& d : P.cells) maxR = std::max(maxR, d.R);
+  L.gcap = std::min<int64_t>(kSelGather, maxR * 3 / 20 + 1024);
+  if (n_q > 0) ZPL_TRY(ensure(c, c->gather, sizeof(uint64_t) * (size_t)nc * kSelQ * L.gcap));
   return ZPL_OK;
 }
 
@@ -311,18 +327,18 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
     for (int i = 0; i < nc; ++i) {
       const int b = P.cell_unit_begin[i], e = P.cell_unit_end[i];
       if (e <= b) continue;
-      const int grid = std::min(e - b, c->n_cu * 2);
+      const int grid = std::min(e - b, c->n_cu);
       HIP_TRY(launch_simulate(grid, dcells, (const double*)c->tables.p,
                               (const uint16_t*)c->guides.p, c->ln, units + b, e - b,
                               queues + 8 + i, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
-                              (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p,
+                              (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p, c->wslots.p,
                               (uint32_t*)c->err.p, s));
     }
   } else {
     HIP_TRY(launch_simulate(L.sim_grid, dcells, (const double*)c->tables.p,
                             (const uint16_t*)c->guides.p, c->ln, units, (int)P.units.size(),
                             queues + 0, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
-                            (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p,
+                            (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p, c->wslots.p,
                             (uint32_t*)c->err.p, s));
   }
   HIP_TRY(mark(2));
@@ -333,7 +349,8 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
   HIP_TRY(mark(3));
   if (n_q > 0 && Dsel)
     HIP_TRY(launch_select(Dsel, dcells, nc, n_q, (const uint32_t*)c->qnum.p,
-                          (const uint32_t*)c->qden.p, (double*)c->qout.p, s));
+                          (const uint32_t*)c->qden.p, (double*)c->qout.p,
+                          (uint64_t*)c->gather.p, L.gcap, s));
   HIP_TRY(mark(4));
   return ZPL_OK;
 }
@@ -500,6 +517,231 @@ zpl_status stage_x(zpl_ctx* c, const int64_t* x, int64_t n, int32_t on_dev, hipS
 
 }  // namespace
 
+
+// ===========================================================================
+// Serving: continuous batching of bootstrap p-value requests.
+//
+// A scheduler thread owns an internal context and stream.  Each iteration it
+// admits queued requests while their device memory fits the budget, fits all
+// of their datasets in one launch, runs all of their B-replicate bootstraps
+// as the cells of one batched simulation, counts D_b >= D_obs per request in
+// one launch, and publishes the results.  Requests arriving meanwhile wait
+// for the next iteration.  Every draw is a pure function of (seed, stream,
+// replicate), so a request's result does not depend on what it is batched
+// with.
+// ===========================================================================
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  uint64_t ticket = 0;
+  std::vector<int64_t> x;
+  int64_t B = 0;
+  uint64_t seed = 0;
+  uint32_t stream_id = 0;
+  Clock::time_point t_submit, t_start, t_done;
+  bool done = false;
+  zpl_status status = ZPL_OK;
+  double ahat = 0.0, D = 0.0, p = 0.0;
+  uint32_t flags = 0;
+  int32_t batch_size = 0;
+};
+
+size_t req_bytes(const Req& r) {
+  // dataset + its overflow/list scratch + bootstrap D + table and guide
+  return (size_t)r.x.size() * 8 * 4 + (size_t)r.B * 8 + sizeof(double) * kH +
+         sizeof(uint16_t) * (kGuide + 1) + 4096;
+}
+
+}  // namespace
+
+struct Server {
+  zpl_ctx* eng = nullptr;  // internal context used only by the scheduler thread
+  hipStream_t stream = nullptr;
+  uint64_t budget = 8ull << 30;
+  int max_batch = 256;
+  int max_queue = 1 << 16;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Req*> queue;
+  std::unordered_map<uint64_t, Req*> reqs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::string fatal;  // scheduler error, reported by later calls
+  uint64_t iterations = 0, served = 0;
+
+  void loop();
+  zpl_status process(std::vector<Req*>& batch);
+};
+
+zpl_status Server::process(std::vector<Req*>& batch) {
+  zpl_ctx* c = eng;
+  hipStream_t s = stream;
+  const int nb = (int)batch.size();
+  // 1. datasets -> device (one concatenated buffer)
+  int64_t total = 0, max_n = 1;
+  for (Req* r : batch) {
+    total += (int64_t)r->x.size();
+    max_n = std::max<int64_t>(max_n, (int64_t)r->x.size());
+  }
+  const size_t pin_need = sizeof(int64_t) * (size_t)total + (sizeof(int64_t) * 2 + 64) * nb + 4096;
+  ZPL_TRY(ensure_pinned(c, pin_need));
+  HIP_TRY(hipStreamSynchronize(s));
+  char* pin = (char*)c->pin;
+  int64_t* px = (int64_t*)pin;
+  int64_t off = 0;
+  for (Req* r : batch) {
+    std::memcpy(px + off, r->x.data(), sizeof(int64_t) * r->x.size());
+    off += (int64_t)r->x.size();
+  }
+  ZPL_TRY(ensure(c, c->fit_x, sizeof(int64_t) * (size_t)std::max<int64_t>(total, 1)));
+  HIP_TRY(hipMemcpyAsync(c->fit_x.p, px, sizeof(int64_t) * (size_t)total, hipMemcpyHostToDevice, s));
+  int64_t* pptr = (int64_t*)(pin + sizeof(int64_t) * total);
+  int64_t* pns = pptr + nb;
+  off = 0;
+  for (int i = 0; i < nb; ++i) {
+    pptr[i] = (int64_t)(intptr_t)((int64_t*)c->fit_x.p + off);
+    pns[i] = (int64_t)batch[i]->x.size();
+    off += pns[i];
+  }
+  ZPL_TRY(ensure(c, c->fit_ptrs, sizeof(int64_t) * nb));
+  ZPL_TRY(ensure(c, c->fit_ns, sizeof(int64_t) * nb));
+  ZPL_TRY(ensure(c, c->fit_out, (sizeof(double) * 2 + sizeof(uint32_t) * 2) * nb));
+  ZPL_TRY(ensure(c, c->fit_st, sizeof(uint32_t) * nb));
+  HIP_TRY(hipMemcpyAsync(c->fit_ptrs.p, pptr, sizeof(int64_t) * nb, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->fit_ns.p, pns, sizeof(int64_t) * nb, hipMemcpyHostToDevice, s));
+  // 2. batched fit
+  const int grid = std::min(nb, c->n_cu * 2);
+  const int64_t stride = heavy_stride(max_n);
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)stride * grid));
+  double* fa = (double*)c->fit_out.p;
+  double* fd = fa + nb;
+  uint32_t* ff = (uint32_t*)(fd + nb);
+  HIP_TRY(launch_fit(grid, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, nb,
+                     c->ln, (int64_t*)c->heavy.p, stride, fa, fd, ff, (uint32_t*)c->fit_st.p, s));
+  double* ha = (double*)(pns + nb);
+  double* hd = ha + nb;
+  uint32_t* hf = (uint32_t*)(hd + nb);
+  uint32_t* hs = hf + nb;
+  HIP_TRY(hipMemcpyAsync(ha, fa, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hd, fd, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hf, ff, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hs, c->fit_st.p, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // 3. one batched simulation over every valid request's bootstrap cell
+  std::vector<zpl_cell> cells;
+  std::vector<int> owner;
+  std::vector<double> dobs;
+  for (int i = 0; i < nb; ++i) {
+    Req* r = batch[i];
+    r->ahat = ha[i];
+    r->D = hd[i];
+    r->flags = hf[i];
+    if (hs[i] != 0u) {
+      r->status = ZPL_EINVAL;
+      continue;
+    }
+    if (!(ha[i] >= kMinAlpha)) {
+      r->status = ZPL_ENOCONV;
+      continue;
+    }
+    cells.push_back(zpl_cell{ha[i], (int64_t)r->x.size(), r->B, r->seed, r->stream_id, 0});
+    owner.push_back(i);
+    dobs.push_back(hd[i]);
+  }
+  if (!cells.empty()) {
+    const int nc = (int)cells.size();
+    int64_t sumB = 0, maxB = 1;
+    for (const zpl_cell& z : cells) {
+      sumB += z.replicates;
+      maxB = std::max(maxB, z.replicates);
+    }
+    ZPL_TRY(ensure(c, c->boot_d, sizeof(double) * (size_t)sumB));
+    Outputs out{(double*)c->boot_d.p, nullptr, nullptr, nullptr, nullptr};
+    ZPL_TRY(run_cells(c, cells.data(), nc, nullptr, nullptr, 0, nullptr, out, nullptr, s));
+    // 4. counts of D_b >= D_obs per cell
+    ZPL_TRY(ensure(c, c->count, (sizeof(unsigned long long) + sizeof(double)) * nc));
+    unsigned long long* cnt = (unsigned long long*)c->count.p;
+    double* ddev = (double*)(cnt + nc);
+    HIP_TRY(hipStreamSynchronize(s));  // the plan upload used the staging area
+    double* pd = (double*)c->pin;
+    std::memcpy(pd, dobs.data(), sizeof(double) * nc);
+    HIP_TRY(hipMemcpyAsync(ddev, pd, sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fill_u32((uint32_t*)cnt, 2 * nc, 0u, s));
+    HIP_TRY(launch_count_cells((const double*)c->boot_d.p, (const DevCell*)c->cells.p, nc, ddev,
+                               cnt, maxB, s));
+    unsigned long long* hc = (unsigned long long*)(pd + nc);
+    HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(unsigned long long) * nc, hipMemcpyDeviceToHost, s));
+    ZPL_TRY(check_err_word(c, s));
+    for (int k = 0; k < nc; ++k) {
+      Req* r = batch[owner[k]];
+      r->p = (double)hc[k] / (double)r->B;
+      r->status = ZPL_OK;
+    }
+  }
+  return ZPL_OK;
+}
+
+void Server::loop() {
+  if (hipSetDevice(eng->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(mu);
+    fatal = "serving: could not create the scheduler stream";
+    stop = true;
+  }
+  for (;;) {
+    std::vector<Req*> batch;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || !queue.empty(); });
+      if (queue.empty() && stop) break;
+      size_t mem = 0;
+      while (!queue.empty() && (int)batch.size() < max_batch) {
+        Req* r = queue.front();
+        const size_t m = req_bytes(*r);
+        if (!batch.empty() && mem + m > budget) break;  // admitted next iteration
+        queue.pop_front();
+        if (m > budget) {
+          r->status = ZPL_ENOMEM;
+          r->done = true;
+          r->t_done = Clock::now();
+          continue;
+        }
+        batch.push_back(r);
+        mem += m;
+      }
+      if (!fatal.empty()) {
+        for (Req* r : batch) {
+          r->status = ZPL_EDEVICE;
+          r->done = true;
+          r->t_done = Clock::now();
+        }
+        cv.notify_all();
+        continue;
+      }
+    }
+    if (batch.empty()) continue;
+    const Clock::time_point t0 = Clock::now();
+    for (Req* r : batch) r->t_start = t0;
+    const zpl_status st = process(batch);
+    std::lock_guard<std::mutex> lk(mu);
+    const Clock::time_point t1 = Clock::now();
+    if (st != ZPL_OK) fatal = "serving: " + g_err;
+    for (Req* r : batch) {
+      if (st != ZPL_OK) r->status = st;
+      r->batch_size = (int32_t)batch.size();
+      r->t_done = t1;
+      r->done = true;
+    }
+    ++iterations;
+    served += batch.size();
+    cv.notify_all();
+  }
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -540,11 +782,12 @@ zpl_status zpl_create(zpl_ctx** out, int32_t device, uint64_t mem_budget_bytes) 
 
 void zpl_destroy(zpl_ctx* c) {
   if (!c) return;
+  if (c->server) (void)zpl_serve_stop(c);
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->graph_valid) (void)hipGraphExecDestroy(c->graph_exec);
   DevBuf* bufs[] = {&c->cells, &c->tables, &c->guides, &c->units, &c->hunits, &c->queues,
-                    &c->esc, &c->esc_cnt, &c->err, &c->list_v, &c->list_c, &c->heavy,
+                    &c->esc, &c->esc_cnt, &c->err, &c->list_v, &c->list_c, &c->wslots, &c->heavy, &c->gather,
                     &c->dbuf, &c->qnum, &c->qden, &c->qout, &c->fit_x, &c->fit_ptrs,
                     &c->fit_ns, &c->fit_out, &c->fit_st, &c->count, &c->boot_d};
   for (DevBuf* b : bufs)
@@ -641,6 +884,106 @@ zpl_status zpl_bootstrap_pvalue(zpl_ctx* c, const int64_t* x, int64_t n, int32_t
   return ZPL_OK;
 }
 
+zpl_status zpl_serve_start(zpl_ctx* c, const zpl_serve_opts* opts) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  if (c->server) return fail(ZPL_EINVAL, "serving already started on this context");
+  zpl_serve_opts o = {0, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.reserved != 0 || o.reserved2 != 0) return fail(ZPL_EINVAL, "opts.reserved must be 0");
+  Server* sv = new Server();
+  if (o.mem_budget_bytes) sv->budget = o.mem_budget_bytes;
+  if (o.max_batch > 0) sv->max_batch = o.max_batch;
+  if (o.max_queue > 0) sv->max_queue = o.max_queue;
+  zpl_status st = zpl_create(&sv->eng, c->device, c->budget);
+  if (st != ZPL_OK) {
+    delete sv;
+    return st;
+  }
+  sv->th = std::thread([sv] { sv->loop(); });
+  c->server = sv;
+  return ZPL_OK;
+}
+
+zpl_status zpl_serve_submit(zpl_ctx* c, const int64_t* x, int64_t n, int64_t B, uint64_t seed,
+                            uint32_t stream_id, uint64_t* ticket) {
+  g_err.clear();
+  if (!c || !x || !ticket) return fail(ZPL_EINVAL, "NULL argument");
+  Server* sv = c->server;
+  if (!sv) return fail(ZPL_EINVAL, "serving not started");
+  if (n < 1 || n > ((int64_t)1 << 31)) return fail(ZPL_EINVAL, "n must be in [1, 2^31]");
+  if (B < 1 || B > ((int64_t)1 << 32)) return fail(ZPL_EINVAL, "B must be in [1, 2^32]");
+  Req* r = new Req();
+  r->x.assign(x, x + n);
+  r->B = B;
+  r->seed = seed;
+  r->stream_id = stream_id;
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->fatal.empty()) {
+      delete r;
+      return fail(ZPL_EDEVICE, "%s", sv->fatal.c_str());
+    }
+    if ((int)sv->queue.size() >= sv->max_queue) {
+      delete r;
+      return fail(ZPL_EBUSY, "serving queue full (%d requests)", sv->max_queue);
+    }
+    r->ticket = sv->next_ticket++;
+    sv->reqs[r->ticket] = r;
+    sv->queue.push_back(r);
+  }
+  sv->cv.notify_all();
+  *ticket = r->ticket;
+  return ZPL_OK;
+}
+
+zpl_status zpl_serve_poll(zpl_ctx* c, uint64_t ticket, int32_t wait_ms, zpl_serve_result* res) {
+  g_err.clear();
+  if (!c || !res) return fail(ZPL_EINVAL, "NULL argument");
+  Server* sv = c->server;
+  if (!sv) return fail(ZPL_EINVAL, "serving not started");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(ZPL_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Req* r = it->second;
+  if (!r->done && wait_ms > 0)
+    sv->cv.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return r->done; });
+  std::memset(res, 0, sizeof *res);
+  res->done = r->done ? 1 : 0;
+  if (!r->done) return ZPL_OK;
+  res->status = r->status;
+  res->alpha_hat = r->ahat;
+  res->D = r->D;
+  res->p_value = r->p;
+  res->flags = r->flags;
+  res->batch_size = r->batch_size;
+  using ms = std::chrono::duration<double, std::milli>;
+  res->queue_ms = ms(r->t_start - r->t_submit).count();
+  res->latency_ms = ms(r->t_done - r->t_submit).count();
+  sv->reqs.erase(it);
+  delete r;
+  return ZPL_OK;
+}
+
+zpl_status zpl_serve_stop(zpl_ctx* c) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  Server* sv = c->server;
+  if (!sv) return ZPL_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->th.joinable()) sv->th.join();
+  for (auto& kv : sv->reqs) delete kv.second;
+  zpl_destroy(sv->eng);
+  delete sv;
+  c->server = nullptr;
+  return ZPL_OK;
+}
+
 zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
                             uint32_t stream_id, int64_t rep_lo, int64_t count,
                             int64_t* x_out, uint32_t* flags_out, void* stream) {
@@ -658,7 +1001,7 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
   ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
-  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * kG));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
   ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
@@ -684,7 +1027,7 @@ zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, double* T_out, void* stream) 
   ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
-  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * kG));
+  ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
   ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));

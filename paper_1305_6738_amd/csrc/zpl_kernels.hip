@@ -71,21 +71,41 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Inverse-CDF body search: x = min{k in 1..kH : T[k] >= U} (the ">=" rule of
-// the paper's sampler).  The guide table brackets the answer; a binary search
-// finishes it.  Entries k <= TL come from LDS, the rest from global memory.
+// Inverse-CDF sampling: x = min{k in 1..kH : T[k] >= U} (the ">=" rule of
+// the paper's sampler).  The guide brackets the answer in [g[b], g[b+1]];
+// most brackets are a single value or two, resolved with at most one table
+// probe ("fast path").  Wider brackets and U > T[kH] (the tail) are deferred
+// to a per-wave queue and resolved 64 at a time.
 // ---------------------------------------------------------------------------
-template <int TL>
-__device__ __forceinline__ int body_search(double U, const double* __restrict__ Ts,
-                                           const double* __restrict__ Tg,
-                                           const uint16_t* __restrict__ guide) {
-  const int j = (int)(U * (double)kG);
-  int lo = guide[j];
-  int hi = (j + 1 < kG) ? (int)guide[j + 1] : kH;
+__device__ __forceinline__ int guide_index(double U) {
+  if (U < 0.5) return (int)(U * (double)(2 * kGA));
+  const double e = 1.0 - U;  // exact: U in (1/2, 1)
+  const uint64_t b = (uint64_t)__double_as_longlong(e);
+  const int E = (int)(b >> 52);                                  // 970..1021
+  const int s = (int)((b >> (52 - kGBits)) & ((1u << kGBits) - 1));
+  return kGA + ((1021 - E) << kGBits) + (((1 << kGBits) - 1) - s);
+}
+
+// Packed guide entry: bracket low in bits 0..15, high in bits 16..31.
+// Returns the draw, or 0 when it must be deferred.
+__device__ __forceinline__ int fast_draw(double U, double tmax, const double* __restrict__ T,
+                                         const uint32_t* __restrict__ guide) {
+  if (U > tmax) return 0;
+  const uint32_t gg = guide[guide_index(U)];
+  const int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
+  if (hi == lo) return lo;
+  if (T[lo - 1] >= U) return lo;
+  return (hi == lo + 1) ? hi : 0;
+}
+
+// Full search of a deferred body draw.
+__device__ __forceinline__ int slow_search(double U, const double* __restrict__ T,
+                                           const uint32_t* __restrict__ guide) {
+  const uint32_t gg = guide[guide_index(U)];
+  int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    const double t = (mid <= TL) ? Ts[mid - 1] : Tg[mid - 1];
-    if (t >= U)
+    if (T[mid - 1] >= U)
       hi = mid;
     else
       lo = mid + 1;
@@ -93,20 +113,28 @@ __device__ __forceinline__ int body_search(double U, const double* __restrict__ 
   return lo;
 }
 
+// Deferred draw: its uniform, its index in the replicate (bit 31 = tail),
+// and the lane that owns the replicate (lane form).
+struct QEntry {
+  double U;
+  uint32_t i;
+  uint32_t owner;
+};
+constexpr uint32_t kTailBit = 0x80000000u;
+
 __device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k0,
                                               uint32_t k1, uint32_t i, uint32_t rep,
                                               uint32_t stream, uint32_t* flags) {
   return tail_draw(beta, gm, k0, k1, i, rep, stream, flags);
 }
 
-template <int TL>
-__device__ __forceinline__ int64_t draw_one(double U, uint32_t i, uint32_t rep,
-                                            const DevCell& c, const double* __restrict__ Ts,
-                                            const double* __restrict__ Tg,
-                                            const uint16_t* __restrict__ guide,
-                                            uint32_t& fl) {
-  if (U <= c.tmax) return (int64_t)body_search<TL>(U, Ts, Tg, guide);
-  return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, i, rep, c.stream, &fl);
+// Resolves a deferred draw.
+__device__ __forceinline__ int64_t resolve(const QEntry& e, uint32_t rep, const DevCell& c,
+                                           const double* __restrict__ T,
+                                           const uint32_t* __restrict__ guide, uint32_t& fl) {
+  if (e.i & kTailBit)
+    return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, e.i & ~kTailBit, rep, c.stream, &fl);
+  return (int64_t)slow_search(e.U, T, guide);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,16 +151,16 @@ __device__ __forceinline__ int64_t draw_one(double U, uint32_t i, uint32_t rep,
 template <class Src>
 __device__ __forceinline__ double ks_distance(Src& src, double a, const double (&suf)[17],
                                               int64_t n, const double* __restrict__ ln) {
-  const double z = suf[0], dn = (double)n;
+  const double iz = 1.0 / suf[0], idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0;
 #pragma unroll
   for (int v = 1; v <= 16; ++v) {
     const uint32_t c = src.small(v);
     if (c) {
-      const double t2 = fabs(suf[v - 1] / z - (double)(n - C) / dn);
+      const double t2 = fabs(fma(suf[v - 1], iz, -(double)(n - C) * idn));
       C += c;
-      const double t1 = fabs(suf[v] / z - (double)(n - C) / dn);
+      const double t1 = fabs(fma(suf[v], iz, -(double)(n - C) * idn));
       D = fmax(D, fmax(t1, t2));
     }
   }
@@ -142,10 +170,10 @@ __device__ __forceinline__ double ks_distance(Src& src, double a, const double (
   uint32_t c;
   while (src.next_large(v, c)) {
     const double zv1 = (v - 1 == vprev) ? zprev : survival_at(a, v, ln);
-    const double t2 = fabs(zv1 / z - (double)(n - C) / dn);
+    const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
     C += c;
     const double zv = survival_next(a, v, ln);
-    const double t1 = fabs(zv / z - (double)(n - C) / dn);
+    const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
     D = fmax(D, fmax(t1, t2));
     zprev = zv;
     vprev = v;
@@ -351,47 +379,135 @@ __device__ __forceinline__ int next_pow2(int v) {
 }
 
 // ---------------------------------------------------------------------------
-// Lane mode: one replicate per lane.
+// LDS of the simulation kernel: the cell's CDF table and packed guide, and one
+// region per wave (lane form or wave form).
 // ---------------------------------------------------------------------------
-__device__ void lane_replicate(const DevCell& c, int32_t cell_id, int64_t rep, bool active,
-                               uint32_t* __restrict__ hist, int64_t* __restrict__ ov,
-                               int lane, const double* __restrict__ Ts,
-                               const double* __restrict__ Tg,
-                               const uint16_t* __restrict__ guide,
-                               const double* __restrict__ ln, const Outputs& out,
-                               uint64_t* esc_list, uint32_t* esc_count, uint32_t esc_cap,
-                               uint32_t* err) {
-  if (!active) return;
-  uint32_t* h = hist + lane;
-  int64_t* o = ov + lane;
+struct LaneRegion {
+  uint32_t hist[kHLB / 2 * 64];  // dword b of lane l at hist[b * 64 + l]
+  int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
+  QEntry q[kQCap];
+  uint32_t ovc[64];  // overflow count per lane (may exceed kCL)
+  uint32_t fl[64];   // flags per lane
+  uint32_t qn;
+};
+
+struct WaveRegion {
+  uint32_t hist[kHW];
+  int64_t ov[kCW];
+  QEntry q[kQCap];
+  uint32_t ovc;
+  uint32_t qn;
+};
+
+union WaveLds {
+  LaneRegion lane;
+  WaveRegion wave;
+};
+
+struct SimLds {
+  double T[kH];
+  uint32_t guide[kGuide];
+  WaveLds w[kWaves];
+  int unit;
+};
+
+// Stages the cell's table and packed guide (g[b] | g[b+1] << 16) into LDS.
+__device__ __forceinline__ void load_cell_tables(double* T, uint32_t* guide,
+                                                 const double* __restrict__ Tg,
+                                                 const uint16_t* __restrict__ g, int tid,
+                                                 int nthreads) {
+  for (int k = tid; k < kH; k += nthreads) T[k] = Tg[k];
+  for (int b = tid; b < kGuide; b += nthreads)
+    guide[b] = (uint32_t)g[b] | ((uint32_t)g[b + 1] << 16);
+}
+
+// Moves queue entries [m, qn) to the front after lanes resolved [0, m).
+template <class Region>
+__device__ __forceinline__ void queue_compact(Region* L, int m, int lane) {
+  const int rem = (int)L->qn - m;
+  const bool ha = lane < rem, hb = lane + 64 < rem;
+  QEntry a = {0.0, 0u, 0u}, b = {0.0, 0u, 0u};
+  if (ha) a = L->q[m + lane];
+  if (hb) b = L->q[m + 64 + lane];
+  wave_sync();
+  if (ha) L->q[lane] = a;
+  if (hb) L->q[64 + lane] = b;
+  if (lane == 0) L->qn = (uint32_t)rem;
+  wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Lane form: one replicate per lane.  Fast-path draws go straight into the
+// lane's histogram column; deferred draws from all lanes are resolved 64 at a
+// time by whichever lane picks them up, into the owner's column.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lane_insert(LaneRegion* L, int owner, int64_t x) {
+  if (x <= kHLB) {
+    const int v = (int)x - 1;
+    atomicAdd(&L->hist[(v >> 1) * 64 + owner], 1u << ((v & 1) * 16));
+  } else {
+    const uint32_t p = atomicAdd(&L->ovc[owner], 1u);
+    if (p < (uint32_t)kCL) L->ov[p * 64 + owner] = x;
+  }
+}
+
+__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, int64_t rep0,
+                                           const DevCell& c, const double* __restrict__ T,
+                                           const uint32_t* __restrict__ guide, int lane) {
+  if (lane < m) {
+    const QEntry e = L->q[lane];
+    uint32_t fl = 0;
+    const int64_t x = resolve(e, (uint32_t)(rep0 + e.owner), c, T, guide, fl);
+    if (fl) atomicOr(&L->fl[e.owner], fl);
+    lane_insert(L, (int)e.owner, x);
+  }
+  wave_sync();
+  queue_compact(L, m, lane);
+}
+
+__device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int64_t rep0,
+                                          int count, LaneRegion* L, int lane,
+                                          const double* __restrict__ T,
+                                          const uint32_t* __restrict__ guide,
+                                          const double* __restrict__ ln, const Outputs& out,
+                                          uint64_t* esc_list, uint32_t* esc_count,
+                                          uint32_t esc_cap, uint32_t* err) {
+  const bool active = lane < count;
 #pragma unroll
-  for (int b = 0; b < kHLB / 2; ++b) h[b * 64] = 0u;
-  int oc = 0;
-  bool esc = false;
-  uint32_t fl = 0;
+  for (int b = 0; b < kHLB / 2; ++b) L->hist[b * 64 + lane] = 0u;
+  L->ovc[lane] = 0u;
+  L->fl[lane] = 0u;
+  if (lane == 0) L->qn = 0u;
+  wave_sync();
   const int64_t n = c.n;
-  const uint32_t r = (uint32_t)rep;
+  const uint32_t r = (uint32_t)(rep0 + lane);
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   for (uint32_t j = 0; j < nblk; ++j) {
-    const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
+    if (active) {
+      const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      const uint32_t i = 2u * j + (uint32_t)half;
-      if (half == 1 && (int64_t)i >= n) break;
-      const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-      const int64_t x = draw_one<kTL>(U, i, r, c, Ts, Tg, guide, fl);
-      if (x <= kHLB) {
-        const int v = (int)x - 1;
-        atomicAdd(&h[(v >> 1) * 64], 1u << ((v & 1) * 16));
-      } else if (oc < kCL) {
-        o[oc * 64] = x;
-        ++oc;
-      } else {
-        esc = true;
+      for (int half = 0; half < 2; ++half) {
+        const uint32_t i = 2u * j + (uint32_t)half;
+        if (half == 1 && (int64_t)i >= n) break;
+        const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
+        const int x = fast_draw(U, c.tmax, T, guide);
+        if (x) {
+          lane_insert(L, lane, x);
+        } else {
+          const uint32_t slot = atomicAdd(&L->qn, 1u);
+          L->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, (uint32_t)lane};
+        }
       }
     }
+    wave_sync();
+    if (L->qn >= 64u) lane_drain(L, 64, rep0, c, T, guide, lane);
   }
-  if (esc) {
+  for (int m = (int)L->qn; m > 0; m = (int)L->qn)
+    lane_drain(L, m < 64 ? m : 64, rep0, c, T, guide, lane);
+  if (!active) return;
+  const int oc = (int)L->ovc[lane];
+  const uint32_t fl = L->fl[lane];
+  if (oc > kCL) {
     const uint32_t slot = atomicAdd(esc_count, 1u);
     if (slot < esc_cap)
       esc_list[slot] = ((uint64_t)(uint32_t)cell_id << 32) | r;
@@ -399,6 +515,8 @@ __device__ void lane_replicate(const DevCell& c, int32_t cell_id, int64_t rep, b
       atomicOr(err, kErrEscOverflow);
     return;
   }
+  uint32_t* h = L->hist + lane;
+  int64_t* o = L->ov + lane;
   // insertion sort of the (at most kCL) overflow values
   for (int p = 1; p < oc; ++p) {
     const int64_t v = o[p * 64];
@@ -413,10 +531,10 @@ __device__ void lane_replicate(const DevCell& c, int32_t cell_id, int64_t rep, b
   uint64_t fp = 0;
   int64_t xmax = 0;
   for (int b = 0; b < kHLB / 2; ++b) {
-    const uint32_t w = h[b * 64];
+    const uint32_t wv = h[b * 64];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      const uint32_t k = half ? (w >> 16) : (w & 0xffffu);
+      const uint32_t k = half ? (wv >> 16) : (wv & 0xffffu);
       const int64_t v = 2 * b + half + 1;
       if (k) {
         u128_add_mul(S, k, ln_fixed(v, ln));
@@ -435,11 +553,11 @@ __device__ void lane_replicate(const DevCell& c, int32_t cell_id, int64_t rep, b
   double a, D;
   uint32_t flags;
   finish_replicate(src, S, n, fl, ln, a, D, flags);
-  write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
+  write_outputs(out, c.out_off + rep0 + lane, D, a, flags, fp, xmax);
 }
 
 // ---------------------------------------------------------------------------
-// Wave mode: one wave draws one replicate at a time into an LDS histogram;
+// Wave form: one wave draws one replicate at a time into an LDS histogram;
 // finishes are deferred and run one replicate per lane.
 // ---------------------------------------------------------------------------
 struct WaveSlot {
@@ -449,24 +567,39 @@ struct WaveSlot {
   uint32_t off, len, flags, esc;
 };
 
-struct WaveLds {
-  uint32_t hist[kHW];
-  int64_t ov[kCW];
-  WaveSlot slot[64];
-  uint32_t ovc;
-};
-
 struct WaveSync {
   __device__ void operator()() const { wave_sync(); }
 };
 
-__device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nrep,
-                           WaveLds* __restrict__ L, int64_t* __restrict__ lv,
-                           uint32_t* __restrict__ lc, int lane,
-                           const double* __restrict__ Ts, const double* __restrict__ Tg,
-                           const uint16_t* __restrict__ guide, const double* __restrict__ ln,
-                           const Outputs& out, uint64_t* esc_list, uint32_t* esc_count,
-                           uint32_t esc_cap, uint32_t* err) {
+__device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
+  if (x <= kHW) {
+    atomicAdd(&L->hist[x - 1], 1u);
+  } else {
+    const uint32_t p = atomicAdd(&L->ovc, 1u);
+    if (p < (uint32_t)kCW) L->ov[p] = x;
+  }
+}
+
+__device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t rep, const DevCell& c,
+                                           const double* __restrict__ T,
+                                           const uint32_t* __restrict__ guide, uint32_t& fl,
+                                           int lane) {
+  if (lane < m) {
+    const QEntry e = L->q[lane];
+    wave_insert(L, resolve(e, rep, c, T, guide, fl));
+  }
+  wave_sync();
+  queue_compact(L, m, lane);
+}
+
+__device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0,
+                                           int nrep, WaveRegion* L, WaveSlot* slots,
+                                           int64_t* __restrict__ lv, uint32_t* __restrict__ lc,
+                                           int lane, const double* __restrict__ T,
+                                           const uint32_t* __restrict__ guide,
+                                           const double* __restrict__ ln, const Outputs& out,
+                                           uint64_t* esc_list, uint32_t* esc_count,
+                                           uint32_t esc_cap, uint32_t* err) {
   const int64_t n = c.n;
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   int done = 0;
@@ -477,27 +610,37 @@ __device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nr
     while (done + q < nrep && q < 64 && used + (uint32_t)(kHW + kCW) <= (uint32_t)kListCap) {
       const uint32_t r = (uint32_t)(r0 + done + q);
       for (int k = lane; k < kHW; k += 64) L->hist[k] = 0u;
-      if (lane == 0) L->ovc = 0u;
+      if (lane == 0) {
+        L->ovc = 0u;
+        L->qn = 0u;
+      }
       wave_sync();
       uint32_t c1 = 0, fl = 0;
-      for (uint32_t j = (uint32_t)lane; j < nblk; j += 64u) {
-        const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
+      for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
+        const uint32_t j = j0 + (uint32_t)lane;
+        if (j < nblk) {
+          const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const uint32_t i = 2u * j + (uint32_t)half;
-          if (half == 1 && (int64_t)i >= n) break;
-          const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-          const int64_t x = draw_one<kTL>(U, i, r, c, Ts, Tg, guide, fl);
-          if (x == 1) {
-            ++c1;
-          } else if (x <= kHW) {
-            atomicAdd(&L->hist[x - 1], 1u);
-          } else {
-            const uint32_t idx = atomicAdd(&L->ovc, 1u);
-            if (idx < (uint32_t)kCW) L->ov[idx] = x;
+          for (int half = 0; half < 2; ++half) {
+            const uint32_t i = 2u * j + (uint32_t)half;
+            if (half == 1 && (int64_t)i >= n) break;
+            const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
+            const int x = fast_draw(U, c.tmax, T, guide);
+            if (x == 1) {
+              ++c1;
+            } else if (x) {
+              wave_insert(L, x);
+            } else {
+              const uint32_t slot = atomicAdd(&L->qn, 1u);
+              L->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u};
+            }
           }
         }
+        wave_sync();
+        if (L->qn >= 64u) wave_drain(L, 64, r, c, T, guide, fl, lane);
       }
+      for (int m = (int)L->qn; m > 0; m = (int)L->qn)
+        wave_drain(L, m < 64 ? m : 64, r, c, T, guide, fl, lane);
       c1 = wave_sum_u32(c1);
       fl = wave_or_u32(fl);
       if (lane == 0) L->hist[0] += c1;
@@ -510,7 +653,7 @@ __device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nr
             esc_list[slot] = ((uint64_t)(uint32_t)cell_id << 32) | r;
           else
             atomicOr(err, kErrEscOverflow);
-          L->slot[q].esc = 1u;
+          slots[q].esc = 1u;
         }
         wave_sync();
         ++q;
@@ -525,7 +668,7 @@ __device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nr
       const Summary s = build_list(L->hist, kHW, L->ov, (int)oc, lv + used, lc + used, lane,
                                    ln, WaveSync{});
       if (lane == 0) {
-        WaveSlot& sl = L->slot[q];
+        WaveSlot sl;
         sl.S = s.S;
         sl.fp = s.fp;
         sl.xmax = s.xmax;
@@ -533,14 +676,17 @@ __device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nr
         sl.len = (uint32_t)s.len;
         sl.flags = fl;
         sl.esc = 0u;
+        slots[q] = sl;
       }
       used += (uint32_t)s.len;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       wave_sync();
       ++q;
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // deferred finishes, one replicate per lane
     if (lane < q) {
-      const WaveSlot sl = L->slot[lane];
+      const WaveSlot sl = slots[lane];
       if (!sl.esc) {
         ListSrc src{lv + sl.off, lc + sl.off, (int)sl.len, 0};
         double a, D;
@@ -549,196 +695,216 @@ __device__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0, int nr
         write_outputs(out, c.out_off + r0 + done + lane, D, a, flags, sl.fp, sl.xmax);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     wave_sync();
     done += q;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Persistent simulation kernel: workgroups pull units (a cell and up to 256
-// replicates) from a global queue; the cell's table prefix and guide are
-// staged in LDS when the cell changes.  Lane-mode units give one replicate to
-// each lane; wave-mode units give 64 replicates to each wave.
+// Persistent simulation kernel: workgroups pull units (a cell and up to 512
+// replicates) from a global queue; the cell's table and guide are staged in
+// LDS when the cell changes.  Lane-form units give one replicate to each
+// lane; wave-form units give 64 replicates to each wave.
 // ---------------------------------------------------------------------------
-union WaveRegion {
-  struct {
-    uint32_t hist[kHLB / 2 * 64];
-    int64_t ov[kCL * 64];
-  } lane;
-  WaveLds wave;
-};
-
-__global__ __launch_bounds__(kBlock, 2) void k_simulate(
+__global__ __launch_bounds__(kBlock, 1) void k_simulate(
     const DevCell* __restrict__ cells, const double* __restrict__ tables,
     const uint16_t* __restrict__ guides, const double* __restrict__ ln,
     const Unit* __restrict__ units, int n_units, uint32_t* queue, Outputs out,
     uint64_t* esc_list, uint32_t* esc_count, uint32_t esc_cap, int64_t* list_v,
-    uint32_t* list_c, uint32_t* err) {
-  __shared__ double s_T[kTL];
-  __shared__ uint16_t s_guide[kG];
-  __shared__ WaveRegion s_wave[kWaves];
-  __shared__ int s_unit;
-
+    uint32_t* list_c, WaveSlot* wslots, uint32_t* err) {
+  __shared__ SimLds L;
   const int tid = (int)threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const int64_t gwave = (int64_t)blockIdx.x * kWaves + wave;
   int64_t* lv = list_v + gwave * kListCap;
   uint32_t* lc = list_c + gwave * kListCap;
+  WaveSlot* slots = wslots + gwave * 64;
   int loaded = -1;
 
   for (;;) {
-    if (tid == 0) s_unit = (int)atomicAdd(queue, 1u);
+    if (tid == 0) L.unit = (int)atomicAdd(queue, 1u);
     __syncthreads();
-    const int u = s_unit;
+    const int u = L.unit;
     if (u >= n_units) break;
     const Unit un = units[u];
     const DevCell c = cells[un.cell];
-    const double* Tg = tables + (size_t)un.cell * kH;
     if (un.cell != loaded) {
-      const uint16_t* g = guides + (size_t)un.cell * kG;
-      for (int k = tid; k < kTL; k += kBlock) s_T[k] = Tg[k];
-      for (int k = tid; k < kG; k += kBlock) s_guide[k] = g[k];
+      load_cell_tables(L.T, L.guide, tables + (size_t)un.cell * kH,
+                       guides + (size_t)un.cell * (kGuide + 1), tid, kBlock);
       loaded = un.cell;
       __syncthreads();
     }
     const int first = wave * 64;
-    if (c.mode == kModeLane) {
-      const int idx = first + lane;
-      lane_replicate(c, un.cell, un.r0 + idx, idx < un.count, s_wave[wave].lane.hist,
-                     s_wave[wave].lane.ov, lane, s_T, Tg, s_guide, ln, out, esc_list,
-                     esc_count, esc_cap, err);
-    } else if (first < un.count) {
+    if (first < un.count) {
       const int nrep = (un.count - first) < 64 ? (un.count - first) : 64;
-      wave_batch(c, un.cell, un.r0 + first, nrep, &s_wave[wave].wave, lv, lc, lane, s_T, Tg,
-                 s_guide, ln, out, esc_list, esc_count, esc_cap, err);
+      if (c.mode == kModeLane)
+        lane_wave(c, un.cell, un.r0 + first, nrep, &L.w[wave].lane, lane, L.T, L.guide, ln, out,
+                  esc_list, esc_count, esc_cap, err);
+      else
+        wave_batch(c, un.cell, un.r0 + first, nrep, &L.w[wave].wave, slots, lv, lc, lane, L.T,
+                   L.guide, ln, out, esc_list, esc_count, esc_cap, err);
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Heavy form: one wave per workgroup, the whole table in LDS, values above
-// kHeavyHist in per-wave global scratch (sorted there).  Runs the planned
-// heavy units, then every replicate that overflowed the lane or wave form.
+// Heavy form: 4 waves per workgroup share the table and guide; each wave
+// draws one replicate at a time, keeps values above kHeavyHist in its global
+// scratch and sorts them there.  Runs the planned heavy units, then every
+// replicate that overflowed the lane or wave form.
 // ---------------------------------------------------------------------------
-struct BlockSync {
-  __device__ void operator()() const { __syncthreads(); }
+struct HeavyWave {
+  uint32_t hist[kHeavyHist];
+  QEntry q[kQCap];
+  uint32_t ovc;
+  uint32_t qn;
 };
 
 struct HeavyLds {
   double T[kH];
-  uint16_t guide[kG];
-  uint32_t hist[kHeavyHist];
-  uint32_t ovc;
+  uint32_t guide[kGuide];
+  HeavyWave w[kHeavyWaves];
   int item;
 };
 
-// Draw source for the heavy form: the Philox stream of (cell, replicate).
-struct DrawGen {
-  const DevCell* c;
-  const HeavyLds* L;
-  uint32_t rep;
-  __device__ __forceinline__ int64_t operator()(uint32_t i, const Words4& w, int half,
-                                               uint32_t& fl) const {
-    const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-    return draw_one<kH>(U, i, rep, *c, L->T, L->T, L->guide, fl);
-  }
+// Ordering of one wave's global-memory stores before its later loads.
+__device__ __forceinline__ void wave_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct GlobalSync {
+  __device__ void operator()() const { wave_sync_global(); }
 };
 
 // Histogram/overflow fill, sort, compact list and finish of one replicate by
-// one wave (blockDim == 64).  `values(i)` gives draw i.
+// one wave.  fill(sink, flags) calls sink(x) for every value.
 template <class Fill>
-__device__ void heavy_core(HeavyLds* L, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
-                           uint32_t* lc, const double* __restrict__ ln, uint32_t fl_in,
-                           double& a, double& D, uint32_t& flags, uint64_t& fp,
-                           int64_t& xmax, bool& ok) {
+__device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
+                           uint32_t* lc, const double* __restrict__ ln, double& a, double& D,
+                           uint32_t& flags, uint64_t& fp, int64_t& xmax, bool& ok) {
   const int lane = lane_id();
-  for (int k = lane; k < kHeavyHist; k += 64) L->hist[k] = 0u;
-  if (lane == 0) L->ovc = 0u;
-  __syncthreads();
-  uint32_t c1 = 0, fl = fl_in;
+  for (int k = lane; k < kHeavyHist; k += 64) W->hist[k] = 0u;
+  if (lane == 0) {
+    W->ovc = 0u;
+    W->qn = 0u;
+  }
+  wave_sync_global();
+  uint32_t c1 = 0, fl = 0;
   bool bad = false;
-  fill([&](int64_t x) {
+  auto sink = [&](int64_t x) {
     if (x < 1) {
       bad = true;
     } else if (x == 1) {
       ++c1;
     } else if (x <= kHeavyHist) {
-      atomicAdd(&L->hist[x - 1], 1u);
+      atomicAdd(&W->hist[x - 1], 1u);
     } else {
-      const uint32_t idx = atomicAdd(&L->ovc, 1u);
+      const uint32_t idx = atomicAdd(&W->ovc, 1u);
       gov[idx] = x;
     }
-  }, fl);
+  };
+  fill(sink, fl);
   c1 = wave_sum_u32(c1);
   fl = wave_or_u32(fl);
   const uint32_t anybad = wave_or_u32(bad ? 1u : 0u);
-  if (lane == 0) L->hist[0] += c1;
-  __syncthreads();
+  if (lane == 0) W->hist[0] += c1;
+  wave_sync_global();
   ok = (anybad == 0u);
   if (!ok) return;
-  const int oc = (int)L->ovc;
+  const int oc = (int)W->ovc;
   if (oc > 1) {
     const int P = next_pow2(oc);
     for (int k = oc + lane; k < P; k += 64) gov[k] = INT64_MAX;
-    __syncthreads();
-    wave_bitonic(gov, P, lane, BlockSync{});
+    wave_sync_global();
+    wave_bitonic(gov, P, lane, GlobalSync{});
   }
-  const Summary s = build_list(L->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, BlockSync{});
-  __syncthreads();
-  ListSrc src{lv, lc, s.len, 0};
-  finish_replicate(src, s.S, n, fl, ln, a, D, flags);
+  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, GlobalSync{});
+  wave_sync_global();
+  if (lane == 0) {
+    ListSrc src{lv, lc, s.len, 0};
+    finish_replicate(src, s.S, n, fl, ln, a, D, flags);
+  }
   fp = s.fp;
   xmax = s.xmax;
 }
 
-__device__ void heavy_load_table(HeavyLds* L, const double* T, const uint16_t* g) {
-  for (int k = lane_id(); k < kH; k += 64) L->T[k] = T[k];
-  for (int k = lane_id(); k < kG; k += 64) L->guide[k] = g[k];
-  __syncthreads();
-}
-
-__device__ void heavy_replicate(HeavyLds* L, const DevCell& c, uint32_t rep, int64_t* gov,
-                                int64_t* lv, uint32_t* lc, const double* __restrict__ ln,
-                                const Outputs& out) {
+__device__ void heavy_replicate(HeavyWave* W, const double* __restrict__ T,
+                                const uint32_t* __restrict__ guide, const DevCell& c,
+                                uint32_t rep, int64_t* gov, int64_t* lv, uint32_t* lc,
+                                const double* __restrict__ ln, const Outputs& out) {
   const int lane = lane_id();
   const int64_t n = c.n;
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
-  DrawGen gen{&c, L, rep};
   auto fill = [&](auto sink, uint32_t& fl) {
-    for (uint32_t j = (uint32_t)lane; j < nblk; j += 64u) {
-      const Words4 w = philox4x32_10(j, rep, c.stream, 0u, c.k0, c.k1);
-      sink(gen(2u * j, w, 0, fl));
-      if ((int64_t)(2u * j + 1u) < n) sink(gen(2u * j + 1u, w, 1, fl));
+    for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
+      const uint32_t j = j0 + (uint32_t)lane;
+      if (j < nblk) {
+        const Words4 w = philox4x32_10(j, rep, c.stream, 0u, c.k0, c.k1);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const uint32_t i = 2u * j + (uint32_t)half;
+          if (half == 1 && (int64_t)i >= n) break;
+          const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
+          const int x = fast_draw(U, c.tmax, T, guide);
+          if (x) {
+            sink(x);
+          } else {
+            const uint32_t slot = atomicAdd(&W->qn, 1u);
+            W->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u};
+          }
+        }
+      }
+      wave_sync();
+      while (W->qn >= 64u) {
+        const QEntry e = W->q[lane];
+        sink(resolve(e, rep, c, T, guide, fl));
+        wave_sync();
+        queue_compact(W, 64, lane);
+      }
+    }
+    for (int m = (int)W->qn; m > 0; m = (int)W->qn) {
+      if (lane < m) {
+        const QEntry e = W->q[lane];
+        sink(resolve(e, rep, c, T, guide, fl));
+      }
+      wave_sync();
+      queue_compact(W, m, lane);
     }
   };
-  double a, D;
-  uint32_t flags;
+  double a = 0.0, D = 0.0;
+  uint32_t flags = 0;
   uint64_t fp;
   int64_t xmax;
   bool ok;
-  heavy_core(L, n, fill, gov, lv, lc, ln, 0u, a, D, flags, fp, xmax, ok);
+  heavy_core(W, n, fill, gov, lv, lc, ln, a, D, flags, fp, xmax, ok);
   if (lane == 0) write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
-  __syncthreads();
+  wave_sync_global();
 }
 
-__global__ __launch_bounds__(64) void k_heavy(
+__global__ __launch_bounds__(64 * kHeavyWaves) void k_heavy(
     const DevCell* __restrict__ cells, const double* __restrict__ tables,
     const uint16_t* __restrict__ guides, const double* __restrict__ ln,
     const Unit* __restrict__ units, int n_units, const uint64_t* __restrict__ esc_list,
     const uint32_t* __restrict__ esc_count, uint32_t esc_cap, uint32_t* queues,
     Outputs out, int64_t* scratch, int64_t scratch_stride) {
   __shared__ HeavyLds L;
-  int64_t* gov = scratch + (int64_t)blockIdx.x * scratch_stride;
+  const int tid = (int)threadIdx.x;
+  const int wave = tid >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * kHeavyWaves + wave;
+  int64_t* gov = scratch + gw * scratch_stride;
   // list area after the overflow area: values then counts
   const int64_t half = scratch_stride / 2;
   int64_t* lv = gov + half;
   uint32_t* lc = reinterpret_cast<uint32_t*>(lv + half / 2);
   int loaded = -1;
-  // planned heavy units
+  // planned heavy units: each wave takes every 4th replicate of the unit
   for (;;) {
-    if (threadIdx.x == 0) L.item = (int)atomicAdd(&queues[0], 1u);
+    if (tid == 0) L.item = (int)atomicAdd(&queues[0], 1u);
     __syncthreads();
     const int u = L.item;
     __syncthreads();
@@ -746,16 +912,19 @@ __global__ __launch_bounds__(64) void k_heavy(
     const Unit un = units[u];
     const DevCell c = cells[un.cell];
     if (un.cell != loaded) {
-      heavy_load_table(&L, tables + (size_t)un.cell * kH, guides + (size_t)un.cell * kG);
+      load_cell_tables(L.T, L.guide, tables + (size_t)un.cell * kH,
+                       guides + (size_t)un.cell * (kGuide + 1), tid, 64 * kHeavyWaves);
       loaded = un.cell;
+      __syncthreads();
     }
-    for (int k = 0; k < un.count; ++k)
-      heavy_replicate(&L, c, (uint32_t)(un.r0 + k), gov, lv, lc, ln, out);
+    for (int k = wave; k < un.count; k += kHeavyWaves)
+      heavy_replicate(&L.w[wave], L.T, L.guide, c, (uint32_t)(un.r0 + k), gov, lv, lc, ln, out);
+    __syncthreads();
   }
-  // replicates that overflowed the lane or wave form
+  // replicates that overflowed the lane or wave form (wave 0 of each group)
   const uint32_t ne = *esc_count < esc_cap ? *esc_count : esc_cap;
   for (;;) {
-    if (threadIdx.x == 0) L.item = (int)atomicAdd(&queues[1], 1u);
+    if (tid == 0) L.item = (int)atomicAdd(&queues[1], 1u);
     __syncthreads();
     const uint32_t e = (uint32_t)L.item;
     __syncthreads();
@@ -765,10 +934,13 @@ __global__ __launch_bounds__(64) void k_heavy(
     const uint32_t rep = (uint32_t)code;
     const DevCell c = cells[cell];
     if (cell != loaded) {
-      heavy_load_table(&L, tables + (size_t)cell * kH, guides + (size_t)cell * kG);
+      load_cell_tables(L.T, L.guide, tables + (size_t)cell * kH,
+                       guides + (size_t)cell * (kGuide + 1), tid, 64 * kHeavyWaves);
       loaded = cell;
+      __syncthreads();
     }
-    heavy_replicate(&L, c, rep, gov, lv, lc, ln, out);
+    if (wave == 0) heavy_replicate(&L.w[0], L.T, L.guide, c, rep, gov, lv, lc, ln, out);
+    __syncthreads();
   }
 }
 
@@ -783,7 +955,7 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
                                            int64_t scratch_stride, double* ahat_out,
                                            double* D_out, uint32_t* flags_out,
                                            uint32_t* status_out) {
-  __shared__ HeavyLds L;
+  __shared__ HeavyWave W;
   int64_t* gov = scratch + (int64_t)blockIdx.x * scratch_stride;
   const int64_t half = scratch_stride / 2;
   int64_t* lv = gov + half;
@@ -800,14 +972,14 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
     uint64_t fp;
     int64_t xmax;
     bool ok;
-    heavy_core(&L, n, fill, gov, lv, lc, ln, 0u, a, D, flags, fp, xmax, ok);
+    heavy_core(&W, n, fill, gov, lv, lc, ln, a, D, flags, fp, xmax, ok);
     if (lane == 0) {
       ahat_out[set] = a;
       D_out[set] = D;
       flags_out[set] = flags;
       status_out[set] = ok ? 0u : kErrBadValue;
     }
-    __syncthreads();
+    wave_sync_global();
   }
 }
 
@@ -832,24 +1004,45 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
   tables[(size_t)cell * kH + (k - 1)] = 1.0 - zk / suf[0];
 }
 
+// Guide entry b: the smallest k that a uniform in bin b can map to.  Bins
+// b < kGA hold U in [b/(2 kGA), (b+1)/(2 kGA)); the others hold U with
+// e = 1 - U in one (octave, sub-bin) cell, i.e. U in (1 - e_hi, 1 - e_lo].
+// Entry kGuide is the sentinel kH.
 __global__ __launch_bounds__(256) void k_guide(DevCell* __restrict__ cells,
                                               const double* __restrict__ tables,
                                               uint16_t* __restrict__ guides) {
   const int cell = (int)blockIdx.y;
-  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (j >= kG) return;
+  const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b > kGuide) return;
   const double* T = tables + (size_t)cell * kH;
-  const double target = (double)j / (double)kG;
-  int lo = 0, hi = kH;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (T[mid] >= target)
-      hi = mid;
-    else
-      lo = mid + 1;
+  int g = kH;
+  if (b < kGuide) {
+    // first index with T >= target (part A) or T > target (part B)
+    double target;
+    bool strict;
+    if (b < kGA) {
+      target = (double)b / (double)(2 * kGA);
+      strict = false;
+    } else {
+      const int o = (b - kGA) >> kGBits;
+      const int s = ((1 << kGBits) - 1) - ((b - kGA) & ((1 << kGBits) - 1));
+      const double e_hi = ldexp(1.0 + (double)(s + 1) / (double)(1 << kGBits), -(o + 2));
+      target = 1.0 - e_hi;
+      strict = true;
+    }
+    int lo = 0, hi = kH;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const bool ok = strict ? (T[mid] > target) : (T[mid] >= target);
+      if (ok)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    g = lo < kH ? lo + 1 : kH;
   }
-  guides[(size_t)cell * kG + j] = (uint16_t)(lo < kH ? lo + 1 : kH);
-  if (j == 0) {
+  guides[(size_t)cell * (kGuide + 1) + b] = (uint16_t)g;
+  if (b == 0) {
     DevCell& c = cells[cell];
     c.tmax = T[kH - 1];
     c.beta = c.alpha - 1.0;
@@ -870,67 +1063,206 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Order statistics per cell: the element of rank floor(R num/den) in the
-// ascending D values (the annex's index rule), by radix selection on the
-// FP64 bit patterns (D >= 0, so bit order is numeric order).  One workgroup
-// per (cell, quantile).
+// Order statistics per cell: the element of rank k = floor(R num/den) in the
+// ascending D values (the annex's index rule).  D >= 0, so comparing the FP64
+// bit patterns as unsigned integers orders the values.  One workgroup of
+// 1024 threads per cell, up to kSelQ quantiles at a time:
+//   1. a sample of kSelSample values at fixed positions is sorted in LDS;
+//   2. each quantile takes the sample values 5 standard deviations of the
+//      sample rank around its expected position as a bracket [lo, hi];
+//   3. one pass over D counts the values below each bracket and gathers the
+//      values inside it into global scratch;
+//   4. the rank k - below is selected exactly among the gathered values by
+//      radix selection (11-bit digits).
+// If rank k falls outside its bracket, or the bracket overflows its scratch,
+// the radix selection runs over all of D instead.  Both give the same element.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_select(const double* __restrict__ D,
-                                               const DevCell* __restrict__ cells, int n_q,
-                                               const uint32_t* __restrict__ qnum,
-                                               const uint32_t* __restrict__ qden,
-                                               double* __restrict__ qout) {
-  __shared__ uint32_t hist[2048];
-  __shared__ uint32_t part[256];
-  __shared__ uint64_t s_prefix, s_mask;
-  __shared__ int64_t s_k;
-  const int cell = (int)blockIdx.x / n_q;
-  const int qi = (int)blockIdx.x % n_q;
+constexpr int kSelSample = 2048;
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Ascending bitonic sort of a[0..P) (P a power of two) by the whole block.
+__device__ void block_bitonic_u64(uint64_t* a, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = (int)threadIdx.x; i < P; i += (int)blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = a[i], y = a[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+struct SelLds {
+  union {
+    uint64_t sample[kSelSample];
+    uint32_t hist[2048];
+  } u;
+  uint64_t lo[kSelQ], hi[kSelQ];
+  unsigned long long below[kSelQ];
+  uint32_t nb[kSelQ];
+  uint64_t prefix, mask;
+  int64_t krem;
+};
+
+// Exact radix selection (11-bit digits) of rank k of bits[0..R), block-wide.
+// All values share the bits above `top` (the caller's bracket), which are
+// given in `common`; digits of 11 bits run from bit `top` down to bit 0.
+__device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, int64_t R,
+                                 int64_t k, int top, uint64_t common) {
+  const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    const uint64_t m = top >= 63 ? 0ull : (~0ull << (top + 1));
+    L.prefix = common & m;
+    L.mask = m;
+    L.krem = k;
+  }
+  __syncthreads();
+  for (int hi_bit = top; hi_bit >= 0; hi_bit -= 11) {
+    const int width = hi_bit + 1 < 11 ? hi_bit + 1 : 11;
+    const int sh = hi_bit + 1 - width;
+    const uint32_t dm = (1u << width) - 1u;
+    for (int b = tid; b < 2048; b += (int)blockDim.x) L.u.hist[b] = 0u;
+    __syncthreads();
+    const uint64_t pre = L.prefix, msk = L.mask;
+    for (int64_t i = tid; i < R; i += blockDim.x) {
+      const uint64_t b = bits[i];
+      if ((b & msk) == pre) atomicAdd(&L.u.hist[(b >> sh) & dm], 1u);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t sum = 0;
+      for (int t = 0; t < 32; ++t) sum += L.u.hist[lane * 32 + t];
+      const uint32_t incl = wave_incl_scan_u32(sum, lane);
+      const int64_t kk0 = L.krem;
+      const uint64_t hit = __ballot((int64_t)incl > kk0);
+      const int owner = __ffsll((long long)hit) - 1;
+      if (lane == owner) {
+        int64_t kk = kk0 - (int64_t)(incl - sum);
+        int d = lane * 32;
+        while ((int64_t)L.u.hist[d] <= kk) {
+          kk -= L.u.hist[d];
+          ++d;
+        }
+        L.krem = kk;
+        L.prefix = pre | ((uint64_t)d << sh);
+        L.mask = msk | ((uint64_t)dm << sh);
+      }
+    }
+    __syncthreads();
+  }
+  return L.prefix;
+}
+
+__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ D,
+                                                const DevCell* __restrict__ cells, int n_q,
+                                                const uint32_t* __restrict__ qnum,
+                                                const uint32_t* __restrict__ qden,
+                                                double* __restrict__ qout,
+                                                uint64_t* __restrict__ gather, int64_t gcap) {
+  __shared__ SelLds L;
+  const int cell = (int)blockIdx.x;
   const int tid = (int)threadIdx.x;
   const DevCell c = cells[cell];
   const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
+  uint64_t* G = gather + (int64_t)cell * kSelQ * gcap;
   const int64_t R = c.R;
-  if (tid == 0) {
-    s_k = (int64_t)(((uint64_t)R * (uint64_t)qnum[qi]) / (uint64_t)qden[qi]);
-    s_prefix = 0;
-    s_mask = 0;
-  }
-  const int shifts[6] = {53, 42, 31, 20, 9, 0};
-  const int widths[6] = {11, 11, 11, 11, 11, 9};
-  for (int pass = 0; pass < 6; ++pass) {
-    const int sh = shifts[pass];
-    const uint32_t dm = (1u << widths[pass]) - 1u;
-    for (int b = tid; b < 2048; b += 256) hist[b] = 0u;
+  for (int q0 = 0; q0 < n_q; q0 += kSelQ) {
+    const int nq = (n_q - q0) < kSelQ ? (n_q - q0) : kSelQ;
+    // 1. sorted sample
+    for (int t = tid; t < kSelSample; t += 1024)
+      L.u.sample[t] = bits[(int64_t)(((uint64_t)t * (uint64_t)R) / kSelSample)];
     __syncthreads();
-    const uint64_t prefix = s_prefix, mask = s_mask;
-    for (int64_t i = tid; i < R; i += 256) {
-      const uint64_t b = bits[i];
-      if ((b & mask) == prefix) atomicAdd(&hist[(b >> sh) & dm], 1u);
+    block_bitonic_u64(L.u.sample, kSelSample);
+    // 2. brackets: +-(5 sd + 8) sample positions around the expected one
+    if (tid < nq) {
+      const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
+      const double qf = (double)k / (double)R;
+      const int64_t p = (int64_t)(qf * kSelSample);
+      const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
+      const int64_t a = p - dl, b = p + dl;
+      L.lo[tid] = a <= 0 ? 0ull : L.u.sample[a];
+      L.hi[tid] = b >= kSelSample - 1 ? ~0ull : L.u.sample[b];
+      L.below[tid] = 0ull;
+      L.nb[tid] = 0u;
     }
     __syncthreads();
-    uint32_t sum = 0;
-    for (int b = 0; b < 8; ++b) sum += hist[tid * 8 + b];
-    part[tid] = sum;
-    __syncthreads();
-    if (tid == 0) {
-      int64_t k = s_k;
-      int t = 0;
-      while (t < 255 && (int64_t)part[t] <= k) {
-        k -= part[t];
-        ++t;
-      }
-      int d = t * 8;
-      while (d < t * 8 + 7 && (int64_t)hist[d] <= k) {
-        k -= hist[d];
-        ++d;
-      }
-      s_k = k;
-      s_prefix = prefix | ((uint64_t)d << sh);
-      s_mask = mask | ((uint64_t)dm << sh);
+    // 3. count below, gather inside
+    uint64_t lo[kSelQ], hi[kSelQ];
+    uint32_t below[kSelQ];
+#pragma unroll
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      lo[qq] = L.lo[qq];
+      hi[qq] = L.hi[qq];
+      below[qq] = 0u;
     }
+    const int lane = tid & 63;
+    for (int64_t i0 = 0; i0 < R; i0 += 1024) {
+      const int64_t i = i0 + tid;
+      const bool valid = i < R;
+      const uint64_t b = valid ? bits[i] : 0ull;
+#pragma unroll
+      for (int qq = 0; qq < kSelQ; ++qq) {
+        if (qq < nq) {
+          const bool bl = valid && b < lo[qq];
+          const bool in = valid && !bl && b <= hi[qq];
+          below[qq] += bl ? 1u : 0u;
+          const uint64_t m = __ballot(in);
+          if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&L.nb[qq], (uint32_t)__popcll(m));
+            base = (uint32_t)__shfl((int)base, 0, 64);
+            if (in) {
+              const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
+              if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      if (qq < nq) {
+        const uint32_t w = wave_sum_u32(below[qq]);
+        if ((tid & 63) == 0 && w) atomicAdd(&L.below[qq], (unsigned long long)w);
+      }
+    }
+    __threadfence_block();
     __syncthreads();
+    // 4. per quantile: select within the gathered bracket, or over all of D
+    for (int qq = 0; qq < nq; ++qq) {
+      const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + qq]) / qden[q0 + qq]);
+      const int64_t lo_rank = (int64_t)L.below[qq];
+      const int64_t nin = (int64_t)L.nb[qq];
+      uint64_t res;
+      if (k >= lo_rank && k < lo_rank + nin && L.lo[qq] == L.hi[qq])
+        res = L.lo[qq];  // every value in the bracket equals lo (an atom of D)
+      else if (k >= lo_rank && k < lo_rank + nin && nin <= gcap) {
+        const uint64_t x = L.lo[qq] ^ L.hi[qq];
+        const int top = x ? 63 - __clzll((long long)x) : 0;
+        res = radix_select(L, G + qq * gcap, nin, k - lo_rank, top, L.lo[qq]);
+      } else {
+        res = radix_select(L, bits, R, k, 63, 0ull);
+      }
+      if (tid == 0) qout[cell * n_q + q0 + qq] = __longlong_as_double((long long)res);
+      __syncthreads();
+    }
   }
-  if (tid == 0) qout[cell * n_q + qi] = __longlong_as_double((long long)s_prefix);
 }
 
 // count of D_b >= D_obs over the bootstrap replicates.
@@ -946,11 +1278,34 @@ __global__ __launch_bounds__(256) void k_count_ge(const double* __restrict__ Db,
   if ((threadIdx.x & 63u) == 0u && local) atomicAdd(count, (unsigned long long)local);
 }
 
+// Per cell c: count of D[out_off + b] >= dobs[c], b < R (batched bootstrap).
+__global__ __launch_bounds__(256) void k_count_cells(const double* __restrict__ D,
+                                                    const DevCell* __restrict__ cells,
+                                                    const double* __restrict__ dobs,
+                                                    unsigned long long* __restrict__ counts) {
+  const int cell = (int)blockIdx.y;
+  const DevCell c = cells[cell];
+  const double d = dobs[cell];
+  uint32_t local = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.R;
+       i += (int64_t)gridDim.x * blockDim.x)
+    local += (D[c.out_off + i] >= d) ? 1u : 0u;
+  local = wave_sum_u32(local);
+  if ((threadIdx.x & 63u) == 0u && local) atomicAdd(&counts[cell], (unsigned long long)local);
+}
+
 // Raw draws of replicates rep_lo.. in draw order (parity checks of the
-// sampler).  Table read from global memory.
-__global__ void k_draws(const DevCell* __restrict__ cells, const double* __restrict__ tables,
-                        const uint16_t* __restrict__ guides, int64_t rep_lo, int64_t count,
-                        int64_t* __restrict__ x, uint32_t* __restrict__ flags) {
+// sampler), through the same fast path and resolution as the simulation.
+__global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells,
+                                              const double* __restrict__ tables,
+                                              const uint16_t* __restrict__ guides,
+                                              int64_t rep_lo, int64_t count,
+                                              int64_t* __restrict__ x,
+                                              uint32_t* __restrict__ flags) {
+  __shared__ double T[kH];
+  __shared__ uint32_t guide[kGuide];
+  load_cell_tables(T, guide, tables, guides, (int)threadIdx.x, 256);
+  __syncthreads();
   const DevCell c = cells[0];
   const int64_t total = count * c.n;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -961,7 +1316,9 @@ __global__ void k_draws(const DevCell* __restrict__ cells, const double* __restr
     const Words4 w = philox4x32_10(i >> 1, rep, c.stream, 0u, c.k0, c.k1);
     const double U = (i & 1u) ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
     uint32_t fl = 0;
-    x[t] = draw_one<0>(U, i, rep, c, tables, tables, guides, fl);
+    int64_t v = fast_draw(U, c.tmax, T, guide);
+    if (v == 0) v = resolve(QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
+    x[t] = v;
     if (fl) atomicOr(&flags[rr], fl);
   }
 }
@@ -990,18 +1347,21 @@ hipError_t launch_tables(DevCell* cells, int n_cells, double* tables, uint16_t* 
   k_table<<<dim3(kH / 256, n_cells), 256, 0, s>>>(cells, tables, ln);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_guide<<<dim3(kG / 256, n_cells), 256, 0, s>>>(cells, tables, guides);
+  k_guide<<<dim3((kGuide + 1 + 255) / 256, n_cells), 256, 0, s>>>(cells, tables, guides);
   return hipGetLastError();
 }
+
+static_assert(sizeof(WaveSlot) == kWaveSlotBytes, "WaveSlot layout");
 
 hipError_t launch_simulate(int grid, const DevCell* cells, const double* tables,
                            const uint16_t* guides, const double* ln, const Unit* units,
                            int n_units, uint32_t* queue, Outputs out, uint64_t* esc_list,
                            uint32_t* esc_count, uint32_t esc_cap, int64_t* list_v,
-                           uint32_t* list_c, uint32_t* err, hipStream_t s) {
+                           uint32_t* list_c, void* wslots, uint32_t* err, hipStream_t s) {
   if (n_units <= 0 || grid <= 0) return hipSuccess;
   k_simulate<<<grid, kBlock, 0, s>>>(cells, tables, guides, ln, units, n_units, queue, out,
-                                     esc_list, esc_count, esc_cap, list_v, list_c, err);
+                                     esc_list, esc_count, esc_cap, list_v, list_c,
+                                     (WaveSlot*)wslots, err);
   return hipGetLastError();
 }
 
@@ -1011,7 +1371,7 @@ hipError_t launch_heavy(int grid, const DevCell* cells, const double* tables,
                         uint32_t esc_cap, uint32_t* queues, Outputs out, int64_t* scratch,
                         int64_t stride, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  k_heavy<<<grid, 64, 0, s>>>(cells, tables, guides, ln, units, n_units, esc_list, esc_count,
+  k_heavy<<<grid, 64 * kHeavyWaves, 0, s>>>(cells, tables, guides, ln, units, n_units, esc_list, esc_count,
                               esc_cap, queues, out, scratch, stride);
   return hipGetLastError();
 }
@@ -1026,9 +1386,9 @@ hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int
 
 hipError_t launch_select(const double* D, const DevCell* cells, int n_cells, int n_q,
                          const uint32_t* qnum, const uint32_t* qden, double* qout,
-                         hipStream_t s) {
+                         uint64_t* gather, int64_t gcap, hipStream_t s) {
   if (n_cells <= 0 || n_q <= 0) return hipSuccess;
-  k_select<<<n_cells * n_q, 256, 0, s>>>(D, cells, n_q, qnum, qden, qout);
+  k_select<<<n_cells, 1024, 0, s>>>(D, cells, n_q, qnum, qden, qout, gather, gcap);
   return hipGetLastError();
 }
 
@@ -1038,6 +1398,17 @@ hipError_t launch_count_ge(const double* Db, int64_t B, const double* Dobs,
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   k_count_ge<<<grid, 256, 0, s>>>(Db, B, Dobs, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_cells(const double* D, const DevCell* cells, int n_cells,
+                              const double* dobs, unsigned long long* counts, int64_t maxR,
+                              hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  int gx = (int)((maxR + 255) / 256);
+  if (gx > 64) gx = 64;
+  if (gx < 1) gx = 1;
+  k_count_cells<<<dim3(gx, n_cells), 256, 0, s>>>(D, cells, dobs, counts);
   return hipGetLastError();
 }
 

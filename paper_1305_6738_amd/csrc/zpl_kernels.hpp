@@ -6,30 +6,46 @@
 
 namespace zpl {
 
-// Guide table: g[j] = min{k : T[k] >= j/kG}, so the search for U starts at
-// g[floor(U kG)] and ends by g[floor(U kG) + 1].
-constexpr int kG = 2048;
+// Two-part guide table over U.  For U < 1/2: kGA bins uniform in U.  For
+// U > 1/2: bins on e = 1 - U (exact in FP64), one per (octave of e, top
+// kGBits mantissa bits), ordered so that the bin index increases with U.
+// Entry g[b] is the smallest k a uniform in bin b can map to, so U in bin b
+// maps into [g[b], g[b+1]].  On the Zipf law the survival is close to a power
+// of k, so log-scale bins keep most brackets one or two entries wide.
+constexpr int kGA = 256;
+constexpr int kGBits = 6;
+constexpr int kOctaves = 52;  // e in [2^-53, 1/2)
+constexpr int kGuide = kGA + (kOctaves << kGBits);
 
-// Simulation kernel geometry: 4 wave64 per workgroup.
-constexpr int kWaves = 4;
+// Simulation kernel geometry: 8 wave64 per workgroup share the CDF table and
+// the guide in LDS.
+constexpr int kWaves = 8;
 constexpr int kBlock = 64 * kWaves;
-// Leading CDF entries kept in LDS by the lane/wave kernel (later ones are read
-// from the global table, through the caches).
-constexpr int kTL = 512;
-// Lane mode: one replicate per lane; per-lane histogram of values 1..kHLB
+// Lane form: one replicate per lane; per-lane histogram of values 1..kHLB
 // (16-bit counters packed two per dword) plus a per-lane list of up to kCL
-// larger values.  A replicate with more is redone by the heavy kernel.
-constexpr int kHLB = 64;
-constexpr int kCL = 16;
-// Wave mode: one replicate per wave at a time; histogram of values 1..kHW
+// larger values.  A replicate with more is redone by the heavy form.
+constexpr int kHLB = 48;
+constexpr int kCL = 8;
+// Wave form: one replicate per wave at a time; histogram of values 1..kHW
 // plus up to kCW larger values in LDS; finishes run one replicate per lane.
 constexpr int kHW = 1024;
-constexpr int kCW = 1024;
+constexpr int kCW = 512;
+// Deferred draws (multi-entry guide brackets and tail draws) wait in a
+// per-wave queue and are resolved 64 at a time, one per lane.
+constexpr int kQCap = 192;
 // Compact (value, count) list capacity per wave for deferred finishes.
 constexpr int kListCap = 16 * (kHW + kCW);
-// Heavy kernel: one wave per workgroup, whole table in LDS, larger values in
-// a per-wave global scratch area.
+// Heavy form: 4 wave64 per workgroup, values above kHeavyHist in per-wave
+// global scratch (sorted there).
+constexpr int kHeavyWaves = 4;
 constexpr int kHeavyHist = 1024;
+// Quantiles per selection pass and the per-(cell, quantile) capacity of the
+// bracket gather scratch.
+constexpr int kSelQ = 4;
+constexpr int64_t kSelGather = 32768;
+// Size of the per-replicate record of a wave-form batch (global scratch,
+// 64 per wave).
+constexpr int kWaveSlotBytes = 48;
 
 enum Mode : uint32_t { kModeLane = 0, kModeWave = 1, kModeHeavy = 2 };
 

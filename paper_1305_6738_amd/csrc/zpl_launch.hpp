@@ -15,7 +15,7 @@ hipError_t launch_simulate(int grid, const DevCell* cells, const double* tables,
                            const uint16_t* guides, const double* ln, const Unit* units,
                            int n_units, uint32_t* queue, Outputs out, uint64_t* esc_list,
                            uint32_t* esc_count, uint32_t esc_cap, int64_t* list_v,
-                           uint32_t* list_c, uint32_t* err, hipStream_t s);
+                           uint32_t* list_c, void* wslots, uint32_t* err, hipStream_t s);
 hipError_t launch_heavy(int grid, const DevCell* cells, const double* tables,
                         const uint16_t* guides, const double* ln, const Unit* units,
                         int n_units, const uint64_t* esc_list, const uint32_t* esc_count,
@@ -26,9 +26,12 @@ hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int
                       double* D, uint32_t* flags, uint32_t* status, hipStream_t s);
 hipError_t launch_select(const double* D, const DevCell* cells, int n_cells, int n_q,
                          const uint32_t* qnum, const uint32_t* qden, double* qout,
-                         hipStream_t s);
+                         uint64_t* gather, int64_t gcap, hipStream_t s);
 hipError_t launch_count_ge(const double* Db, int64_t B, const double* Dobs,
                            unsigned long long* count, hipStream_t s);
+hipError_t launch_count_cells(const double* D, const DevCell* cells, int n_cells,
+                              const double* dobs, unsigned long long* counts, int64_t maxR,
+                              hipStream_t s);
 hipError_t launch_draws(const DevCell* cell, const double* table, const uint16_t* guide,
                         int64_t rep_lo, int64_t count, int64_t* x, uint32_t* flags,
                         int64_t total, hipStream_t s);

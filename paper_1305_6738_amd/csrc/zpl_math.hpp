@@ -114,6 +114,41 @@ ZPL_HD double hurwitz_tail(double s, double q, double lnq) {
   return qs * (q / (s - 1.0) + 0.5 + em_series(s, 1.0 / q));
 }
 
+// Reciprocal for the small Euler-Maclaurin correction terms (they change
+// zeta by less than 1e-17 relative, so the hardware reciprocal suffices).
+ZPL_HD double rcp_corr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcp(x);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// k^-s for k = 2..16 from the six prime powers 2,3,5,7,11,13 (one exp each)
+// multiplied in a fixed order.  pw[k] for k = 0..16 (pw[0], pw[1] unused).
+ZPL_HD void small_powers(double s, const double* __restrict__ ln, double pw[17]) {
+  const double p2 = pow_neg(s, ln[2]), p3 = pow_neg(s, ln[3]), p5 = pow_neg(s, ln[5]),
+               p7 = pow_neg(s, ln[7]), p11 = pow_neg(s, ln[11]), p13 = pow_neg(s, ln[13]);
+  const double p4 = p2 * p2, p8 = p4 * p2;
+  pw[0] = 0.0;
+  pw[1] = 1.0;
+  pw[2] = p2;
+  pw[3] = p3;
+  pw[4] = p4;
+  pw[5] = p5;
+  pw[6] = p2 * p3;
+  pw[7] = p7;
+  pw[8] = p8;
+  pw[9] = p3 * p3;
+  pw[10] = p2 * p5;
+  pw[11] = p11;
+  pw[12] = p4 * p3;
+  pw[13] = p13;
+  pw[14] = p2 * p7;
+  pw[15] = p3 * p5;
+  pw[16] = p4 * p4;
+}
+
 // zeta(s), zeta'(s), zeta''(s): direct terms k = 1..16 (ln k from `ln`, the
 // library's table of natural logs) plus the Euler-Maclaurin tail at 17 and
 // its first two s-derivatives.  Summed smallest-first in a fixed order.
@@ -125,31 +160,27 @@ ZPL_HD Z3 zeta3(double s, const double* __restrict__ ln) {
   const double q = 17.0;
   const double L = ln[17];
   const double iq = 1.0 / q, iq2 = iq * iq;
-  // Q(s) = q/(s-1) + 1/2 + sum_i c_i P_i(s) q^-(2i-1), P_i = (s)_{2i-1}
+  // Q(s) = q/(s-1) + 1/2 + sum_i c_i P_i(s) q^-(2i-1), P_i = (s)_{2i-1};
+  // Q' and Q'' use P' = P sum 1/(s+k) and P'' = P ((sum 1/(s+k))^2 - sum 1/(s+k)^2).
   const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
                        1.0 / 30240.0,      -1.0 / 1209600.0,
                        1.0 / 47900160.0,   -691.0 / 1307674368000.0,
                        1.0 / 74724249600.0, -3617.0 / 10670622842880000.0};
-  double t0[8], t1[8], t2[8];
-  double P = s, sg1 = 1.0 / s, sg2 = 1.0 / (s * s), E = iq;
+  const double is = rcp_corr(s);
+  double P = s, sg1 = is, sg2 = is * is, E = iq;
+  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const double ce = c[i] * E;
-    t0[i] = ce * P;
-    t1[i] = ce * (P * sg1);
-    t2[i] = ce * (P * fma(sg1, sg1, -sg2));
+    Q0 = fma(ce, P, Q0);
+    Q1 = fma(ce, P * sg1, Q1);
+    Q2 = fma(ce, P * fma(sg1, sg1, -sg2), Q2);
     const double u = s + (double)(2 * i + 1), v = s + (double)(2 * i + 2);
+    const double iu = rcp_corr(u), iv = rcp_corr(v);
     P *= u * v;
-    sg1 += 1.0 / u + 1.0 / v;
-    sg2 += 1.0 / (u * u) + 1.0 / (v * v);
+    sg1 += iu + iv;
+    sg2 += iu * iu + iv * iv;
     E *= iq2;
-  }
-  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0;
-#pragma unroll
-  for (int i = 7; i >= 0; --i) {
-    Q0 += t0[i];
-    Q1 += t1[i];
-    Q2 += t2[i];
   }
   const double sm1 = s - 1.0, ism1 = 1.0 / sm1;
   Q0 += 0.5;
@@ -161,10 +192,12 @@ ZPL_HD Z3 zeta3(double s, const double* __restrict__ ln) {
   double z0 = qs * Q0;
   double z1 = qs * fma(-L, Q0, Q1);
   double z2 = qs * fma(L * L, Q0, fma(-2.0 * L, Q1, Q2));
+  double pw[17];
+  small_powers(s, ln, pw);
 #pragma unroll
   for (int k = 16; k >= 2; --k) {
     const double lk = ln[k];
-    const double t = pow_neg(s, lk);
+    const double t = pw[k];
     z0 += t;
     z1 = fma(-lk, t, z1);
     z2 = fma(lk * lk, t, z2);
@@ -178,7 +211,9 @@ ZPL_HD Z3 zeta3(double s, const double* __restrict__ ln) {
 // strictly (mu' = -Var[ln X]), so the root is unique.  Newton-Raphson is run
 // on ln mu(a) - ln m (nearly linear in a for large a), inside a bracket
 // [1 + 2^-20, 64] that shrinks with the sign of mu - m; a step leaving the
-// bracket becomes a bisection.  Stops when |step| <= 2^-50 a.
+// bracket becomes a bisection.  Stops once |step| <= 2^-40 a: convergence is
+// quadratic, so the iterate after such a step is at the FP64 noise level of
+// mu (a tighter test would only chase that noise).
 // ---------------------------------------------------------------------------
 ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags) {
   double lo = 1.0 + 0x1p-20, hi = 64.0;
@@ -198,11 +233,12 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
       hi = a;
     const double var = fma(-mu, mu, z.z2 / z.z0);
     double an = a + (log(mu) - lm) * (mu / var);
-    if (!(an > lo && an < hi)) {
+    // the bracket is closed: a converged step may land exactly on lo or hi
+    if (!(an >= lo && an <= hi)) {
       an = 0.5 * (lo + hi);
       *flags |= kFlagBisect;
     }
-    if (fabs(an - a) <= 0x1p-50 * a) return an;
+    if (fabs(an - a) <= 0x1p-40 * a) return an;
     a = an;
   }
   *flags |= kFlagNoConv;
@@ -215,9 +251,11 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
 // it for small t (suf[0] = zeta(a)); larger t use hurwitz_tail.
 // ---------------------------------------------------------------------------
 ZPL_HD void survival_head(double a, const double* __restrict__ ln, double suf[17]) {
+  double pw[17];
+  small_powers(a, ln, pw);
   suf[16] = hurwitz_tail(a, 17.0, ln[17]);
 #pragma unroll
-  for (int t = 15; t >= 1; --t) suf[t] = suf[t + 1] + pow_neg(a, ln[t + 1]);
+  for (int t = 15; t >= 1; --t) suf[t] = suf[t + 1] + pw[t + 1];
   suf[0] = suf[1] + 1.0;
 }
 

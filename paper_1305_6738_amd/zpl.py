@@ -37,6 +37,17 @@ class Cell(C.Structure):
                 ("seed", C.c_uint64), ("stream", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class ServeOpts(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch", C.c_int32),
+                ("max_queue", C.c_int32), ("reserved", C.c_int32), ("reserved2", C.c_int32)]
+
+
+class ServeResult(C.Structure):
+    _fields_ = [("done", C.c_int32), ("status", C.c_int32), ("alpha_hat", C.c_double),
+                ("D", C.c_double), ("p_value", C.c_double), ("flags", C.c_uint32),
+                ("batch_size", C.c_int32), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
 class SimOpts(C.Structure):
     _fields_ = [("launch", C.c_int32), ("form", C.c_int32), ("use_graph", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -73,6 +84,14 @@ def lib() -> C.CDLL:
         L.zpl_bootstrap_pvalue.argtypes = [vp, vp, i64, i32, i64, u64, u32, P(d), P(d), P(d),
                                            P(u32), vp]
         L.zpl_bootstrap_pvalue.restype = i32
+        L.zpl_serve_start.argtypes = [vp, P(ServeOpts)]
+        L.zpl_serve_start.restype = i32
+        L.zpl_serve_submit.argtypes = [vp, vp, i64, i64, u64, u32, P(u64)]
+        L.zpl_serve_submit.restype = i32
+        L.zpl_serve_poll.argtypes = [vp, u64, i32, P(ServeResult)]
+        L.zpl_serve_poll.restype = i32
+        L.zpl_serve_stop.argtypes = [vp]
+        L.zpl_serve_stop.restype = i32
         L.zpl_sample_draws.argtypes = [vp, d, i64, u64, u32, i64, i64, vp, vp, vp]
         L.zpl_sample_draws.restype = i32
         L.zpl_cdf_table.argtypes = [vp, d, vp, vp]
@@ -84,6 +103,7 @@ def lib() -> C.CDLL:
 def exported_symbols() -> list:
     return ["zpl_create", "zpl_destroy", "zpl_last_error", "zpl_simulate_cells",
             "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
+            "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
             "zpl_sample_draws", "zpl_cdf_table"]
 
 
@@ -205,6 +225,30 @@ class Context:
         del keep
         _check(st)
         return {"alpha_hat": a.value, "D": D.value, "p_value": p.value, "flags": f.value}
+
+    # -- serving (continuous batching) ---------------------------------------
+    def serve_start(self, mem_budget_bytes: int = 0, max_batch: int = 0, max_queue: int = 0):
+        o = ServeOpts(int(mem_budget_bytes), int(max_batch), int(max_queue), 0, 0)
+        _check(lib().zpl_serve_start(self._h, C.byref(o)))
+
+    def serve_submit(self, x, B: int, seed: int, stream_id: int = 0) -> int:
+        a = np.ascontiguousarray(np.asarray(x), dtype=np.int64)
+        t = C.c_uint64()
+        _check(lib().zpl_serve_submit(self._h, C.c_void_p(a.ctypes.data), a.size, int(B),
+                                      int(seed), int(stream_id), C.byref(t)))
+        return t.value
+
+    def serve_poll(self, ticket: int, wait_ms: int = 0) -> Optional[dict]:
+        r = ServeResult()
+        _check(lib().zpl_serve_poll(self._h, int(ticket), int(wait_ms), C.byref(r)))
+        if not r.done:
+            return None
+        return {"status": r.status, "alpha_hat": r.alpha_hat, "D": r.D, "p_value": r.p_value,
+                "flags": r.flags, "batch_size": r.batch_size, "queue_ms": r.queue_ms,
+                "latency_ms": r.latency_ms}
+
+    def serve_stop(self):
+        _check(lib().zpl_serve_stop(self._h))
 
     # -- zpl_sample_draws / zpl_cdf_table -----------------------------------
     def sample_draws(self, alpha: float, n: int, seed: int, stream_id: int, rep_lo: int,

@@ -235,3 +235,25 @@ def test_invalid_arguments_raise(ctx):
         ctx.simulate_cells([(2.0, 10, 10, 0, 0)], quantiles=[(10, 10)])
     with pytest.raises(ZplError):
         ctx.fit(np.array([1, 0, 2], np.int64))
+
+
+def test_quantiles_with_atoms_and_extremes(ctx, orc):
+    """Order statistics on tie-heavy D (the all-ones atom of Table 1 at
+    gamma = 3.5, N = 10 holds about half the mass) and at extreme ranks."""
+    qs = [(9, 10), (95, 100), (99, 100), (999, 1000), (0, 1), (1, 2), (99999, 100000),
+          (1, 3), (2, 3)]
+    cells = [(3.5, 10, 50000, 42, 0), (4.0, 20, 30000, 1, 1), (2.0, 3, 7, 5, 2),
+             (2.5, 100, 1, 5, 3)]
+    R = sum(c[2] for c in cells)
+    d = torch.zeros(R, dtype=torch.float64, device="cuda")
+    say("quantiles with atoms")
+    q = ctx.simulate_cells(cells, quantiles=qs, d_out=d)
+    D = d.cpu().numpy()
+    lo = 0
+    for ci, cell in enumerate(cells):
+        Dc = D[lo:lo + cell[2]]
+        for qi, (a, b) in enumerate(qs):
+            assert q[ci, qi] == orc.quantile(Dc, a, b), (cell, a, b)
+        lo += cell[2]
+    # the paper's atoms: Table 1, N = 10, gamma = 3.5: q.90 = .0819
+    assert round(q[0, 0], 4) == 0.0819
