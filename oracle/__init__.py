@@ -41,12 +41,44 @@ def build(force: bool = True) -> Path:
     return _LIB
 
 
+def compile_variant(src: Path, out: Path) -> Path:
+    """Compile another copy of the oracle source (used by tests that plant
+    mistakes in the oracle to check that the pins catch them)."""
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-I", str(_HERE), str(src),
+                    "-o", str(out), "-lquadmath", "-lm", "-lpthread"], check=True,
+                   capture_output=True)
+    return out
+
+
+class use_library:
+    """Context manager: route this module's functions to another build."""
+
+    def __init__(self, path: Path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(C.CDLL(str(self.path)))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+
+
 def lib():
     global _lib
     if _lib is None:
         if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
             build(force=True)
-        L = C.CDLL(str(_LIB))
+        _lib = _bind(C.CDLL(str(_LIB)))
+    return _lib
+
+
+def _bind(L):
+    """Declare the C signatures on a loaded oracle library."""
+    if True:  # keeps the declarations' indentation
         d, i64, u32, u64 = C.c_double, C.c_int64, C.c_uint32, C.c_uint64
         P = C.POINTER
         L.orc_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
@@ -74,8 +106,7 @@ def lib():
         L.orc_bootstrap_pvalue.argtypes = [P(i64), i64, i64, u64, u32, P(d), P(d),
                                            P(d), P(u32), C.c_int]
         L.orc_bootstrap_pvalue.restype = C.c_int
-        _lib = L
-    return _lib
+    return L
 
 
 def _ptr(a: np.ndarray, ct):

@@ -1,0 +1,155 @@
+"""Plants plausible mistakes in copies of the oracle (on the CPU) and checks
+that each one fails at least one of the pins that the real oracle passes.
+This shows the pins constrain every part of the oracle that matters.
+
+Two edits look like mistakes but are not, and are deliberately absent: taking
+the KS term at a sample value one-sided (a negative deviation there is always
+dominated by the one just below the next sample value, which the other term
+covers), and flipping the sign of the Newton derivative (the bracketed
+bisection safeguard still converges to the same root)."""
+import math
+import re
+from pathlib import Path
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+ROOT = Path(__file__).resolve().parent.parent
+SRC = ROOT / "oracle" / "zpl_oracle.c"
+
+# (name, original text, planted mistake)
+MUTANTS = [
+    ("drop EM half term", "z0 += 0.5 * as;", "z0 += 0.0 * as;"),
+    ("sign of zeta' integral term", "z1 += a1s * (-L / sm1 - 1.0 / (sm1 * sm1));",
+     "z1 += a1s * (L / sm1 - 1.0 / (sm1 * sm1));"),
+    ("one Bernoulli term dropped early", "#define ORC_EM_P 10", "#define ORC_EM_P 1"),
+    ("CDF index off by one", "T[k - 1] = 1.0 - hurwitz0(alpha, (double)k + 1.0) / z;",
+     "T[k - 1] = 1.0 - hurwitz0(alpha, (double)k) / z;"),
+    ("uniform without the odd bit", "uint64_t m = (w >> 11) | 1u;", "uint64_t m = (w >> 11);"),
+    ("Philox key schedule", "k1 += PHILOX_W1;", "k1 += PHILOX_W0;"),
+    ("Philox word order", "uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;"),
+    ("tail exponent alpha instead of alpha-1",
+     "const double beta = alpha - 1.0; /* exact in FP64 for alpha > 1 */",
+     "const double beta = alpha; /* planted */"),
+    ("tail acceptance skipped", "if (W * gm <= tail_g(beta, (double)X)) return X;", "return X;"),
+    ("all-ones rule missing", "s = log(2.0);", "s = 0.0;"),
+    ("KS misses the point below each value", "if (d2 > D) D = d2;", "(void)d2;"),
+    ("KS against the CDF one value up", "double Fv = 1.0 - hurwitz0(a, (double)v + 1.0) / z;",
+     "double Fv = 1.0 - hurwitz0(a, (double)v + 2.0) / z;"),
+    ("quantile index off by one", "uint64_t idx = ((uint64_t)R * (uint64_t)num) / (uint64_t)den;",
+     "uint64_t idx = ((uint64_t)R * (uint64_t)num) / (uint64_t)den + 1;"),
+    ("MLE equation sign", "double g = -r1 - m;", "double g = r1 - m;"),
+    ("bootstrap strict inequality", "if (Db[b] >= d) ++ge;", "if (Db[b] > d) ++ge;"),
+]
+
+
+def _checks(orc):
+    """Fast pins; returns the names of those that fail."""
+    failed = []
+    z2 = orc.zeta3(2.0)
+    if abs(z2[0] - math.pi ** 2 / 6) > 1e-15 * 2:
+        failed.append("zeta(2)")
+    zp2 = float(mp.pi ** 2 / 6 * (mp.euler + mp.log(2 * mp.pi) - 12 * mp.log(mp.glaisher)))
+    if abs(z2[1] - zp2) > 1e-14:
+        failed.append("zeta'(2)")
+    for a in (1.2, 2.5):
+        T = orc.cdf_table(a)
+        want = 1 - mp.zeta(a, 3) / mp.zeta(a)
+        if abs(T[1] - float(want)) > 1e-15:
+            failed.append("cdf table")
+    if orc.u53(0, 0) != 2.0 ** -53:
+        failed.append("u53")
+    if list(orc.philox((1, 2, 3, 4), (5, 6))) != [_PHILOX_REF[k] for k in range(4)]:
+        failed.append("philox")
+    # sampler law: tail fraction and tail mean log at alpha = 1.3
+    x, _ = orc.sample(1.3, 40000, 5, 1, 0)
+    tail = x[x > 4096].astype(np.float64)
+    exp_frac = float(mp.zeta(1.3, 4097) / mp.zeta(1.3))
+    if abs(tail.size / x.size - exp_frac) > 6 * math.sqrt(exp_frac / x.size):
+        failed.append("tail fraction")
+    if tail.size > 50:
+        # P(X >= 10 m | X >= m) for m = 4097 under p(k) ~ k^-1.3
+        frac10 = np.mean(tail >= 40970)
+        want10 = float(mp.zeta(1.3, 40970) / mp.zeta(1.3, 4097))
+        if abs(frac10 - want10) > 6 * math.sqrt(want10 * (1 - want10) / tail.size):
+            failed.append("tail shape")
+    # tail draws whose first proposal the real oracle rejects
+    for (a, i), want in _REF["tail"].items():
+        if orc.tail_draw(a, 77, 3, 0, i)[0] != want:
+            failed.append("tail rejection")
+            break
+    r = orc.fit(np.ones(10, np.int64))
+    if abs(r["D"] - 0.0819313) > 1e-6:
+        failed.append("all-ones atom")
+    for xs in (np.array([1, 1, 1, 2, 5, 5, 9]), np.array([2, 40, 41, 300])):
+        r = orc.fit(xs)
+        a = r["alpha_hat"]
+        z = mp.zeta(a)
+        best, F = mp.mpf(0), mp.mpf(0)
+        for t in range(1, int(xs.max()) + 5):
+            F += mp.mpf(t) ** (-a) / z
+            Sn = mp.mpf(int(np.sum(xs <= t))) / len(xs)
+            best = max(best, abs(F - Sn))
+        if abs(r["D"] - float(best)) > 1e-12:
+            failed.append("KS brute force")
+        S = float(np.sum(np.log(xs)))
+        if abs(-float(mp.zeta(a, 1, 1) / mp.zeta(a)) - S / len(xs)) > 1e-12:
+            failed.append("MLE equation")
+    D = np.arange(100, dtype=np.float64)
+    if orc.quantile(D, 9, 10) != 90.0:
+        failed.append("quantile index")
+    ones = orc.bootstrap_pvalue(np.ones(10, np.int64), 300, 3, 1)
+    if ones["p_value"] < 0.3:
+        failed.append("bootstrap ties")
+    return failed
+
+
+_PHILOX_REF = {}
+_REF = {"tail": {}}
+
+
+def _reference(orc):
+    """Values of the real oracle that the quick pins compare mutants with."""
+    if _PHILOX_REF:
+        return
+    _PHILOX_REF.update(enumerate(orc.philox((1, 2, 3, 4), (5, 6))))
+    # draw indices whose first tail proposal is rejected (found with float
+    # arithmetic on the oracle's Philox words; the real oracle's answer is
+    # the reference)
+    key = (77, 0)
+    for a in (1.2, 1.5):
+        beta, m = a - 1.0, 4097.0
+        g = lambda k: 1.0 / (-k * math.expm1(-beta * math.log1p(1.0 / k)))  # noqa: E731
+        found = 0
+        for i in range(200000):
+            w = orc.philox((i, 0, 3, 0x80000000), key)
+            V = ((int(w[0]) << 32 | int(w[1])) >> 11 | 1) / 2.0 ** 53
+            W = ((int(w[2]) << 32 | int(w[3])) >> 11 | 1) / 2.0 ** 53
+            Y = m * V ** (-1.0 / beta)
+            if Y >= 2.0 ** 62:
+                continue
+            if W * g(m) > g(math.floor(Y)):
+                _REF["tail"][(a, i)] = orc.tail_draw(a, 77, 3, 0, i)[0]
+                found += 1
+                if found == 3:
+                    break
+    assert len(_REF["tail"]) >= 4
+
+
+def test_real_oracle_passes_the_quick_pins(orc):
+    _reference(orc)
+    assert _checks(orc) == []
+
+
+@pytest.mark.parametrize("name,orig,planted", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(orc, tmp_path, name, orig, planted):
+    _reference(orc)
+    src = SRC.read_text()
+    assert src.count(orig) >= 1, "mutation site not found: %s" % name
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(orig, planted, 1))
+    lib = orc.compile_variant(mutant, tmp_path / ("m_%s.so" % re.sub(r"\W+", "_", name)))
+    with orc.use_library(lib):
+        failed = _checks(orc)
+    assert failed, "planted mistake '%s' passed every pin" % name
