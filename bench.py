@@ -34,6 +34,9 @@ OPS_PER_DRAW = 40 + 3 + 4 + 2
 OPS_PER_REPLICATE = 2000
 # VALU lane-op peak: 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_OPS = 256 * 64 * 2.4e9
+# Autotuning grid: the table's exponents x sample sizes spanning 10..1e5.
+TUNE_ALPHAS = [1.5 + 0.25 * i for i in range(9)]
+TUNE_NS = [10, 30, 100, 300, 1000, 3000, 10000, 30000, 100000]
 
 
 def progress(msg):
@@ -126,6 +129,9 @@ def main(argv=None):
                     help="only the batched timed region (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--tune", default="measure",
+                    help="'measure' (autotune before timing), 'none' (built-in rule) or "
+                         "the path of a saved tuning table")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -134,7 +140,7 @@ def main(argv=None):
 
     import torch
     from inputs import table_slice
-    from paper_1305_6738_amd import Context
+    from paper_1305_6738_amd import Context, load_tuning, plan_forms
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -144,6 +150,19 @@ def main(argv=None):
     ctx = Context(0)
     d = torch.empty(total_R, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    tuning = {"source": args.tune}
+    if args.tune == "measure":
+        t0 = time.perf_counter()
+        table = ctx.autotune(TUNE_ALPHAS, TUNE_NS, stream=stream)
+        tuning.update(seconds=time.perf_counter() - t0,
+                      grid="%d alphas x %d n" % (len(TUNE_ALPHAS), len(TUNE_NS)))
+        progress("autotune: %.2f s" % tuning["seconds"])
+    elif args.tune != "none":
+        table = load_tuning(args.tune)
+        ctx.set_tuning(table)
+    else:
+        table = None
+    tuning["forms"] = plan_forms(cells, table)
     ctx.set_timing(True)
 
     for _ in range(args.warmup):
@@ -181,6 +200,7 @@ def main(argv=None):
                       "n": 1000, "cells": len(cells), "replicates_per_cell": args.replicates,
                       "quantiles": ["%d/%d" % qq for qq in QS], "launch": "batched"},
            "kernel_ms": {k: sum(t[k] for t in all_ms) / len(all_ms) for k in all_ms[0]},
+           "tuning": tuning,
            "roofline": roofline}
 
     if not args.no_extras:
@@ -207,6 +227,20 @@ def main(argv=None):
         g_ms = (time.perf_counter() - t0) * 1e3 / args.steps
         out["graph_value"] = total_R / (g_ms / 1e3)
         progress("graph replay: %.3f ms/step" % g_ms)
+        # the same batched launch under the built-in form rule (no table)
+        if table is not None:
+            ctx.set_tuning(None)
+            ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nplain):
+                ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+            torch.cuda.synchronize()
+            u_ms = (time.perf_counter() - t0) * 1e3 / nplain
+            out["untuned_value"] = total_R / (u_ms / 1e3)
+            out["untuned_forms"] = plan_forms(cells)
+            ctx.set_tuning(table)
+            progress("built-in form rule: %.3f ms/step" % u_ms)
         out["fit_latency"] = fit_latency(ctx)
         progress("fit latency done")
         if args.serve_seconds > 0:

@@ -40,7 +40,10 @@
  * Errors: every function returns a zpl_status; nothing is thrown across the
  * ABI.  On failure zpl_last_error() describes the error (per thread, valid
  * until the next call on that thread).  A context is not thread-safe: calls
- * on one context must be serialised by the caller.
+ * on one context must be serialised by the caller, and because the calls
+ * share the context's scratch, work enqueued by one call must not overlap on
+ * the device with another's (use one stream per context, or synchronise
+ * before switching streams).
  */
 #ifndef ZPL_H
 #define ZPL_H
@@ -129,6 +132,46 @@ zpl_status zpl_simulate_cells(zpl_ctx *ctx, const zpl_cell *cells, int32_t n_cel
                               double *quantiles, double *d_out, double *alpha_hat_out,
                               uint32_t *flags_out, uint64_t *fingerprint_out,
                               const zpl_sim_opts *opts, void *stream);
+
+/* --------------------------------------------------------------------------
+ * Autotuning of the execution form (the batched launch of Sect. 3's
+ * simulations over cells of uneven n).  Every form computes the same bits;
+ * the choice only changes speed.  The lane form runs one replicate per lane
+ * and suits short replicates with light tails; the wave form runs one
+ * replicate per wavefront with per-lane finishes; the heavy form keeps large
+ * values in global memory.  A tuning table holds the measured cost of each
+ * form on a grid of (alpha, n); with one installed, the planner gives every
+ * cell the cheapest form eligible there (cost interpolated bilinearly in
+ * alpha and ln n) and orders the work units by measured cost.
+ * ------------------------------------------------------------------------ */
+typedef struct zpl_tune_entry {
+  double alpha;
+  int64_t n;
+  double ns_per_replicate[3]; /* lane, wave, heavy form: nanoseconds per
+                                 replicate with the whole device busy;
+                                 negative = form not eligible there       */
+} zpl_tune_entry;
+
+/* Measure the grid alphas[n_alpha] x ns[n_n] (each strictly increasing;
+ * alpha in [1.01, 64], n in [1, 2^20], at most 64 values per axis) on the
+ * context's device and install the table in the context.  table_out (host,
+ * [n_alpha * n_n], alpha-major: entry ia * n_n + in) receives it, or NULL.
+ * Each eligible (point, form) runs a probe cell sized to give every compute
+ * unit one unit of work, twice; the probes are synchronous on `stream`. */
+zpl_status zpl_autotune(zpl_ctx *ctx, const double *alphas, int32_t n_alpha,
+                        const int64_t *ns, int32_t n_n, zpl_tune_entry *table_out,
+                        void *stream);
+
+/* Install a saved table (host, `count` entries in zpl_autotune's layout);
+ * count = 0 removes it (built-in rule).  ZPL_EINVAL if the entries do not
+ * form an alpha-major grid with increasing axes and finite costs. */
+zpl_status zpl_set_tuning(zpl_ctx *ctx, const zpl_tune_entry *table, int32_t count);
+
+/* The planner's form for each cell (ZPL_FORM_LANE/WAVE/HEAVY into
+ * forms_out[n_cells], host) under `table` (count = 0: the built-in rule).
+ * Host-only: touches no device and needs no context. */
+zpl_status zpl_plan_forms(const zpl_tune_entry *table, int32_t count, const zpl_cell *cells,
+                          int32_t n_cells, int32_t *forms_out);
 
 /* Per-kernel timing of simulations (HIP events on the call's stream).
  * zpl_set_timing(ctx, 1) makes every later non-graph zpl_simulate_cells

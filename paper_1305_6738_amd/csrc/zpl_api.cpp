@@ -81,6 +81,13 @@ double tail_prob(double a, int h) {
   return zt / suf[0];
 }
 
+struct Tuning {
+  std::vector<double> alphas;  // strictly increasing
+  std::vector<int64_t> ns;     // strictly increasing
+  std::vector<double> cost;    // [(ia * ns.size() + in) * 3 + form], < 0: not measured
+  bool empty() const { return alphas.empty(); }
+};
+
 }  // namespace
 
 struct Server;
@@ -102,12 +109,17 @@ struct zpl_ctx {
   bool graph_valid = false;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<char> graph_key;
+  // The plan buffers (cells, units, hunits, qnum, qden) are rewritten by
+  // every call; plan_gen counts the uploads, and a replay re-uploads its
+  // plan when another call wrote the buffers after it (graph_plan_gen).
+  uint64_t plan_gen = 0, graph_plan_gen = 0;
   uint32_t esc_cap = 0;
   // optional per-kernel timing of the last non-graph simulation
   hipStream_t cap_stream = nullptr;  // graphs are captured here (never the null stream)
   bool timing = false;
   bool timed = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  Tuning tune;  // measured form costs (empty: built-in rule)
 };
 
 namespace {
@@ -155,6 +167,103 @@ zpl_status ensure_pinned(zpl_ctx* c, size_t bytes) {
   } while (0)
 
 // ---------------------------------------------------------------------------
+// Tuning table: the measured cost (ns per replicate, whole device busy) of
+// each execution form on a grid of (alpha, n).  With a table the planner
+// picks the cheapest eligible form of every cell and orders the work units by
+// measured cost; without one it uses the built-in rule below.  Every form
+// gives the same bits, so a table changes speed only.
+// ---------------------------------------------------------------------------
+
+constexpr int kTuneMaxAxis = 64;
+
+zpl_status parse_tuning(const zpl_tune_entry* e, int32_t count, Tuning& t) {
+  t = Tuning();
+  if (count == 0) return ZPL_OK;
+  if (count < 0 || !e) return fail(ZPL_EINVAL, "tuning table: bad count or NULL entries");
+  // alpha-major grid: the n axis is the run of entries sharing the first alpha
+  int nn = 1;
+  while (nn < count && e[nn].alpha == e[0].alpha) ++nn;
+  if (count % nn != 0)
+    return fail(ZPL_EINVAL, "tuning table: %d entries do not form an alpha x n grid", count);
+  const int na = count / nn;
+  if (na > kTuneMaxAxis || nn > kTuneMaxAxis)
+    return fail(ZPL_EINVAL, "tuning table: at most %d values per axis", kTuneMaxAxis);
+  for (int ia = 0; ia < na; ++ia) {
+    const double a = e[ia * nn].alpha;
+    if (!(a >= 1.0 && a <= 64.0)) return fail(ZPL_EINVAL, "tuning table: alpha %g outside (1, 64]", a);
+    if (ia > 0 && !(a > t.alphas.back()))
+      return fail(ZPL_EINVAL, "tuning table: alphas must increase");
+    t.alphas.push_back(a);
+  }
+  for (int in = 0; in < nn; ++in) {
+    const int64_t n = e[in].n;
+    if (n < 1) return fail(ZPL_EINVAL, "tuning table: n must be >= 1");
+    if (in > 0 && !(n > t.ns.back())) return fail(ZPL_EINVAL, "tuning table: n must increase");
+    t.ns.push_back(n);
+  }
+  t.cost.resize((size_t)count * 3);
+  for (int ia = 0; ia < na; ++ia)
+    for (int in = 0; in < nn; ++in) {
+      const zpl_tune_entry& x = e[ia * nn + in];
+      if (x.alpha != t.alphas[ia] || x.n != t.ns[in])
+        return fail(ZPL_EINVAL, "tuning table: entry %d is not (alpha %g, n %lld) of the grid",
+                    ia * nn + in, t.alphas[ia], (long long)t.ns[in]);
+      for (int f = 0; f < 3; ++f) {
+        const double v = x.ns_per_replicate[f];
+        if (!std::isfinite(v)) return fail(ZPL_EINVAL, "tuning table: cost not finite");
+        t.cost[(size_t)(ia * nn + in) * 3 + f] = v;
+      }
+    }
+  return ZPL_OK;
+}
+
+// Position of x on an increasing axis: segment i and weight w of axis[i+1]
+// (clamped to the ends).
+void axis_locate(const std::vector<double>& ax, double x, int& i, double& w) {
+  const int m = (int)ax.size();
+  if (m == 1 || x <= ax[0]) {
+    i = 0;
+    w = 0.0;
+    return;
+  }
+  if (x >= ax[m - 1]) {
+    i = m - 2;
+    w = 1.0;
+    return;
+  }
+  i = 0;
+  while (ax[i + 1] < x) ++i;
+  w = (x - ax[i]) / (ax[i + 1] - ax[i]);
+}
+
+// Cost per replicate of form f (0 lane, 1 wave, 2 heavy) at (alpha, n):
+// bilinear in (alpha, ln n) on the grid, clamped in alpha and below the
+// smallest n, proportional to n above the largest.  Negative when a grid
+// corner that carries weight at the point has no measurement.
+double tuned_cost(const Tuning& t, int f, double alpha, int64_t n) {
+  std::vector<double> lns(t.ns.size());
+  for (size_t k = 0; k < t.ns.size(); ++k) lns[k] = std::log((double)t.ns[k]);
+  int ia, in;
+  double wa, wn;
+  axis_locate(t.alphas, alpha, ia, wa);
+  axis_locate(lns, std::log((double)n), in, wn);
+  const int nn = (int)t.ns.size();
+  const int ia1 = std::min(ia + 1, (int)t.alphas.size() - 1), in1 = std::min(in + 1, nn - 1);
+  const double c00 = t.cost[(size_t)(ia * nn + in) * 3 + f];
+  const double c01 = t.cost[(size_t)(ia * nn + in1) * 3 + f];
+  const double c10 = t.cost[(size_t)(ia1 * nn + in) * 3 + f];
+  const double c11 = t.cost[(size_t)(ia1 * nn + in1) * 3 + f];
+  const double w00 = (1 - wa) * (1 - wn), w01 = (1 - wa) * wn, w10 = wa * (1 - wn), w11 = wa * wn;
+  // a corner that carries weight must have a measurement
+  if ((w00 > 0 && c00 < 0) || (w01 > 0 && c01 < 0) || (w10 > 0 && c10 < 0) || (w11 > 0 && c11 < 0))
+    return -1.0;
+  double v = (w00 > 0 ? w00 * c00 : 0.0) + (w01 > 0 ? w01 * c01 : 0.0) +
+             (w10 > 0 ? w10 * c10 : 0.0) + (w11 > 0 ? w11 * c11 : 0.0);
+  if (n > t.ns.back()) v *= (double)n / (double)t.ns.back();
+  return v;
+}
+
+// ---------------------------------------------------------------------------
 // Planner: execution form per cell and the unit list.
 // ---------------------------------------------------------------------------
 struct Plan {
@@ -164,16 +273,42 @@ struct Plan {
   std::vector<int> cell_unit_begin, cell_unit_end;  // per cell range in `units`
   int64_t total_R = 0;
   int64_t max_n = 0;
+  int64_t lw_R = 0;  // replicates in lane and wave cells
 };
 
-uint32_t choose_form(double alpha, int64_t n) {
+// Forms a tuned planner may pick: the lane form only where a replicate rarely
+// overflows its per-lane list, the wave form only where the LDS overflow
+// area almost surely holds a replicate's large values.
+bool form_eligible(uint32_t m, double alpha, int64_t n) {
+  if (m == kModeLane) return n <= 65535 && (double)n * tail_prob(alpha, kHLB) <= 2.5;
+  if (m == kModeWave) {
+    const double mu = (double)n * tail_prob(alpha, kHW);
+    return mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)kCW;
+  }
+  return true;
+}
+
+uint32_t choose_form(double alpha, int64_t n, const Tuning* t) {
+  if (t && !t->empty()) {
+    int best = -1;
+    double bc = 0.0;
+    for (int f = 0; f < 3; ++f) {
+      if (!form_eligible((uint32_t)f, alpha, n)) continue;
+      const double v = tuned_cost(*t, f, alpha, n);
+      if (v >= 0.0 && (best < 0 || v < bc)) {
+        best = f;
+        bc = v;
+      }
+    }
+    if (best >= 0) return (uint32_t)best;
+  }
   if (n <= 65535 && (double)n * tail_prob(alpha, kHLB) <= 2.0) return kModeLane;
-  const double mu = (double)n * tail_prob(alpha, kHW);
-  if (mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)kCW) return kModeWave;
+  if (form_eligible(kModeWave, alpha, n)) return kModeWave;
   return kModeHeavy;
 }
 
-zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P) {
+zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
+                     const Tuning* tune = nullptr) {
   P = Plan();
   P.cells.resize(n_cells);
   P.cell_unit_begin.assign(n_cells, 0);
@@ -205,18 +340,25 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P) {
         break;
       case ZPL_FORM_WAVE: m = kModeWave; break;
       case ZPL_FORM_HEAVY: m = kModeHeavy; break;
-      default: m = choose_form(z.alpha, z.n);
+      default: m = choose_form(z.alpha, z.n, tune);
     }
     d.mode = m;
     P.total_R += z.replicates;
     P.max_n = std::max(P.max_n, z.n);
+    if (m != kModeHeavy) P.lw_R += z.replicates;
   }
   // units: kBlock replicates (one per lane, or 64 per wave) for lane/wave
-  // cells, 8 replicates (2 per wave) for heavy cells
+  // cells, 8 replicates (2 per wave) for heavy cells; weights for the
+  // longest-first order come from the tuning table when there is one
   std::vector<std::pair<double, Unit>> tmp;
   for (int i = 0; i < n_cells; ++i) {
     const DevCell& d = P.cells[i];
     const int per = d.mode == kModeHeavy ? 8 : kBlock;
+    double w = (double)d.n;
+    if (tune && !tune->empty()) {
+      const double v = tuned_cost(*tune, (int)d.mode, d.alpha, d.n);
+      if (v > 0.0) w = v;
+    }
     for (int64_t r = 0; r < d.R; r += per) {
       Unit u;
       u.cell = i;
@@ -225,7 +367,7 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P) {
       if (d.mode == kModeHeavy)
         P.hunits.push_back(u);
       else
-        tmp.push_back({(double)d.n * u.count, u});
+        tmp.push_back({w * u.count, u});
     }
   }
   // longest units first; ties by cell so a workgroup tends to keep its table
@@ -275,9 +417,10 @@ zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L
   ZPL_TRY(ensure(c, c->queues, sizeof(uint32_t) * (size_t)(nc + 8)));
   ZPL_TRY(ensure(c, c->esc_cnt, sizeof(uint32_t) * 4));
   ZPL_TRY(ensure(c, c->err, sizeof(uint32_t) * 4));
-  // escalation list: generous, escalations are rare by construction
-  const uint32_t esc_cap = (uint32_t)std::min<int64_t>(std::max<int64_t>(P.total_R / 4, 4096),
-                                                       (int64_t)1 << 24);
+  // escalation list: a slot for every lane/wave replicate (each escalates at
+  // most once), so it cannot overflow below 2^31 such replicates
+  const uint32_t esc_cap =
+      (uint32_t)std::min<int64_t>(std::max<int64_t>(P.lw_R, 64), (int64_t)1 << 31);
   ZPL_TRY(ensure(c, c->esc, sizeof(uint64_t) * esc_cap));
   c->esc_cap = esc_cap;
   const int sim_grid =
@@ -382,7 +525,7 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
     if (q_den[i] == 0 || q_num[i] >= q_den[i])
       return fail(ZPL_EINVAL, "quantile %d: need num < den (got %u/%u)", i, q_num[i], q_den[i]);
   Plan P;
-  ZPL_TRY(make_plan(cells, n_cells, o.form, P));
+  ZPL_TRY(make_plan(cells, n_cells, o.form, P, &c->tune));
   if (o.launch == ZPL_LAUNCH_PLAIN) plain_unit_order(P);
   const bool need_sel = quantiles && n_q > 0;
   const bool need_dbuf = need_sel && out.D == nullptr;
@@ -407,7 +550,7 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
   put(&s, sizeof s);
   const bool replay = o.use_graph && o.launch == ZPL_LAUNCH_BATCHED && c->graph_valid &&
                       c->graph_key == key;
-  if (!replay) {
+  if (!replay || c->plan_gen != c->graph_plan_gen) {
     // upload the plan
     const size_t bc = sizeof(DevCell) * P.cells.size(), bu = sizeof(Unit) * P.units.size(),
                  bh = sizeof(Unit) * P.hunits.size(), bq = sizeof(uint32_t) * (size_t)n_q;
@@ -428,6 +571,7 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
       HIP_TRY(hipMemcpyAsync(c->qnum.p, pin + bc + bu + bh, bq, hipMemcpyHostToDevice, s));
       HIP_TRY(hipMemcpyAsync(c->qden.p, pin + bc + bu + bh + bq, bq, hipMemcpyHostToDevice, s));
     }
+    ++c->plan_gen;
   }
   const double* Dsel = need_sel ? out.D : nullptr;
   if (o.use_graph && o.launch == ZPL_LAUNCH_BATCHED) {
@@ -455,6 +599,7 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
       c->graph_valid = true;
       c->graph_key = key;
     }
+    c->graph_plan_gen = c->plan_gen;
     HIP_TRY(hipGraphLaunch(c->graph_exec, s));
     c->timed = false;
   } else {
@@ -469,6 +614,58 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
     ZPL_TRY(check_err_word(c, s));
   }
   return ZPL_OK;
+}
+
+// Measures the cost of each eligible form at every grid point: a probe cell
+// with enough replicates to give every compute unit one unit of work (lane
+// and wave forms: kBlock replicates per workgroup; heavy form: 8 per
+// workgroup of its grid), timed with events around the simulation and heavy
+// launches (table build excluded), best of two runs.
+zpl_status autotune_grid(zpl_ctx* c, const double* alphas, int na, const int64_t* ns, int nn,
+                         std::vector<zpl_tune_entry>& out, hipStream_t s) {
+  out.assign((size_t)na * nn, zpl_tune_entry{});
+  const bool was_timing = c->timing;
+  if (!c->ev[0])
+    for (hipEvent_t& e : c->ev) HIP_TRY(hipEventCreate(&e));
+  c->timing = true;
+  zpl_status st = ZPL_OK;
+  for (int ia = 0; ia < na && st == ZPL_OK; ++ia)
+    for (int in = 0; in < nn && st == ZPL_OK; ++in) {
+      zpl_tune_entry& e = out[(size_t)ia * nn + in];
+      e.alpha = alphas[ia];
+      e.n = ns[in];
+      for (int f = 0; f < 3 && st == ZPL_OK; ++f) {
+        e.ns_per_replicate[f] = -1.0;
+        if (!form_eligible((uint32_t)f, alphas[ia], ns[in])) continue;
+        const int64_t R = f == kModeHeavy ? (int64_t)c->n_cu * 2 * 8 : (int64_t)c->n_cu * kBlock;
+        st = ensure(c, c->dbuf, sizeof(double) * (size_t)R);
+        if (st != ZPL_OK) break;
+        const zpl_cell z = {alphas[ia], ns[in], R, 0x7475656eull, (uint32_t)(ia * nn + in), 0};
+        const zpl_sim_opts o = {ZPL_LAUNCH_BATCHED, f + 1, 0, 0};
+        Outputs po{(double*)c->dbuf.p, nullptr, nullptr, nullptr, nullptr};
+        double best = -1.0;
+        for (int rep = 0; rep < 2 && st == ZPL_OK; ++rep) {
+          st = run_cells(c, &z, 1, nullptr, nullptr, 0, nullptr, po, &o, s);
+          if (st != ZPL_OK) break;
+          if (hipEventSynchronize(c->ev[3]) != hipSuccess) {
+            st = fail(ZPL_EDEVICE, "autotune: event wait failed");
+            break;
+          }
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, c->ev[1], c->ev[3]) != hipSuccess) {
+            st = fail(ZPL_EDEVICE, "autotune: event timing failed");
+            break;
+          }
+          const double v = (double)ms * 1e6 / (double)R;
+          if (best < 0.0 || v < best) best = v;
+        }
+        if (st == ZPL_OK) st = check_err_word(c, s);
+        e.ns_per_replicate[f] = best;
+      }
+    }
+  c->timing = was_timing;
+  c->timed = false;
+  return st;
 }
 
 zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, double* ahat,
@@ -814,6 +1011,51 @@ zpl_status zpl_simulate_cells(zpl_ctx* c, const zpl_cell* cells, int32_t n_cells
                    (hipStream_t)stream);
 }
 
+zpl_status zpl_autotune(zpl_ctx* c, const double* alphas, int32_t n_alpha, const int64_t* ns,
+                        int32_t n_n, zpl_tune_entry* table_out, void* stream) {
+  g_err.clear();
+  if (!c || !alphas || !ns) return fail(ZPL_EINVAL, "NULL argument");
+  if (n_alpha < 1 || n_n < 1 || n_alpha > kTuneMaxAxis || n_n > kTuneMaxAxis)
+    return fail(ZPL_EINVAL, "grid axes need 1..%d values", kTuneMaxAxis);
+  for (int i = 0; i < n_alpha; ++i) {
+    if (!(alphas[i] >= kMinAlpha) || !(alphas[i] <= 64.0))
+      return fail(ZPL_EINVAL, "alpha %g outside [1.01, 64]", alphas[i]);
+    if (i > 0 && !(alphas[i] > alphas[i - 1])) return fail(ZPL_EINVAL, "alphas must increase");
+  }
+  for (int i = 0; i < n_n; ++i) {
+    if (ns[i] < 1 || ns[i] > ((int64_t)1 << 20))
+      return fail(ZPL_EINVAL, "grid n %lld outside [1, 2^20]", (long long)ns[i]);
+    if (i > 0 && !(ns[i] > ns[i - 1])) return fail(ZPL_EINVAL, "ns must increase");
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  std::vector<zpl_tune_entry> tab;
+  ZPL_TRY(autotune_grid(c, alphas, n_alpha, ns, n_n, tab, (hipStream_t)stream));
+  ZPL_TRY(parse_tuning(tab.data(), (int32_t)tab.size(), c->tune));
+  if (table_out) std::memcpy(table_out, tab.data(), sizeof(zpl_tune_entry) * tab.size());
+  return ZPL_OK;
+}
+
+zpl_status zpl_set_tuning(zpl_ctx* c, const zpl_tune_entry* table, int32_t count) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  Tuning t;
+  ZPL_TRY(parse_tuning(table, count, t));
+  c->tune = std::move(t);
+  return ZPL_OK;
+}
+
+zpl_status zpl_plan_forms(const zpl_tune_entry* table, int32_t count, const zpl_cell* cells,
+                          int32_t n_cells, int32_t* forms_out) {
+  g_err.clear();
+  if (n_cells < 1 || !cells || !forms_out) return fail(ZPL_EINVAL, "need cells and forms_out");
+  Tuning t;
+  ZPL_TRY(parse_tuning(table, count, t));
+  Plan P;
+  ZPL_TRY(make_plan(cells, n_cells, ZPL_FORM_AUTO, P, &t));
+  for (int i = 0; i < n_cells; ++i) forms_out[i] = (int32_t)P.cells[i].mode + 1;
+  return ZPL_OK;
+}
+
 zpl_status zpl_set_timing(zpl_ctx* c, int32_t enable) {
   g_err.clear();
   if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
@@ -900,6 +1142,7 @@ zpl_status zpl_serve_start(zpl_ctx* c, const zpl_serve_opts* opts) {
     delete sv;
     return st;
   }
+  sv->eng->tune = c->tune;
   sv->th = std::thread([sv] { sv->loop(); });
   c->server = sv;
   return ZPL_OK;
@@ -1006,6 +1249,7 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
   HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  ++c->plan_gen;
   HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
                         c->ln, s));
   HIP_TRY(launch_fill_u32(flags_out, (int)count, 0u, s));
@@ -1032,6 +1276,7 @@ zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, double* T_out, void* stream) 
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
   HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  ++c->plan_gen;
   HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
                         c->ln, s));
   HIP_TRY(hipMemcpyAsync(T_out, c->tables.p, sizeof(double) * kH, hipMemcpyDeviceToDevice, s));

@@ -48,6 +48,10 @@ class ServeResult(C.Structure):
                 ("batch_size", C.c_int32), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("n", C.c_int64), ("ns_per_replicate", C.c_double * 3)]
+
+
 class SimOpts(C.Structure):
     _fields_ = [("launch", C.c_int32), ("form", C.c_int32), ("use_graph", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -96,6 +100,12 @@ def lib() -> C.CDLL:
         L.zpl_sample_draws.restype = i32
         L.zpl_cdf_table.argtypes = [vp, d, vp, vp]
         L.zpl_cdf_table.restype = i32
+        L.zpl_autotune.argtypes = [vp, P(d), i32, P(i64), i32, P(TuneEntry), vp]
+        L.zpl_autotune.restype = i32
+        L.zpl_set_tuning.argtypes = [vp, P(TuneEntry), i32]
+        L.zpl_set_tuning.restype = i32
+        L.zpl_plan_forms.argtypes = [P(TuneEntry), i32, P(Cell), i32, P(i32)]
+        L.zpl_plan_forms.restype = i32
         _lib = L
     return _lib
 
@@ -104,7 +114,52 @@ def exported_symbols() -> list:
     return ["zpl_create", "zpl_destroy", "zpl_last_error", "zpl_simulate_cells",
             "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
             "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
-            "zpl_sample_draws", "zpl_cdf_table"]
+            "zpl_sample_draws", "zpl_cdf_table", "zpl_autotune", "zpl_set_tuning",
+            "zpl_plan_forms"]
+
+
+FORM_NAMES = {FORM_LANE: "lane", FORM_WAVE: "wave", FORM_HEAVY: "heavy"}
+
+
+def _tune_array(table) -> tuple:
+    """A tuning table (list of dicts alpha, n, ns_per_replicate[3]) as a ctypes array."""
+    if not table:
+        return None, 0
+    arr = (TuneEntry * len(table))()
+    for k, e in enumerate(table):
+        arr[k].alpha = float(e["alpha"])
+        arr[k].n = int(e["n"])
+        for f in range(3):
+            arr[k].ns_per_replicate[f] = float(e["ns_per_replicate"][f])
+    return arr, len(table)
+
+
+def _tune_list(arr) -> list:
+    return [{"alpha": e.alpha, "n": e.n, "ns_per_replicate": [e.ns_per_replicate[f] for f in range(3)]}
+            for e in arr]
+
+
+def plan_forms(cells: Sequence, table=None) -> list:
+    """The planner's form ("lane" / "wave" / "heavy") for each cell under a
+    tuning table (None: the built-in rule).  Host-only."""
+    arr, cnt = _tune_array(table)
+    cs = _cells(cells)
+    out = (C.c_int32 * len(cs))()
+    _check(lib().zpl_plan_forms(arr, cnt, cs, len(cs), out))
+    return [FORM_NAMES[int(v)] for v in out]
+
+
+def save_tuning(path, table):
+    import json
+    Path(path).write_text(json.dumps({"zpl_tuning": 1, "entries": table}, indent=1))
+
+
+def load_tuning(path) -> list:
+    import json
+    doc = json.loads(Path(path).read_text())
+    if doc.get("zpl_tuning") != 1:
+        raise ValueError("%s is not a zpl tuning table" % path)
+    return doc["entries"]
 
 
 def _check(st: int):
@@ -195,6 +250,20 @@ class Context:
         return out[:, :nq] if nq else None
 
     # -- timing ---------------------------------------------------------------
+    def autotune(self, alphas: Sequence[float], ns: Sequence[int], stream=None) -> list:
+        """Measure every eligible form on the grid alphas x ns and install the
+        table (zpl_autotune).  Returns it as a list of dicts, alpha-major."""
+        a = (C.c_double * len(alphas))(*[float(v) for v in alphas])
+        n = (C.c_int64 * len(ns))(*[int(v) for v in ns])
+        out = (TuneEntry * (len(alphas) * len(ns)))()
+        _check(lib().zpl_autotune(self._h, a, len(alphas), n, len(ns), out, _stream(stream)))
+        return _tune_list(out)
+
+    def set_tuning(self, table):
+        """Install a saved table (None or [] removes it)."""
+        arr, cnt = _tune_array(table)
+        _check(lib().zpl_set_tuning(self._h, arr, cnt))
+
     def set_timing(self, enable: bool = True):
         _check(lib().zpl_set_timing(self._h, 1 if enable else 0))
 

@@ -1,0 +1,121 @@
+"""Host logic of the tuned planner (zpl_plan_forms touches no device).
+
+The form choice never changes results (GPU tests check that every form gives
+the same bits); these tests check which form the planner picks: the built-in
+rule, the cheapest eligible form under a table, bilinear interpolation in
+(alpha, ln n), eligibility limits, fallbacks and table validation.
+"""
+import math
+
+import pytest
+
+from paper_1305_6738_amd import ZplError, load_tuning, plan_forms, save_tuning
+from inputs import table_slice
+
+
+def grid(alphas, ns, cost):
+    return [{"alpha": a, "n": n, "ns_per_replicate": list(cost(a, n))} for a in alphas for n in ns]
+
+
+def test_builtin_rule_on_table_slice():
+    # n = 1000: expected overflow of the per-lane list, n * P(X > 48), is at
+    # most 2 from alpha = 2.5 up (lane form); below, the wave form.
+    forms = plan_forms(table_slice(n=1000, R=1000))
+    assert forms == ["wave"] * 4 + ["lane"] * 5
+
+
+def test_builtin_rule_heavy_for_large_overflow():
+    # alpha = 1.2, n = 1e4: about 1,700 values above the wave form's 1024-bin
+    # histogram, more than its LDS overflow area holds
+    assert plan_forms([(1.2, 10000, 10, 1, 0)]) == ["heavy"]
+    assert plan_forms([(3.5, 10, 10, 1, 0)]) == ["lane"]
+    assert plan_forms([(3.5, 100000, 10, 1, 0)]) == ["wave"]  # lane form needs n <= 65535
+
+
+def test_table_picks_cheapest_form():
+    cells = [(2.5, 100, 10, 1, 0), (3.0, 1000, 10, 1, 1)]
+    heavy = grid([2.0, 3.5], [10, 10000], lambda a, n: (9.0, 9.0, 1.0))
+    wave = grid([2.0, 3.5], [10, 10000], lambda a, n: (9.0, 1.0, 5.0))
+    lane = grid([2.0, 3.5], [10, 10000], lambda a, n: (1.0, 2.0, 5.0))
+    assert plan_forms(cells, heavy) == ["heavy", "heavy"]
+    assert plan_forms(cells, wave) == ["wave", "wave"]
+    assert plan_forms(cells, lane) == ["lane", "lane"]
+
+
+def test_table_respects_eligibility():
+    # lane cheapest everywhere, but at alpha = 1.5, n = 1e4 a replicate has
+    # about 1,100 values above 48 (lane ineligible) and about 240 above 1024
+    # (wave still eligible)
+    t = grid([1.5, 3.5], [10, 100000], lambda a, n: (1.0, 2.0, 3.0))
+    assert plan_forms([(1.5, 10000, 10, 1, 0)], t) == ["wave"]
+    assert plan_forms([(1.2, 10000, 10, 1, 0)], t) == ["heavy"]
+    assert plan_forms([(3.0, 70000, 10, 1, 0)], t) == ["wave"]  # n > 65535
+
+
+def test_bilinear_interpolation_in_log_n():
+    # lane cost rises from 1 at n = 100 to 100 at n = 10,000, wave is 40
+    # throughout: lane wins below ln-interpolated crossover
+    # w = (40 - 1) / 99 of the way from ln 100 to ln 10,000
+    t = grid([3.0, 3.5], [100, 10000], lambda a, n: (1.0 if n == 100 else 100.0, 40.0, 1000.0))
+    w = 39.0 / 99.0
+    n_cross = math.exp(math.log(100) + w * (math.log(10000) - math.log(100)))
+    below, above = int(n_cross * 0.95), int(n_cross * 1.05)
+    assert plan_forms([(3.2, below, 10, 1, 0)], t) == ["lane"]
+    assert plan_forms([(3.2, above, 10, 1, 0)], t) == ["wave"]
+
+
+def test_bilinear_interpolation_in_alpha():
+    # wave cost 10 at alpha 2.5, 30 at 3.5; lane cost 20 throughout:
+    # crossover at alpha = 3.0
+    t = grid([2.5, 3.5], [10, 1000], lambda a, n: (20.0, 10.0 if a == 2.5 else 30.0, 1000.0))
+    assert plan_forms([(2.9, 500, 10, 1, 0)], t) == ["wave"]
+    assert plan_forms([(3.1, 500, 10, 1, 0)], t) == ["lane"]
+
+
+def test_clamped_outside_grid():
+    t = grid([2.5, 3.0], [100, 1000], lambda a, n: (1.0, 2.0, 3.0) if a == 3.0 else (2.0, 1.0, 3.0))
+    # alpha above the grid takes the last row (lane cheapest), below the first (wave)
+    assert plan_forms([(3.4, 300, 10, 1, 0)], t) == ["lane"]
+    assert plan_forms([(2.0, 300, 10, 1, 0)], t) == ["wave"]
+
+
+def test_unmeasured_corner_excludes_form():
+    # lane unmeasured (-1) at one corner of the cell's square: lane not chosen
+    def cost(a, n):
+        return (-1.0 if (a == 3.5 and n == 1000) else 1.0, 2.0, 3.0)
+    t = grid([2.5, 3.5], [100, 1000], cost)
+    assert plan_forms([(3.0, 300, 10, 1, 0)], t) == ["wave"]
+    assert plan_forms([(2.5, 100, 10, 1, 0)], t) == ["lane"]
+
+
+def test_all_unmeasured_falls_back_to_builtin():
+    t = grid([2.5, 3.5], [100, 1000], lambda a, n: (-1.0, -1.0, -1.0))
+    cells = table_slice(n=1000, R=10)
+    assert plan_forms(cells, t) == plan_forms(cells)
+
+
+@pytest.mark.parametrize("bad", ["not_grid", "alpha_order", "n_order", "nan", "alpha_range"])
+def test_invalid_tables_rejected(bad):
+    t = grid([2.5, 3.5], [100, 1000], lambda a, n: (1.0, 2.0, 3.0))
+    if bad == "not_grid":
+        t = t[:3]
+    elif bad == "alpha_order":
+        t = grid([3.5, 2.5], [100, 1000], lambda a, n: (1.0, 2.0, 3.0))
+    elif bad == "n_order":
+        t = grid([2.5, 3.5], [1000, 100], lambda a, n: (1.0, 2.0, 3.0))
+    elif bad == "nan":
+        t[1]["ns_per_replicate"][2] = float("nan")
+    elif bad == "alpha_range":
+        t = grid([0.5, 3.5], [100, 1000], lambda a, n: (1.0, 2.0, 3.0))
+    with pytest.raises(ZplError) as e:
+        plan_forms([(3.0, 300, 10, 1, 0)], t)
+    assert e.value.status == -1
+
+
+def test_save_load_roundtrip(tmp_path):
+    t = grid([2.5, 3.5], [100, 1000], lambda a, n: (a * n, -1.0, 0.125))
+    p = tmp_path / "tune.json"
+    save_tuning(p, t)
+    assert load_tuning(p) == t
+    cells = [(3.0, 300, 10, 1, 0), (2.6, 150, 10, 1, 1)]
+    assert plan_forms(cells, load_tuning(p)) == plan_forms(cells, t)
