@@ -1,8 +1,8 @@
 """Reference (oracle) implementation -- TEST INFRASTRUCTURE ONLY.
 
 A plain, slow CPU implementation (C, FP64) of the Monte Carlo KS critical-value
-method of Rappos & Robert (2013) for the pure discrete power law, used to check
-the GPU library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+method of Rappos & Robert (2013) for the pure discrete power law and its
+truncated variant on 1..K, used to check the GPU library.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
 baseline leg of ``bench.py`` may import this package; the product path never
 does.  The C source is ``zpl_oracle.c``; this module builds it with gcc and
 wraps it with ctypes.
@@ -106,6 +106,19 @@ def _bind(L):
         L.orc_bootstrap_pvalue.argtypes = [P(i64), i64, i64, u64, u32, P(d), P(d),
                                            P(d), P(u32), C.c_int]
         L.orc_bootstrap_pvalue.restype = C.c_int
+        ci = C.c_int
+        L.orc_tz_norm3.argtypes = [d, ci, P(d)]
+        L.orc_tz_cdf_table.argtypes = [d, ci, P(d)]
+        L.orc_tz_cdf_table.restype = ci
+        L.orc_tz_draw.argtypes = [P(d), ci, u64, u32, u32, u32]
+        L.orc_tz_draw.restype = i64
+        L.orc_tz_mle.argtypes = [d, ci, P(u32)]
+        L.orc_tz_mle.restype = d
+        L.orc_tz_fit.argtypes = [P(i64), i64, ci, P(d), P(d), P(d), P(u32)]
+        L.orc_tz_fit.restype = ci
+        L.orc_tz_simulate.argtypes = [d, ci, i64, u64, u32, i64, i64, P(d), P(d), P(d),
+                                      P(u32), P(u64), P(i64), ci]
+        L.orc_tz_simulate.restype = ci
     return L
 
 
@@ -212,3 +225,58 @@ def bootstrap_pvalue(x, B: int, seed: int, stream: int, nthreads: int = 0) -> di
     if rc != 0:
         raise ValueError("oracle bootstrap: invalid input")
     return {"alpha_hat": a.value, "D": D.value, "p_value": p.value, "flags": f.value}
+
+
+# ---- truncated law on 1..K (Sect. 1 with a finite upper limit) -------------
+
+def tz_norm3(g: float, K: int):
+    out = np.zeros(3)
+    lib().orc_tz_norm3(g, K, _ptr(out, C.c_double))
+    return out
+
+
+def tz_cdf_table(g: float, K: int) -> np.ndarray:
+    T = np.zeros(K)
+    if lib().orc_tz_cdf_table(g, K, _ptr(T, C.c_double)) != 0:
+        raise ValueError("K must be >= 2")
+    return T
+
+
+def tz_sample(g: float, K: int, n: int, seed: int, stream: int, rep: int) -> np.ndarray:
+    T = tz_cdf_table(g, K)
+    return np.array([lib().orc_tz_draw(_ptr(T, C.c_double), K, seed, stream, rep, i)
+                     for i in range(n)], dtype=np.int64)
+
+
+def tz_mle(m: float, K: int):
+    f = C.c_uint32(0)
+    g = lib().orc_tz_mle(m, K, C.byref(f))
+    return g, f.value
+
+
+def tz_fit(x, K: int) -> dict:
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    S, g, D = C.c_double(), C.c_double(), C.c_double()
+    f = C.c_uint32(0)
+    rc = lib().orc_tz_fit(_ptr(x, C.c_int64), x.size, K, C.byref(S), C.byref(g), C.byref(D),
+                          C.byref(f))
+    if rc != 0:
+        raise ValueError("oracle tz_fit: invalid dataset (n < 1, K < 2 or x outside 1..K)")
+    return {"S": S.value, "alpha_hat": g.value, "D": D.value, "flags": f.value}
+
+
+def tz_simulate(g: float, K: int, n: int, seed: int, stream: int, rep_lo: int, count: int,
+                nthreads: int = 0) -> dict:
+    D = np.zeros(count)
+    A = np.zeros(count)
+    S = np.zeros(count)
+    F = np.zeros(count, dtype=np.uint32)
+    FP = np.zeros(count, dtype=np.uint64)
+    XM = np.zeros(count, dtype=np.int64)
+    rc = lib().orc_tz_simulate(g, K, n, seed, stream, rep_lo, count,
+                               _ptr(D, C.c_double), _ptr(A, C.c_double), _ptr(S, C.c_double),
+                               _ptr(F, C.c_uint32), _ptr(FP, C.c_uint64), _ptr(XM, C.c_int64),
+                               nthreads)
+    if rc != 0:
+        raise ValueError("oracle tz_simulate: invalid cell")
+    return {"D": D, "alpha_hat": A, "S": S, "flags": F, "fp": FP, "xmax": XM}

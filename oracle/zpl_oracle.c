@@ -25,8 +25,8 @@
  *     the ">=" tie rule is the annex sampler's.
  *   - Tail (U > T[H]): rejection from the floored Pareto envelope on k >= H+1,
  *     conditioned on x < 2^63 (proposals at or above 2^63 are redrawn).
- *   - All-ones rule: if every draw is 1 (S = 0), S is replaced by ln 2, as the
- *     annex does ("as if one point was 2 instead of 1").
+ *   - All-ones rule: if every draw is 1 (S = 0), S is replaced by ln 2, the
+ *     annex's adjustment (one of the points is counted as a 2).
  *   - MLE solved to full FP64 precision (the annex stops at 1e-5).
  *   - KS sup taken over all integers t >= 0 (equivalently all real x).
  *   - Quantile: ascending order statistic at 0-based index floor(R*num/den),
@@ -508,5 +508,243 @@ int orc_bootstrap_pvalue(const int64_t *x, int64_t n, int64_t B, uint64_t seed,
   *D = d;
   *p = (double)ge / (double)B;
   *flags = f;
+  return 0;
+}
+
+/* ======================================================================== */
+/* The truncated law (Sect. 1 with a finite upper limit K; Tables 2-6):      */
+/* p(k) = k^-g / Z_K(g) for k = 1..K, Z_K(g) = sum_{k=1..K} k^-g.  Every sum */
+/* is taken directly from its definition (largest index first).  The law is  */
+/* defined for every real g; the tables use g > 0, and the MLE may fall at   */
+/* or below 0 for a sample with many large values.                           */
+/* ======================================================================== */
+
+/* suf[t] = sum_{k=t+1..K} k^-g for t = 0..K, so suf[0] = Z_K(g), suf[K] = 0. */
+static void tz_suffix(double g, int K, double *suf) {
+  suf[K] = 0.0;
+  for (int t = K - 1; t >= 0; --t) suf[t] = suf[t + 1] + pow((double)(t + 1), -g);
+}
+
+void orc_tz_norm3(double g, int K, double out[3]) {
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  for (int k = K; k >= 1; --k) {
+    const double t = pow((double)k, -g), l = log((double)k);
+    z0 += t;
+    z1 -= l * t;
+    z2 += l * l * t;
+  }
+  out[0] = z0;
+  out[1] = z1;
+  out[2] = z2;
+}
+
+int orc_tz_cdf_table(double g, int K, double *T) {
+  if (K < 2) return -1;
+  double *suf = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+  if (!suf) return -1;
+  tz_suffix(g, K, suf);
+  for (int k = 1; k <= K; ++k) T[k - 1] = 1.0 - suf[k] / suf[0];
+  free(suf);
+  return 0;
+}
+
+/* Draw i of replicate `rep`: the counter layout of the pure law's body     */
+/* draws; x = min{k in 1..K : T[k] >= U}.  T[K] = 1 > U, so there is no tail. */
+int64_t orc_tz_draw(const double *T, int K, uint64_t seed, uint32_t stream, uint32_t rep,
+                    uint32_t i) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {i >> 1, rep, stream, 0u};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  double U = (i & 1u) ? orc_u53(w[2], w[3]) : orc_u53(w[0], w[1]);
+  int lo = 1, hi = K;
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if (T[mid - 1] >= U)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return (int64_t)lo;
+}
+
+/* MLE (eq. 2 with the finite sums): mu(g) = -Z'/Z is the mean of ln X under */
+/* the law, strictly decreasing from ln K (g -> -inf) to 0 (g -> +inf), so   */
+/* the root of mu(g) = m is unique when 0 < m < ln K.  Newton with the same  */
+/* bisection safeguard as orc_mle, on the bracket [-64, 64]; no root in the  */
+/* bracket (e.g. every value equal to K) returns the bracket end, flagged    */
+/* NOCONV.                                                                    */
+double orc_tz_mle(double m, int K, uint32_t *flags) {
+  double lo = -64.0, hi = 64.0;
+  double z[3];
+  orc_tz_norm3(hi, K, z);
+  if (!(m > -z[1] / z[0])) { /* m at or below mu(64): the root is above 64 */
+    *flags |= ORC_FLAG_NOCONV;
+    return hi;
+  }
+  orc_tz_norm3(lo, K, z);
+  if (!(m < -z[1] / z[0])) { /* m at or above mu(-64) */
+    *flags |= ORC_FLAG_NOCONV;
+    return lo;
+  }
+  double a = 1.0 + 1.0 / m;
+  if (!(a > lo && a < hi)) a = 0.0;
+  for (int it = 0; it < 400; ++it) {
+    orc_tz_norm3(a, K, z);
+    double r1 = z[1] / z[0];
+    double gval = -r1 - m;
+    if (gval == 0.0) return a;
+    if (gval > 0.0)
+      lo = a;
+    else
+      hi = a;
+    double gp = -(z[2] / z[0] - r1 * r1);
+    double an = a - gval / gp;
+    if (!(an >= lo && an <= hi)) {
+      an = 0.5 * (lo + hi);
+      *flags |= ORC_FLAG_BISECT;
+    }
+    double scale = fabs(a) > 1.0 ? fabs(a) : 1.0;
+    if (fabs(an - a) <= 0x1p-50 * scale) return an;
+    a = an;
+  }
+  *flags |= ORC_FLAG_NOCONV;
+  return a;
+}
+
+/* KS distance (eq. 3) of a sorted sample under the truncated law at g, by  */
+/* the same reduction to distinct values as ks_sorted, F(t) = 1 - suf[t]/Z. */
+static double tz_ks_sorted(const int64_t *xs, int64_t n, double g, int K) {
+  double *suf = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+  tz_suffix(g, K, suf);
+  const double z = suf[0], dn = (double)n;
+  double D = 0.0;
+  int64_t i = 0;
+  while (i < n) {
+    int64_t v = xs[i];
+    int64_t below = i;
+    while (i < n && xs[i] == v) ++i;
+    int64_t upto = i;
+    double Fv = 1.0 - suf[v] / z;
+    double Fv1 = 1.0 - suf[v - 1] / z;
+    if (v - 1 == 0) Fv1 = 0.0;
+    double d1 = fabs((double)upto / dn - Fv);
+    double d2 = fabs((double)below / dn - Fv1);
+    if (d1 > D) D = d1;
+    if (d2 > D) D = d2;
+  }
+  free(suf);
+  return D;
+}
+
+static void tz_fit_sorted(const int64_t *xs, int64_t n, int K, double *S, double *ahat,
+                          double *D, uint32_t *flags) {
+  double s = neumaier_sum_log(xs, n);
+  if (s == 0.0) {
+    s = log(2.0);
+    *flags |= ORC_FLAG_ALL_ONES;
+  }
+  double a = orc_tz_mle(s / (double)n, K, flags);
+  *S = s;
+  *ahat = a;
+  *D = tz_ks_sorted(xs, n, a, K);
+}
+
+int orc_tz_fit(const int64_t *x, int64_t n, int K, double *S, double *g_hat, double *D,
+               uint32_t *flags) {
+  if (n < 1 || K < 2) return -1;
+  for (int64_t i = 0; i < n; ++i)
+    if (x[i] < 1 || x[i] > K) return -1;
+  int64_t *xs = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!xs) return -1;
+  memcpy(xs, x, sizeof(int64_t) * (size_t)n);
+  qsort(xs, (size_t)n, sizeof(int64_t), cmp_i64);
+  uint32_t f = 0;
+  tz_fit_sorted(xs, n, K, S, g_hat, D, &f);
+  *flags = f;
+  free(xs);
+  return 0;
+}
+
+typedef struct {
+  double g;
+  int K;
+  int64_t n;
+  uint64_t seed;
+  uint32_t stream;
+  int64_t rep_lo;
+  const double *T;
+  double *D, *ahat, *S;
+  uint32_t *flags;
+  uint64_t *fp;
+  int64_t *xmax;
+  int64_t begin, end;
+} tz_job;
+
+static void *tz_worker(void *arg) {
+  tz_job *j = (tz_job *)arg;
+  int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (size_t)j->n);
+  for (int64_t r = j->begin; r < j->end; ++r) {
+    uint32_t rep = (uint32_t)(j->rep_lo + r);
+    uint32_t f = 0;
+    uint64_t h = 0;
+    for (int64_t i = 0; i < j->n; ++i) {
+      x[i] = orc_tz_draw(j->T, j->K, j->seed, j->stream, rep, (uint32_t)i);
+      h += mix64((uint64_t)x[i]);
+    }
+    qsort(x, (size_t)j->n, sizeof(int64_t), cmp_i64);
+    double s, a, d;
+    tz_fit_sorted(x, j->n, j->K, &s, &a, &d, &f);
+    if (j->D) j->D[r] = d;
+    if (j->ahat) j->ahat[r] = a;
+    if (j->S) j->S[r] = s;
+    if (j->flags) j->flags[r] = f;
+    if (j->fp) j->fp[r] = h;
+    if (j->xmax) j->xmax[r] = x[j->n - 1];
+  }
+  free(x);
+  return NULL;
+}
+
+int orc_tz_simulate(double g, int K, int64_t n, uint64_t seed, uint32_t stream, int64_t rep_lo,
+                    int64_t count, double *D, double *g_hat, double *S, uint32_t *flags,
+                    uint64_t *fp, int64_t *xmax, int nthreads) {
+  if (n < 1 || count < 0 || K < 2 || !isfinite(g)) return -1;
+  double *T = (double *)malloc(sizeof(double) * (size_t)K);
+  if (!T || orc_tz_cdf_table(g, K, T) != 0) {
+    free(T);
+    return -1;
+  }
+  int nt = resolve_threads(nthreads);
+  if (nt > count) nt = count > 0 ? (int)count : 1;
+  tz_job *jobs = (tz_job *)calloc((size_t)nt, sizeof(tz_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)nt, sizeof(pthread_t));
+  for (int t = 0; t < nt; ++t) {
+    tz_job *j = &jobs[t];
+    j->g = g;
+    j->K = K;
+    j->n = n;
+    j->seed = seed;
+    j->stream = stream;
+    j->rep_lo = rep_lo;
+    j->T = T;
+    j->D = D;
+    j->ahat = g_hat;
+    j->S = S;
+    j->flags = flags;
+    j->fp = fp;
+    j->xmax = xmax;
+    j->begin = count * t / nt;
+    j->end = count * (t + 1) / nt;
+    if (nt == 1)
+      tz_worker(j);
+    else
+      pthread_create(&th[t], NULL, tz_worker, j);
+  }
+  if (nt > 1)
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  free(T);
   return 0;
 }

@@ -91,6 +91,32 @@ int orc_bootstrap_pvalue(const int64_t *x, int64_t n, int64_t B, uint64_t seed,
                          uint32_t stream, double *alpha_hat, double *D,
                          double *p, uint32_t *flags, int nthreads);
 
+/* ---- Truncated law on 1..K (Sect. 1 with a finite upper limit; Tables 2-6):
+ * p(k) = k^-g / Z_K(g), Z_K(g) = sum_{k=1..K} k^-g, any real g, K >= 2.
+ * Same random-number layout as the pure law's body draws; no tail. */
+
+/* Z_K(g), Z_K'(g), Z_K''(g) by direct summation. */
+void orc_tz_norm3(double g, int K, double out[3]);
+
+/* T[k-1] = F(k; g, K) for k = 1..K (T[K-1] = 1).  Returns -1 if K < 2. */
+int orc_tz_cdf_table(double g, int K, double *T);
+
+/* Draw i of replicate `rep`: min{k <= K : T[k] >= U}. */
+int64_t orc_tz_draw(const double *T, int K, uint64_t seed, uint32_t stream, uint32_t rep,
+                    uint32_t i);
+
+/* MLE of g on [-64, 64] from the mean log m (eq. 2 with finite sums). */
+double orc_tz_mle(double m, int K, uint32_t *flags);
+
+/* Fit one dataset (every x in 1..K).  Returns -1 on invalid input. */
+int orc_tz_fit(const int64_t *x, int64_t n, int K, double *S, double *g_hat, double *D,
+               uint32_t *flags);
+
+/* orc_simulate for the truncated law. */
+int orc_tz_simulate(double g, int K, int64_t n, uint64_t seed, uint32_t stream, int64_t rep_lo,
+                    int64_t count, double *D, double *g_hat, double *S, uint32_t *flags,
+                    uint64_t *fp, int64_t *xmax, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,215 @@
+"""Pins of the oracle's truncated law on 1..K (Sect. 1 with a finite upper
+limit; Tables 2-6), checked against what the paper and the mathematics fix:
+closed forms of the normaliser and of the MLE, numerical derivatives at high
+precision, the pmf, brute-force KS, a grid search of the log-likelihood, the
+paper's all-ones atoms, and Table 2-6 cells within Monte Carlo error.
+"""
+import math
+from fractions import Fraction
+from pathlib import Path
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def _tables():
+    out = {}
+    for line in (GOLDEN / "tables2to6_truncated.txt").read_text().splitlines():
+        if line.startswith("#") or not line.strip():
+            continue
+        K, g, n, *q = line.split()
+        out[(int(K), float(g), int(n))] = [float(v) for v in q]
+    return out
+
+
+def _Z_mp(g, K):
+    with mp.workdps(50):
+        return mp.fsum(mp.mpf(k) ** (-mp.mpf(g)) for k in range(1, K + 1))
+
+
+# --------------------------------------------------------------------------
+# Normaliser Z_K(g) and its derivatives
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("K", [2, 20, 1000])
+def test_norm_closed_forms(orc, K):
+    assert orc.tz_norm3(0.0, K)[0] == K
+    assert orc.tz_norm3(-1.0, K)[0] == K * (K + 1) // 2
+    # a recursive sum of K positive terms is within (K - 1) u of the exact sum
+    # (u = 2^-53), plus the rounding of each term (pow, about 1 ulp)
+    bound = (K + 1) * 2.0 ** -53
+    H = float(sum(Fraction(1, k) for k in range(1, K + 1)))
+    assert abs(orc.tz_norm3(1.0, K)[0] - H) <= bound * H
+    Z2 = float(sum(Fraction(1, k * k) for k in range(1, K + 1)))
+    assert abs(orc.tz_norm3(2.0, K)[0] - Z2) <= bound * Z2
+    # Z'(0) = -ln K!
+    assert abs(orc.tz_norm3(0.0, K)[1] + math.lgamma(K + 1)) <= 1e-13 * math.lgamma(K + 1)
+
+
+@pytest.mark.parametrize("g,K", [(0.25, 20), (1.0, 100), (2.5, 50), (-0.7, 30), (4.0, 1000)])
+def test_norm_derivatives_match_numerical_differentiation(orc, g, K):
+    z = orc.tz_norm3(g, K)
+    with mp.workdps(60):
+        f = lambda s: mp.fsum(mp.mpf(k) ** (-s) for k in range(1, K + 1))  # noqa: E731
+        d1 = mp.diff(f, mp.mpf(g), 1)
+        d2 = mp.diff(f, mp.mpf(g), 2)
+        z0 = f(mp.mpf(g))
+    assert abs(z[0] - float(z0)) <= 1e-14 * float(z0)
+    assert abs(z[1] - float(d1)) <= 1e-13 * abs(float(d1))
+    assert abs(z[2] - float(d2)) <= 1e-13 * abs(float(d2))
+
+
+@pytest.mark.parametrize("g,K", [(0.25, 20), (1.0, 50), (3.5, 1000), (-0.5, 100)])
+def test_cdf_table_is_the_cumulative_pmf(orc, g, K):
+    T = orc.tz_cdf_table(g, K)
+    assert T[-1] == 1.0
+    assert np.all(np.diff(T) > 0)
+    Z = _Z_mp(g, K)
+    with mp.workdps(50):
+        F = [mp.fsum(mp.mpf(j) ** (-mp.mpf(g)) for j in range(1, k + 1)) / Z for k in range(1, K + 1)]
+    assert max(abs(float(F[k]) - T[k]) for k in range(K)) < 4e-15
+
+
+# --------------------------------------------------------------------------
+# Sampler: the table search and its law
+# --------------------------------------------------------------------------
+def test_draws_are_the_table_search(orc):
+    for g, K in [(0.5, 20), (2.0, 100), (1.0, 1000)]:
+        T = orc.tz_cdf_table(g, K)
+        x = orc.tz_sample(g, K, 301, seed=9, stream=4, rep=17)
+        U = []
+        for i in range(301):
+            w = orc.philox([i >> 1, 17, 4, 0], [9, 0])
+            U.append(orc.u53(w[2], w[3]) if i & 1 else orc.u53(w[0], w[1]))
+        want = np.searchsorted(T, np.array(U), side="left") + 1
+        assert np.array_equal(x, want)
+        assert x.min() >= 1 and x.max() <= K
+
+
+@pytest.mark.parametrize("g,K", [(0.25, 20), (1.0, 50), (2.5, 100)])
+def test_draws_chi_square(orc, g, K):
+    from scipy import stats
+    r = orc.tz_simulate(g, K, 2000, 5, 1, 0, 40, nthreads=4)  # noqa: F841 (exercises the path)
+    x = np.concatenate([orc.tz_sample(g, K, 4000, 5, 1, rep) for rep in range(10)])
+    Z = float(_Z_mp(g, K))
+    p = np.array([k ** (-g) for k in range(1, K + 1)]) / Z
+    obs = np.bincount(x, minlength=K + 1)[1:]
+    # pool the sparse tail so every expected count is >= 20
+    exp = p * x.size
+    cut = K
+    while exp[cut - 1:].sum() < 20:
+        cut -= 1
+    o = np.concatenate([obs[:cut - 1], [obs[cut - 1:].sum()]])
+    e = np.concatenate([exp[:cut - 1], [exp[cut - 1:].sum()]])
+    chi2 = ((o - e) ** 2 / e).sum()
+    assert stats.chi2.sf(chi2, len(o) - 1) > 1e-3
+
+
+# --------------------------------------------------------------------------
+# MLE (eq. 2 with finite sums)
+# --------------------------------------------------------------------------
+def test_mle_closed_form_K2(orc):
+    # K = 2: mu(g) = ln2 2^-g / (1 + 2^-g), so g = log2((ln 2 - m) / m)
+    for x in ([1, 1, 1, 2], [1, 2], [1, 2, 2, 2], [1] * 9 + [2], [1, 2] * 3 + [2]):
+        r = orc.tz_fit(np.array(x), 2)
+        m = r["S"] / len(x)
+        want = math.log2((math.log(2) - m) / m)
+        assert abs(r["alpha_hat"] - want) <= 1e-13 * max(1.0, abs(want)), x
+    assert abs(orc.tz_fit(np.array([1, 2]), 2)["alpha_hat"]) < 1e-14
+
+
+def test_mle_uniform_sample_gives_zero(orc):
+    # each value once: mean ln x = ln(K!)/K = mu(0)
+    for K in (5, 20, 300):
+        r = orc.tz_fit(np.arange(1, K + 1), K)
+        assert abs(r["alpha_hat"]) < 1e-12
+        assert r["D"] < 1e-14
+
+
+def test_mle_grid_search_of_loglikelihood(orc):
+    rng = np.random.default_rng(3)
+    for K in (20, 50, 1000):
+        for _ in range(4):
+            x = np.minimum(rng.zipf(1.6, size=int(rng.integers(5, 40))), K)
+            r = orc.tz_fit(x, K)
+            S = r["S"]
+            n = len(x)
+            ll = lambda g: -g * S - n * math.log(float(_Z_mp(g, K)))  # noqa: E731
+            grid = np.linspace(r["alpha_hat"] - 0.5, r["alpha_hat"] + 0.5, 201)
+            best = grid[int(np.argmax([ll(g) for g in grid]))]
+            lo, hi = best - 0.005, best + 0.005
+            for _ in range(60):  # golden-section refinement
+                a = hi - (hi - lo) / 1.618033988749895
+                b = lo + (hi - lo) / 1.618033988749895
+                if ll(a) > ll(b):
+                    hi = b
+                else:
+                    lo = a
+            assert abs(0.5 * (lo + hi) - r["alpha_hat"]) < 1e-6, (K, x)
+
+
+def test_mle_no_root_is_flagged(orc):
+    r = orc.tz_fit(np.full(7, 20), 20)  # every value equal to K: mean ln x = ln K
+    assert r["flags"] & orc.FLAG_NOCONV
+    assert r["alpha_hat"] == -64.0
+
+
+def test_fit_rejects_values_outside_support(orc):
+    with pytest.raises(ValueError):
+        orc.tz_fit(np.array([1, 21]), 20)
+    with pytest.raises(ValueError):
+        orc.tz_fit(np.array([0, 2]), 20)
+    with pytest.raises(ValueError):
+        orc.tz_fit(np.array([1, 1]), 1)
+
+
+# --------------------------------------------------------------------------
+# KS (eq. 3): brute force over every t in 0..K
+# --------------------------------------------------------------------------
+def test_ks_bruteforce(orc):
+    rng = np.random.default_rng(12)
+    for K in (20, 100):
+        for _ in range(5):
+            x = np.minimum(rng.zipf(1.4, size=int(rng.integers(3, 30))), K)
+            r = orc.tz_fit(x, K)
+            g = r["alpha_hat"]
+            with mp.workdps(40):
+                Z = _Z_mp(g, K)
+                F = mp.mpf(0)
+                best = mp.mpf(0)
+                xs = np.sort(x)
+                for t in range(1, K + 1):
+                    F += mp.mpf(t) ** (-mp.mpf(g)) / Z
+                    Sn = mp.mpf(int(np.searchsorted(xs, t, side="right"))) / len(x)
+                    best = max(best, abs(F - Sn))
+            assert abs(r["D"] - float(best)) < 1e-14, (K, x)
+
+
+# --------------------------------------------------------------------------
+# The paper's tables
+# --------------------------------------------------------------------------
+def test_all_ones_atoms_match_tables_2_to_6(orc):
+    """An all-ones replicate has D = 1 - F(1; g_hat) with g_hat from S = ln 2:
+    the printed atoms (.0821 at K = 20, .0819 above; .0440 at N = 20)."""
+    tab = _tables()
+    for K in (20, 50, 100, 500, 1000):
+        for n, cells in [(10, [(4.0, 0), (4.0, 1)]), (20, [(4.0, 0)])]:
+            r = orc.tz_fit(np.ones(n, dtype=np.int64), K)
+            assert r["flags"] & orc.FLAG_ALL_ONES
+            Z = _Z_mp(r["alpha_hat"], K)
+            assert abs(r["D"] - float(1 - 1 / Z)) < 1e-15
+            for g, qi in cells:
+                assert round(r["D"], 4) == tab[(K, g, n)][qi], (K, n, g, qi)
+
+
+@pytest.mark.parametrize("K,g,n,R,tol", [(20, 1.0, 100, 20000, 0.0012), (50, 0.5, 50, 20000, 0.0015),
+                                         (100, 2.0, 100, 20000, 0.0012), (1000, 1.5, 500, 6000, 0.0010),
+                                         (500, 3.0, 30, 20000, 0.0025)])
+def test_tables_2_to_6_statistical(orc, K, g, n, R, tol):
+    want = _tables()[(K, g, n)]
+    r = orc.tz_simulate(g, K, n, 2024, 0, 0, R)
+    for qi, (num, den) in enumerate([(9, 10), (95, 100)]):
+        got = orc.quantile(r["D"], num, den)
+        assert abs(got - want[qi]) <= tol, (K, g, n, qi, got, want[qi])
