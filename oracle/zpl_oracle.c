@@ -573,7 +573,10 @@ int64_t orc_tz_draw(const double *T, int K, uint64_t seed, uint32_t stream, uint
 /* the root of mu(g) = m is unique when 0 < m < ln K.  Newton with the same  */
 /* bisection safeguard as orc_mle, on the bracket [-64, 64]; no root in the  */
 /* bracket (e.g. every value equal to K) returns the bracket end, flagged    */
-/* NOCONV.                                                                    */
+/* NOCONV.  The iteration stops after a step of at most 2^-40 max(|g|, 1)    */
+/* and returns the next iterate: Newton converges quadratically, so that    */
+/* iterate sits at the rounding noise of mu, while a tighter threshold can  */
+/* lie below that noise when |g| < 1 and never be met.                      */
 double orc_tz_mle(double m, int K, uint32_t *flags) {
   double lo = -64.0, hi = 64.0;
   double z[3];
@@ -605,7 +608,7 @@ double orc_tz_mle(double m, int K, uint32_t *flags) {
       *flags |= ORC_FLAG_BISECT;
     }
     double scale = fabs(a) > 1.0 ? fabs(a) : 1.0;
-    if (fabs(an - a) <= 0x1p-50 * scale) return an;
+    if (fabs(an - a) <= 0x1p-40 * scale) return an;
     a = an;
   }
   *flags |= ORC_FLAG_NOCONV;
