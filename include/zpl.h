@@ -71,18 +71,25 @@ typedef int32_t zpl_status;
 
 typedef struct zpl_ctx zpl_ctx;
 
-/* One (alpha, n) cell of a critical-value table (Sect. 3, Table 1): R
- * replicates of n draws at exponent alpha (> 1), random stream (seed,
- * stream).  Replicate r of the cell is the same whatever else is computed
- * alongside it.  alpha must lie in [1.01, 64]: closer to 1 the law puts so
- * much mass at or above 2^63 that the capped tail sampler slows down. */
+/* One (alpha, n) cell of a critical-value table (Sect. 3; Table 1 for the
+ * pure law, Tables 2-6 for the truncated one): R replicates of n draws at
+ * exponent alpha, random stream (seed, stream).  Replicate r of the cell is
+ * the same whatever else is computed alongside it.
+ *   kmax = 0: the pure law of eq. (1) on k >= 1; alpha must lie in
+ *             [1.01, 64] (closer to 1 the law puts so much mass at or above
+ *             2^63 that the capped tail sampler slows down).
+ *   kmax = K in 2..4096: the truncated law p(k) = k^-alpha / sum_{j<=K} j^-alpha
+ *             on k = 1..K (Sect. 1 with a finite upper limit); alpha may be
+ *             any value in [-64, 64], and alpha_hat is solved on [-64, 64]
+ *             (ZPL_FLAG_NOCONV and the bracket end when the sample's mean log
+ *             has no root there, e.g. every value equal to K). */
 typedef struct zpl_cell {
   double alpha;
   int64_t n;
   int64_t replicates;
   uint64_t seed;
   uint32_t stream;
-  uint32_t reserved; /* must be 0 */
+  uint32_t kmax;
 } zpl_cell;
 
 /* Launch form of zpl_simulate_cells. */
@@ -190,6 +197,14 @@ zpl_status zpl_get_timing(zpl_ctx *ctx, double *ms4);
 zpl_status zpl_fit(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
                    double *alpha_hat, double *D, uint32_t *flags, void *stream);
 
+/* zpl_fit under the truncated law on 1..kmax (2 <= kmax <= 4096; every x in
+ * 1..kmax, else ZPL_EINVAL): alpha_hat on [-64, 64] from eq. (2) with the
+ * finite sums, and D from eq. (3) with the truncated CDF.  ZPL_ENOCONV
+ * (outputs still set) if the mean log has no root in the bracket. */
+zpl_status zpl_fit_truncated(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
+                             uint32_t kmax, double *alpha_hat, double *D, uint32_t *flags,
+                             void *stream);
+
 /* Bespoke cutoff of Sect. 4 as a parametric-bootstrap p-value: fit x, then
  * simulate B replicates of n draws at alpha_hat (random stream (seed,
  * stream_id)), refit each by MLE (the tables apply only to MLE fits), and
@@ -249,18 +264,20 @@ zpl_status zpl_serve_poll(zpl_ctx *ctx, uint64_t ticket, int32_t wait_ms,
 /* Finish the queued requests and stop the scheduler. */
 zpl_status zpl_serve_stop(zpl_ctx *ctx);
 
-/* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, n, seed,
- * stream_id) in draw order, for checking the sampler bit for bit.
+/* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, kmax, n,
+ * seed, stream_id) in draw order, for checking the sampler bit for bit
+ * (alpha and kmax as in zpl_cell).
  *   x_out     device [count * n] int64;  flags_out device [count] uint32
  *             (ZPL_FLAG_TAIL_CAPPED per replicate).
  * Asynchronous on `stream`. */
-zpl_status zpl_sample_draws(zpl_ctx *ctx, double alpha, int64_t n, uint64_t seed,
+zpl_status zpl_sample_draws(zpl_ctx *ctx, double alpha, uint32_t kmax, int64_t n, uint64_t seed,
                             uint32_t stream_id, int64_t rep_lo, int64_t count,
                             int64_t *x_out, uint32_t *flags_out, void *stream);
 
-/* The FP64 CDF table F(k; alpha), k = 1..4096, the sampler searches.
+/* The FP64 CDF table F(k; alpha), k = 1..4096, the sampler searches (the
+ * truncated law's for kmax > 0, with F(k) = 1 for k >= kmax).
  *   T_out  device [4096].  Asynchronous on `stream`. */
-zpl_status zpl_cdf_table(zpl_ctx *ctx, double alpha, double *T_out, void *stream);
+zpl_status zpl_cdf_table(zpl_ctx *ctx, double alpha, uint32_t kmax, double *T_out, void *stream);
 
 #ifdef __cplusplus
 }

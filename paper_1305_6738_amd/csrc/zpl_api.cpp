@@ -73,8 +73,19 @@ const HostLn& host_ln() {
 // exponents are never below about 1.023: mean ln x < ln 2^63.)
 constexpr double kMinAlpha = 1.01;
 
-// P(X > h) under exponent a.
-double tail_prob(double a, int h) {
+// P(X > h) under exponent a: the pure law (K = 0) or the truncated law on
+// 1..K (finite sums).
+double tail_prob(double a, int h, uint32_t K = 0) {
+  if (K > 0) {
+    if ((uint32_t)h >= K) return 0.0;
+    double z = 0.0, t = 0.0;
+    for (int k = (int)K; k >= 1; --k) {
+      const double w = std::exp(-a * host_ln().v[k]);
+      z += w;
+      if (k > h) t += w;
+    }
+    return t / z;
+  }
   double suf[17];
   survival_head(a, host_ln().v.data(), suf);
   const double zt = h >= 16 ? survival_next(a, h, host_ln().v.data()) : suf[h];
@@ -279,21 +290,21 @@ struct Plan {
 // Forms a tuned planner may pick: the lane form only where a replicate rarely
 // overflows its per-lane list, the wave form only where the LDS overflow
 // area almost surely holds a replicate's large values.
-bool form_eligible(uint32_t m, double alpha, int64_t n) {
-  if (m == kModeLane) return n <= 65535 && (double)n * tail_prob(alpha, kHLB) <= 2.5;
+bool form_eligible(uint32_t m, double alpha, int64_t n, uint32_t K = 0) {
+  if (m == kModeLane) return n <= 65535 && (double)n * tail_prob(alpha, kHLB, K) <= 2.5;
   if (m == kModeWave) {
-    const double mu = (double)n * tail_prob(alpha, kHW);
+    const double mu = (double)n * tail_prob(alpha, kHW, K);
     return mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)kCW;
   }
   return true;
 }
 
-uint32_t choose_form(double alpha, int64_t n, const Tuning* t) {
+uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0) {
   if (t && !t->empty()) {
     int best = -1;
     double bc = 0.0;
     for (int f = 0; f < 3; ++f) {
-      if (!form_eligible((uint32_t)f, alpha, n)) continue;
+      if (!form_eligible((uint32_t)f, alpha, n, K)) continue;
       const double v = tuned_cost(*t, f, alpha, n);
       if (v >= 0.0 && (best < 0 || v < bc)) {
         best = f;
@@ -302,8 +313,8 @@ uint32_t choose_form(double alpha, int64_t n, const Tuning* t) {
     }
     if (best >= 0) return (uint32_t)best;
   }
-  if (n <= 65535 && (double)n * tail_prob(alpha, kHLB) <= 2.0) return kModeLane;
-  if (form_eligible(kModeWave, alpha, n)) return kModeWave;
+  if (n <= 65535 && (double)n * tail_prob(alpha, kHLB, K) <= 2.0) return kModeLane;
+  if (form_eligible(kModeWave, alpha, n, K)) return kModeWave;
   return kModeHeavy;
 }
 
@@ -315,14 +326,20 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
   P.cell_unit_end.assign(n_cells, 0);
   for (int i = 0; i < n_cells; ++i) {
     const zpl_cell& z = cells[i];
-    if (!(z.alpha >= kMinAlpha) || !(z.alpha <= 64.0))
-      return fail(ZPL_EINVAL, "cell %d: alpha must be in [1.01, 64], got %g", i, z.alpha);
+    if (z.kmax == 0) {
+      if (!(z.alpha >= kMinAlpha) || !(z.alpha <= 64.0))
+        return fail(ZPL_EINVAL, "cell %d: alpha must be in [1.01, 64], got %g", i, z.alpha);
+    } else {
+      if (z.kmax < 2 || z.kmax > (uint32_t)kH)
+        return fail(ZPL_EINVAL, "cell %d: kmax must be 0 or in [2, %d], got %u", i, kH, z.kmax);
+      if (!(z.alpha >= -64.0) || !(z.alpha <= 64.0))
+        return fail(ZPL_EINVAL, "cell %d: alpha must be in [-64, 64], got %g", i, z.alpha);
+    }
     if (z.n < 1 || z.n > ((int64_t)1 << 31))
       return fail(ZPL_EINVAL, "cell %d: n must be in [1, 2^31], got %lld", i, (long long)z.n);
     if (z.replicates < 1 || z.replicates > ((int64_t)1 << 32))
       return fail(ZPL_EINVAL, "cell %d: replicates must be in [1, 2^32], got %lld", i,
                   (long long)z.replicates);
-    if (z.reserved != 0) return fail(ZPL_EINVAL, "cell %d: reserved field must be 0", i);
     DevCell& d = P.cells[i];
     std::memset(&d, 0, sizeof d);
     d.alpha = z.alpha;
@@ -332,6 +349,7 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
     d.k0 = (uint32_t)z.seed;
     d.k1 = (uint32_t)(z.seed >> 32);
     d.stream = z.stream;
+    d.K = z.kmax;
     uint32_t m;
     switch (form) {
       case ZPL_FORM_LANE:
@@ -340,7 +358,7 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
         break;
       case ZPL_FORM_WAVE: m = kModeWave; break;
       case ZPL_FORM_HEAVY: m = kModeHeavy; break;
-      default: m = choose_form(z.alpha, z.n, tune);
+      default: m = choose_form(z.alpha, z.n, tune, z.kmax);
     }
     d.mode = m;
     P.total_R += z.replicates;
@@ -669,7 +687,7 @@ zpl_status autotune_grid(zpl_ctx* c, const double* alphas, int na, const int64_t
 }
 
 zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, double* ahat,
-                      double* D, uint32_t* flags, uint32_t* status) {
+                      double* D, uint32_t* flags, uint32_t* status, uint32_t K = 0) {
   const int64_t stride = heavy_stride(n);
   ZPL_TRY(ensure(c, c->fit_ptrs, sizeof(int64_t*)));
   ZPL_TRY(ensure(c, c->fit_ns, sizeof(int64_t)));
@@ -687,7 +705,7 @@ zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, d
   uint32_t* of = (uint32_t*)(o + 2);
   HIP_TRY(launch_fit(1, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, 1,
                      c->ln, (int64_t*)c->heavy.p, stride, o, o + 1, of,
-                     (uint32_t*)c->fit_st.p, s));
+                     (uint32_t*)c->fit_st.p, K, s));
   char* hp = (char*)c->pin + 16;
   HIP_TRY(hipMemcpyAsync(hp, o, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(hp + 16, of, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -817,7 +835,8 @@ zpl_status Server::process(std::vector<Req*>& batch) {
   double* fd = fa + nb;
   uint32_t* ff = (uint32_t*)(fd + nb);
   HIP_TRY(launch_fit(grid, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, nb,
-                     c->ln, (int64_t*)c->heavy.p, stride, fa, fd, ff, (uint32_t*)c->fit_st.p, s));
+                     c->ln, (int64_t*)c->heavy.p, stride, fa, fd, ff, (uint32_t*)c->fit_st.p, 0u,
+                     s));
   double* ha = (double*)(pns + nb);
   double* hd = ha + nb;
   uint32_t* hf = (uint32_t*)(hd + nb);
@@ -1093,6 +1112,26 @@ zpl_status zpl_fit(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
   return ZPL_OK;
 }
 
+zpl_status zpl_fit_truncated(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                             uint32_t kmax, double* alpha_hat, double* D, uint32_t* flags,
+                             void* stream) {
+  g_err.clear();
+  if (!c || !x || !alpha_hat || !D || !flags) return fail(ZPL_EINVAL, "NULL argument");
+  if (n < 1 || n > ((int64_t)1 << 31)) return fail(ZPL_EINVAL, "n must be in [1, 2^31]");
+  if (kmax < 2 || kmax > (uint32_t)kH)
+    return fail(ZPL_EINVAL, "kmax must be in [2, %d], got %u", kH, kmax);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t* xd;
+  ZPL_TRY(stage_x(c, x, n, x_on_device, s, &xd));
+  uint32_t st = 0;
+  ZPL_TRY(fit_device(c, xd, n, s, alpha_hat, D, flags, &st, kmax));
+  if (st & kErrBadValue) return fail(ZPL_EINVAL, "every x must be in [1, %u]", kmax);
+  if (*flags & ZPL_FLAG_NOCONV)
+    return fail(ZPL_ENOCONV, "the mean log has no root in [-64, 64] (or the iteration cap was reached)");
+  return ZPL_OK;
+}
+
 zpl_status zpl_bootstrap_pvalue(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
                                 int64_t B, uint64_t seed, uint32_t stream_id,
                                 double* alpha_hat, double* D, double* p_value,
@@ -1227,21 +1266,19 @@ zpl_status zpl_serve_stop(zpl_ctx* c) {
   return ZPL_OK;
 }
 
-zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
+zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t n, uint64_t seed,
                             uint32_t stream_id, int64_t rep_lo, int64_t count,
                             int64_t* x_out, uint32_t* flags_out, void* stream) {
   g_err.clear();
   if (!c || !x_out || !flags_out) return fail(ZPL_EINVAL, "NULL argument");
-  if (!(alpha >= kMinAlpha) || !(alpha <= 64.0))
-    return fail(ZPL_EINVAL, "alpha must be in [1.01, 64]");
   if (n < 1 || count < 1 || rep_lo < 0 || rep_lo + count > ((int64_t)1 << 32) ||
       n > ((int64_t)1 << 31))
     return fail(ZPL_EINVAL, "bad n / replicate range");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  zpl_cell z = {alpha, n, count, seed, stream_id, 0};
+  zpl_cell z = {alpha, n, count, seed, stream_id, kmax};
   Plan P;
-  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha and kmax
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
@@ -1259,16 +1296,14 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, int64_t n, uint64_t seed,
   return ZPL_OK;
 }
 
-zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, double* T_out, void* stream) {
+zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, uint32_t kmax, double* T_out, void* stream) {
   g_err.clear();
   if (!c || !T_out) return fail(ZPL_EINVAL, "NULL argument");
-  if (!(alpha >= kMinAlpha) || !(alpha <= 64.0))
-    return fail(ZPL_EINVAL, "alpha must be in [1.01, 64]");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  zpl_cell z = {alpha, 1, 1, 0, 0, 0};
+  zpl_cell z = {alpha, 1, 1, 0, 0, kmax};
   Plan P;
-  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha and kmax
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));

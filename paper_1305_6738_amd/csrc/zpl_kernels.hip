@@ -144,13 +144,15 @@ __device__ __forceinline__ int64_t resolve(const QEntry& e, uint32_t rep, const 
 // |Z(v)/zeta - (n - C(v))/n| and |Z(v-1)/zeta - (n - C(v-1))/n|: between
 // sample values S_n is flat and F rises, so the sup over all t is reached at
 // a sample value or one below it.  Values <= 16 use the precomputed head
-// suf[], larger ones the Euler-Maclaurin tail.  Src yields the distinct
-// values: small(v) returns the count of v for v = 1..16 in order, then
-// next_large() returns the remaining (value, count) pairs ascending.
+// suf[]; for larger ones Z(v) comes from the Euler-Maclaurin tail and
+// Z(v-1) = Z(v) + v^-a.  Src yields the distinct values: small(v) returns
+// the count of v for v = 1..16 in order, then next_large() returns the
+// remaining (value, count) pairs ascending.
 // ---------------------------------------------------------------------------
 template <class Src>
-__device__ __forceinline__ double ks_distance(Src& src, double a, const double (&suf)[17],
-                                              int64_t n, const double* __restrict__ ln) {
+__device__ __forceinline__ double ks_distance(Src& src, const EmCoef& E,
+                                              const double (&suf)[17], int64_t n,
+                                              const double* __restrict__ ln) {
   const double iz = 1.0 / suf[0], idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0;
@@ -169,10 +171,10 @@ __device__ __forceinline__ double ks_distance(Src& src, double a, const double (
   int64_t v;
   uint32_t c;
   while (src.next_large(v, c)) {
-    const double zv1 = (v - 1 == vprev) ? zprev : survival_at(a, v, ln);
+    const double zv = survival_next(E, v, ln);
+    const double zv1 = (v - 1 == vprev) ? zprev : zv + pow_neg(E.s, ln_value(v, ln));
     const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
     C += c;
-    const double zv = survival_next(a, v, ln);
     const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
     D = fmax(D, fmax(t1, t2));
     zprev = zv;
@@ -181,11 +183,50 @@ __device__ __forceinline__ double ks_distance(Src& src, double a, const double (
   return D;
 }
 
-// S (with the paper's all-ones rule), alpha_hat (eq. 2) and D (eq. 3).
+// KS distance (eq. 3) under the truncated law on 1..K: F(t) = P(t)/Z with
+// P(t) = sum_{k<=t} k^-a accumulated in ascending k as the distinct values
+// are visited, and Z = Z_K(a) summed from K down.  Same terms as
+// ks_distance: |F(v) - C(v)/n| and |F(v-1) - C(v-1)/n| per distinct v.
+template <class Src>
+__device__ __forceinline__ double ks_distance_trunc(Src& src, double a, uint32_t K, int64_t n,
+                                                    const double* __restrict__ ln) {
+  double Z = 0.0;
+  for (int k = (int)K; k >= 2; --k) Z += pow_neg(a, ln[k]);
+  Z += 1.0;
+  const double iz = 1.0 / Z, idn = 1.0 / (double)n;
+  int64_t C = 0;
+  double D = 0.0, P = 0.0;
+  int64_t k = 0;  // P = P(k)
+  auto term = [&](int64_t v, uint32_t c) {
+    while (k < v - 1) {
+      ++k;
+      P += k == 1 ? 1.0 : pow_neg(a, ln[k]);
+    }
+    const double t2 = fabs(fma(P, iz, -(double)C * idn));
+    ++k;
+    P += k == 1 ? 1.0 : pow_neg(a, ln[k]);
+    C += c;
+    const double t1 = fabs(fma(P, iz, -(double)C * idn));
+    D = fmax(D, fmax(t1, t2));
+  };
+#pragma unroll
+  for (int v = 1; v <= 16; ++v) {
+    const uint32_t c = src.small(v);
+    if (c) term(v, c);
+  }
+  int64_t v;
+  uint32_t c;
+  while (src.next_large(v, c)) term(v, c);
+  return D;
+}
+
+// S (with the paper's all-ones rule), alpha_hat (eq. 2) and D (eq. 3), for
+// the pure law (K = 0) or the truncated law on 1..K.
 template <class Src>
 __device__ __forceinline__ void finish_replicate(Src& src, const U128& S, int64_t n,
                                                  uint32_t fl, const double* __restrict__ ln,
-                                                 double& ahat, double& D, uint32_t& flags) {
+                                                 uint32_t K, double& ahat, double& D,
+                                                 uint32_t& flags) {
   double Sd;
   if (S.lo == 0 && S.hi == 0) {  // every draw was 1: S := ln 2
     Sd = ln[2];
@@ -193,11 +234,18 @@ __device__ __forceinline__ void finish_replicate(Src& src, const U128& S, int64_
   } else {
     Sd = u128_to_S(S);
   }
-  const double a = mle_alpha(Sd / (double)n, ln, &fl);
-  double suf[17];
-  survival_head(a, ln, suf);
-  D = ks_distance(src, a, suf, n, ln);
-  ahat = a;
+  if (K) {
+    const double a = mle_alpha_trunc(Sd / (double)n, K, ln, &fl);
+    D = ks_distance_trunc(src, a, K, n, ln);
+    ahat = a;
+  } else {
+    const double a = mle_alpha(Sd / (double)n, ln, &fl);
+    const EmCoef E = em_coef(a);
+    double suf[17];
+    survival_head(E, ln, suf);
+    D = ks_distance(src, E, suf, n, ln);
+    ahat = a;
+  }
   flags = fl;
 }
 
@@ -252,24 +300,149 @@ struct LaneSrc {
   }
 };
 
-// A compact ascending (value, count) list.
+// A compact ascending (value, count) list in global memory.  The entry after
+// the one being consumed is loaded ahead, so its latency overlaps the FP64
+// work of the current value.
 struct ListSrc {
   const int64_t* vals;
   const uint32_t* cnts;
   int len;
-  int p;
+  int p;  // index of the entry held in (nv, nc)
+  int64_t nv;
+  uint32_t nc;
+  __device__ __forceinline__ ListSrc(const int64_t* v, const uint32_t* c, int l)
+      : vals(v), cnts(c), len(l), p(0), nv(0), nc(0u) {
+    if (len > 0) {
+      nv = vals[0];
+      nc = cnts[0];
+    }
+  }
+  __device__ __forceinline__ void advance() {
+    ++p;
+    if (p < len) {
+      nv = vals[p];
+      nc = cnts[p];
+    }
+  }
   __device__ __forceinline__ uint32_t small(int v) {
-    if (p < len && vals[p] == (int64_t)v) return cnts[p++];
+    if (p < len && nv == (int64_t)v) {
+      const uint32_t c = nc;
+      advance();
+      return c;
+    }
     return 0u;
   }
   __device__ __forceinline__ bool next_large(int64_t& v, uint32_t& c) {
     if (p >= len) return false;
-    v = vals[p];
-    c = cnts[p];
-    ++p;
+    v = nv;
+    c = nc;
+    advance();
     return true;
   }
 };
+
+// ks_distance over a compact ascending list in global memory, by a whole
+// wave: the values <= 16 are taken by every lane as in ks_distance, the rest
+// is cut into 64 contiguous chunks, one per lane.  A wave prefix sum gives
+// each chunk its count C of draws below it, and a chunk whose first value v
+// follows its predecessor (v - 1 = previous value) recomputes the same
+// zeta(a, v) the sequential loop would have carried over, so every term, and
+// hence the maximum, is bit-identical to ks_distance.  Returns D on every lane.
+__device__ __forceinline__ uint64_t wave_excl_scan_u64(uint64_t v, int lane) {
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    if (lane >= d) x += ((uint64_t)hi << 32) | lo;
+  }
+  return x - v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    const uint64_t b = shfl_xor_u64((uint64_t)__double_as_longlong(v), m);
+    v = fmax(v, __longlong_as_double((long long)b));
+  }
+  return v;
+}
+
+__device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_t* __restrict__ lc,
+                                   int len, const EmCoef& E, const double (&suf)[17], int64_t n,
+                                   const double* __restrict__ ln, int lane) {
+  const double iz = 1.0 / suf[0], idn = 1.0 / (double)n;
+  int64_t C = 0;
+  double D = 0.0;
+  int p = 0;
+#pragma unroll
+  for (int v = 1; v <= 16; ++v) {
+    if (p < len && lv[p] == (int64_t)v) {
+      const double t2 = fabs(fma(suf[v - 1], iz, -(double)(n - C) * idn));
+      C += lc[p];
+      const double t1 = fabs(fma(suf[v], iz, -(double)(n - C) * idn));
+      D = fmax(D, fmax(t1, t2));
+      ++p;
+    }
+  }
+  const int p16 = p;
+  const int chunk = (len - p16 + 63) / 64;
+  const int q0 = p16 + lane * chunk;
+  const int q1 = min(q0 + chunk, len);
+  uint64_t cs = 0;
+  for (int q = q0; q < q1; ++q) cs += lc[q];
+  C += (int64_t)wave_excl_scan_u64(cs, lane);
+  if (q0 < q1) {
+    int64_t vprev = q0 == p16 ? 16 : lv[q0 - 1];
+    double zprev = suf[16];
+    bool have = q0 == p16;  // zprev is zeta(a, vprev + 1)
+    for (int q = q0; q < q1; ++q) {
+      const int64_t v = lv[q];
+      const double zv = survival_next(E, v, ln);
+      double zv1;
+      if (v - 1 == vprev)
+        zv1 = have ? zprev : survival_next(E, vprev, ln);
+      else
+        zv1 = zv + pow_neg(E.s, ln_value(v, ln));
+      const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
+      C += lc[q];
+      const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
+      D = fmax(D, fmax(t1, t2));
+      zprev = zv;
+      vprev = v;
+      have = true;
+    }
+  }
+  return wave_max_f64(D);
+}
+
+// finish_replicate by a whole wave over a global list (heavy form, fit):
+// every lane solves the same MLE; the KS is split over the lanes.
+__device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const uint32_t* lc, int len,
+                                                      const U128& S, int64_t n, uint32_t fl,
+                                                      const double* __restrict__ ln, int lane,
+                                                      uint32_t K, double& ahat, double& D,
+                                                      uint32_t& flags) {
+  if (K) {  // O(K) per replicate either way: every lane runs the same sequence
+    ListSrc src(lv, lc, len);
+    finish_replicate(src, S, n, fl, ln, K, ahat, D, flags);
+    return;
+  }
+  double Sd;
+  if (S.lo == 0 && S.hi == 0) {
+    Sd = ln[2];
+    fl |= kFlagAllOnes;
+  } else {
+    Sd = u128_to_S(S);
+  }
+  const double a = mle_alpha(Sd / (double)n, ln, &fl);
+  const EmCoef E = em_coef(a);
+  double suf[17];
+  survival_head(E, ln, suf);
+  D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane);
+  ahat = a;
+  flags = fl;
+}
 
 // ---------------------------------------------------------------------------
 // Wave-cooperative helpers for the wave and heavy forms.
@@ -309,6 +482,13 @@ __device__ __forceinline__ int lower_bound_i64(const int64_t* a, int n, int64_t 
   return lo;
 }
 
+// Ordering of one wave's global-memory stores before its later loads.
+__device__ __forceinline__ void wave_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Builds the compact (value, count) list of one replicate from a histogram
 // of values 1..nbins (hist[v-1]) and a sorted overflow array ov[0..oc),
 // appending at lv/lc (length returned).  Also returns, identical on every
@@ -320,50 +500,51 @@ struct Summary {
   int len;
 };
 
-template <class Sync>
 __device__ Summary build_list(const uint32_t* hist, int nbins, const int64_t* ov, int oc,
                               int64_t* lv, uint32_t* lc, int lane,
-                              const double* __restrict__ ln, Sync sync) {
-  U128 S = {0, 0};
-  uint64_t fp = 0;
-  int64_t xmax = 0;
+                              const double* __restrict__ ln) {
+  const uint64_t below = lanes_below(lane);
   int len = 0;
-  for (int b0 = 0; b0 < nbins; b0 += 64) {
-    const int v = b0 + lane + 1;
-    const uint32_t c = (v <= nbins) ? hist[v - 1] : 0u;
-    if (c) {
-      u128_add_mul(S, c, ln_fixed(v, ln));
-      fp += (uint64_t)c * mix64((uint64_t)v);
-      xmax = v;
-    }
-    const uint64_t m = __ballot(c != 0u);
-    if (c) {
-      const int pos = len + __popcll(m & lanes_below(lane));
-      lv[pos] = v;
-      lc[pos] = c;
-    }
-    len += __popcll(m);
+  // 1. non-zero histogram bins, four per lane per step (16-byte LDS reads;
+  //    nbins is a multiple of 256), compacted in ascending order
+  for (int b0 = 0; b0 < nbins; b0 += 256) {
+    const uint4 h = *reinterpret_cast<const uint4*>(hist + b0 + 4 * lane);
+    const uint32_t nz = (h.x != 0u) + (h.y != 0u) + (h.z != 0u) + (h.w != 0u);
+    const uint64_t m0 = __ballot(nz & 1u), m1 = __ballot(nz & 2u), m2 = __ballot(nz & 4u);
+    int pos = len + __popcll(m0 & below) + 2 * __popcll(m1 & below) + 4 * __popcll(m2 & below);
+    const int64_t v0 = b0 + 4 * lane + 1;
+    if (h.x) { lv[pos] = v0;     lc[pos] = h.x; ++pos; }
+    if (h.y) { lv[pos] = v0 + 1; lc[pos] = h.y; ++pos; }
+    if (h.z) { lv[pos] = v0 + 2; lc[pos] = h.z; ++pos; }
+    if (h.w) { lv[pos] = v0 + 3; lc[pos] = h.w; }
+    len += __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
   }
+  // 2. runs of equal values in the sorted overflow array
   for (int p0 = 0; p0 < oc; p0 += 64) {
     const int p = p0 + lane;
     const bool valid = p < oc;
     const int64_t v = valid ? ov[p] : 0;
-    bool end = false;
-    if (valid) {
-      u128_add(S, ln_fixed(v, ln), 0);
-      fp += mix64((uint64_t)v);
-      xmax = v;
-      end = (p == oc - 1) || (ov[p + 1] != v);
-    }
+    const bool end = valid && ((p == oc - 1) || (ov[p + 1] != v));
     const uint64_t m = __ballot(end);
     if (end) {
-      const int pos = len + __popcll(m & lanes_below(lane));
+      const int pos = len + __popcll(m & below);
       lv[pos] = v;
       lc[pos] = (uint32_t)(p + 1 - lower_bound_i64(ov, oc, v));
     }
     len += __popcll(m);
   }
-  sync();
+  wave_sync_global();  // the list is in global memory
+  // 3. exact S, fingerprint and maximum over the compact list
+  U128 S = {0, 0};
+  uint64_t fp = 0;
+  int64_t xmax = 0;
+  for (int q = lane; q < len; q += 64) {
+    const int64_t v = lv[q];
+    const uint32_t c = lc[q];
+    u128_add_mul(S, c, ln_fixed(v, ln));
+    fp += (uint64_t)c * mix64((uint64_t)v);
+    xmax = v > xmax ? v : xmax;
+  }
   Summary s;
   s.S = wave_sum_u128(S);
   s.fp = wave_sum_u64(fp);
@@ -382,7 +563,7 @@ __device__ __forceinline__ int next_pow2(int v) {
 // LDS of the simulation kernel: the cell's CDF table and packed guide, and one
 // region per wave (lane form or wave form).
 // ---------------------------------------------------------------------------
-struct LaneRegion {
+struct alignas(16) LaneRegion {
   uint32_t hist[kHLB / 2 * 64];  // dword b of lane l at hist[b * 64 + l]
   int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
   QEntry q[kQCap];
@@ -391,7 +572,7 @@ struct LaneRegion {
   uint32_t qn;
 };
 
-struct WaveRegion {
+struct alignas(16) WaveRegion {
   uint32_t hist[kHW];
   int64_t ov[kCW];
   QEntry q[kQCap];
@@ -405,7 +586,7 @@ union WaveLds {
 };
 
 struct SimLds {
-  double T[kH];
+  alignas(16) double T[kH];
   uint32_t guide[kGuide];
   WaveLds w[kWaves];
   int unit;
@@ -426,14 +607,46 @@ template <class Region>
 __device__ __forceinline__ void queue_compact(Region* L, int m, int lane) {
   const int rem = (int)L->qn - m;
   const bool ha = lane < rem, hb = lane + 64 < rem;
-  QEntry a = {0.0, 0u, 0u}, b = {0.0, 0u, 0u};
-  if (ha) a = L->q[m + lane];
-  if (hb) b = L->q[m + 64 + lane];
+  double ua = 0.0, ub = 0.0;
+  uint32_t ia = 0u, ib = 0u;
+  if (ha) {
+    ua = L->q[m + lane].U;
+    ia = L->q[m + lane].i;
+  }
+  if (hb) {
+    ub = L->q[m + 64 + lane].U;
+    ib = L->q[m + 64 + lane].i;
+  }
   wave_sync();
-  if (ha) L->q[lane] = a;
-  if (hb) L->q[64 + lane] = b;
+  if (ha) {
+    L->q[lane].U = ua;
+    L->q[lane].i = ia;
+  }
+  if (hb) {
+    L->q[64 + lane].U = ub;
+    L->q[64 + lane].i = ib;
+  }
   if (lane == 0) L->qn = (uint32_t)rem;
   wave_sync();
+}
+
+// Moves queue entries [m, qn) to q[0, qn - m) when qn - m < 64 (one entry
+// per lane; fields copied one by one so the entry stays in registers).
+__device__ __forceinline__ void queue_shift(QEntry* q, int m, uint32_t qn, int lane) {
+  const bool ha = lane < (int)qn - m;
+  double u = 0.0;
+  uint32_t i = 0u, o = 0u;
+  if (ha) {
+    u = q[m + lane].U;
+    i = q[m + lane].i;
+    o = q[m + lane].owner;
+  }
+  wave_sync();
+  if (ha) {
+    q[lane].U = u;
+    q[lane].i = i;
+    q[lane].owner = o;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -451,9 +664,13 @@ __device__ __forceinline__ void lane_insert(LaneRegion* L, int owner, int64_t x)
   }
 }
 
-__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, int64_t rep0,
+// Resolves queue entries [0, m) (one per lane, into the owner's column) and
+// moves entries [m, qn) to the front.  qn is the wave-uniform queue length;
+// the leading wave_sync makes entries written by other lanes visible.
+__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qn, int64_t rep0,
                                            const DevCell& c, const double* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int lane) {
+  wave_sync();
   if (lane < m) {
     const QEntry e = L->q[lane];
     uint32_t fl = 0;
@@ -461,9 +678,12 @@ __device__ __forceinline__ void lane_drain(LaneRegion* L, int m, int64_t rep0,
     if (fl) atomicOr(&L->fl[e.owner], fl);
     lane_insert(L, (int)e.owner, x);
   }
-  wave_sync();
-  queue_compact(L, m, lane);
+  queue_shift(L->q, m, qn, lane);
 }
+
+// Draw blocks per iteration of the lane form's loop: their guide and table
+// reads are independent, so their LDS latencies overlap.
+constexpr int kLaneBlocks = 2;
 
 __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int64_t rep0,
                                           int count, LaneRegion* L, int lane,
@@ -477,33 +697,51 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   for (int b = 0; b < kHLB / 2; ++b) L->hist[b * 64 + lane] = 0u;
   L->ovc[lane] = 0u;
   L->fl[lane] = 0u;
-  if (lane == 0) L->qn = 0u;
   wave_sync();
   const int64_t n = c.n;
   const uint32_t r = (uint32_t)(rep0 + lane);
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
-  for (uint32_t j = 0; j < nblk; ++j) {
-    if (active) {
-      const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
+  // Queue length, identical on every lane (ballot counts).  It is below 64
+  // before each append of at most 64 entries, so it never exceeds 127 and
+  // the queue (kQCap = 192 entries) cannot overflow.
+  uint32_t qn = 0;
+  for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
+    double U[2 * kLaneBlocks];
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const uint32_t i = 2u * j + (uint32_t)half;
-        if (half == 1 && (int64_t)i >= n) break;
-        const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-        const int x = fast_draw(U, c.tmax, T, guide);
-        if (x) {
-          lane_insert(L, lane, x);
-        } else {
-          const uint32_t slot = atomicAdd(&L->qn, 1u);
-          L->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, (uint32_t)lane};
-        }
+    for (int b = 0; b < kLaneBlocks; ++b) {
+      const Words4 w = philox4x32_10(j + (uint32_t)b, r, c.stream, 0u, c.k0, c.k1);
+      U[2 * b] = u53(w.w0, w.w1);
+      U[2 * b + 1] = u53(w.w2, w.w3);
+    }
+    int x[2 * kLaneBlocks];
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) {
+      const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
+      x[d] = valid ? fast_draw(U[d], c.tmax, T, guide) : -1;
+    }
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) {
+      if (x[d] > 0) lane_insert(L, lane, x[d]);
+      const bool def = x[d] == 0;
+      const uint64_t m = __ballot(def);
+      if (def) {
+        const uint32_t i = 2u * j + (uint32_t)d;
+        const uint32_t slot = qn + (uint32_t)__popcll(m & lanes_below(lane));
+        L->q[slot] = QEntry{U[d], U[d] > c.tmax ? (i | kTailBit) : i, (uint32_t)lane};
+      }
+      qn += (uint32_t)__popcll(m);
+      if (qn >= 64u) {
+        lane_drain(L, 64, qn, rep0, c, T, guide, lane);
+        qn -= 64u;
       }
     }
-    wave_sync();
-    if (L->qn >= 64u) lane_drain(L, 64, rep0, c, T, guide, lane);
   }
-  for (int m = (int)L->qn; m > 0; m = (int)L->qn)
-    lane_drain(L, m < 64 ? m : 64, rep0, c, T, guide, lane);
+  while (qn > 0u) {
+    const int m = qn < 64u ? (int)qn : 64;
+    lane_drain(L, m, qn, rep0, c, T, guide, lane);
+    qn -= (uint32_t)m;
+  }
+  wave_sync();
   if (!active) return;
   const int oc = (int)L->ovc[lane];
   const uint32_t fl = L->fl[lane];
@@ -552,7 +790,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   LaneSrc src{h, o, oc, 17, 0};
   double a, D;
   uint32_t flags;
-  finish_replicate(src, S, n, fl, ln, a, D, flags);
+  finish_replicate(src, S, n, fl, ln, c.K, a, D, flags);
   write_outputs(out, c.out_off + rep0 + lane, D, a, flags, fp, xmax);
 }
 
@@ -580,17 +818,22 @@ __device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
   }
 }
 
-__device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t rep, const DevCell& c,
-                                           const double* __restrict__ T,
+// Resolves queue entries [0, m) (one per lane) into the histogram and moves
+// entries [m, qn) to the front (qn wave-uniform; see lane_drain).
+__device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qn, uint32_t rep,
+                                           const DevCell& c, const double* __restrict__ T,
                                            const uint32_t* __restrict__ guide, uint32_t& fl,
                                            int lane) {
+  wave_sync();
   if (lane < m) {
     const QEntry e = L->q[lane];
     wave_insert(L, resolve(e, rep, c, T, guide, fl));
   }
-  wave_sync();
-  queue_compact(L, m, lane);
+  queue_shift(L->q, m, qn, lane);
 }
+
+// Draw blocks per lane per iteration of the wave form's loop.
+constexpr int kWaveBlocks = 2;
 
 __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0,
                                            int nrep, WaveRegion* L, WaveSlot* slots,
@@ -610,40 +853,66 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
     while (done + q < nrep && q < 64 && used + (uint32_t)(kHW + kCW) <= (uint32_t)kListCap) {
       const uint32_t r = (uint32_t)(r0 + done + q);
       for (int k = lane; k < kHW; k += 64) L->hist[k] = 0u;
-      if (lane == 0) {
-        L->ovc = 0u;
-        L->qn = 0u;
-      }
+      if (lane == 0) L->ovc = 0u;
       wave_sync();
-      uint32_t c1 = 0, fl = 0;
-      for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
-        const uint32_t j = j0 + (uint32_t)lane;
-        if (j < nblk) {
-          const Words4 w = philox4x32_10(j, r, c.stream, 0u, c.k0, c.k1);
+      // values 1..3 take most draws: counted in registers, not LDS atomics
+      uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
+      uint32_t qn = 0;  // queue length, wave-uniform; below 64 before each append
+      for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
+        double U[2 * kWaveBlocks];
 #pragma unroll
-          for (int half = 0; half < 2; ++half) {
-            const uint32_t i = 2u * j + (uint32_t)half;
-            if (half == 1 && (int64_t)i >= n) break;
-            const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-            const int x = fast_draw(U, c.tmax, T, guide);
-            if (x == 1) {
-              ++c1;
-            } else if (x) {
-              wave_insert(L, x);
-            } else {
-              const uint32_t slot = atomicAdd(&L->qn, 1u);
-              L->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u};
-            }
+        for (int b = 0; b < kWaveBlocks; ++b) {
+          const Words4 w = philox4x32_10(j0 + 64u * (uint32_t)b + (uint32_t)lane, r, c.stream,
+                                         0u, c.k0, c.k1);
+          U[2 * b] = u53(w.w0, w.w1);
+          U[2 * b + 1] = u53(w.w2, w.w3);
+        }
+        int x[2 * kWaveBlocks];
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) {
+          const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
+          x[d] = (int64_t)i < n ? fast_draw(U[d], c.tmax, T, guide) : -1;
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) {
+          const int xd = x[d];
+          if (xd == 1)
+            ++c1;
+          else if (xd == 2)
+            ++c2;
+          else if (xd == 3)
+            ++c3;
+          else if (xd > 0)
+            wave_insert(L, xd);
+          const bool def = xd == 0;
+          const uint64_t m = __ballot(def);
+          if (def) {
+            const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
+            const uint32_t slot = qn + (uint32_t)__popcll(m & lanes_below(lane));
+            L->q[slot] = QEntry{U[d], U[d] > c.tmax ? (i | kTailBit) : i, 0u};
+          }
+          qn += (uint32_t)__popcll(m);
+          if (qn >= 64u) {
+            wave_drain(L, 64, qn, r, c, T, guide, fl, lane);
+            qn -= 64u;
           }
         }
-        wave_sync();
-        if (L->qn >= 64u) wave_drain(L, 64, r, c, T, guide, fl, lane);
       }
-      for (int m = (int)L->qn; m > 0; m = (int)L->qn)
-        wave_drain(L, m < 64 ? m : 64, r, c, T, guide, fl, lane);
+      while (qn > 0u) {
+        const int m = qn < 64u ? (int)qn : 64;
+        wave_drain(L, m, qn, r, c, T, guide, fl, lane);
+        qn -= (uint32_t)m;
+      }
       c1 = wave_sum_u32(c1);
+      c2 = wave_sum_u32(c2);
+      c3 = wave_sum_u32(c3);
       fl = wave_or_u32(fl);
-      if (lane == 0) L->hist[0] += c1;
+      wave_sync();
+      if (lane == 0) {
+        L->hist[0] += c1;
+        L->hist[1] += c2;
+        L->hist[2] += c3;
+      }
       wave_sync();
       const uint32_t oc = L->ovc;
       if (oc > (uint32_t)kCW) {
@@ -666,7 +935,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         wave_bitonic(L->ov, P, lane, WaveSync{});
       }
       const Summary s = build_list(L->hist, kHW, L->ov, (int)oc, lv + used, lc + used, lane,
-                                   ln, WaveSync{});
+                                   ln);
       if (lane == 0) {
         WaveSlot sl;
         sl.S = s.S;
@@ -688,10 +957,10 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
     if (lane < q) {
       const WaveSlot sl = slots[lane];
       if (!sl.esc) {
-        ListSrc src{lv + sl.off, lc + sl.off, (int)sl.len, 0};
+        ListSrc src(lv + sl.off, lc + sl.off, (int)sl.len);
         double a, D;
         uint32_t flags;
-        finish_replicate(src, sl.S, n, sl.flags, ln, a, D, flags);
+        finish_replicate(src, sl.S, n, sl.flags, ln, c.K, a, D, flags);
         write_outputs(out, c.out_off + r0 + done + lane, D, a, flags, sl.fp, sl.xmax);
       }
     }
@@ -756,7 +1025,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_simulate(
 // scratch and sorts them there.  Runs the planned heavy units, then every
 // replicate that overflowed the lane or wave form.
 // ---------------------------------------------------------------------------
-struct HeavyWave {
+struct alignas(16) HeavyWave {
   uint32_t hist[kHeavyHist];
   QEntry q[kQCap];
   uint32_t ovc;
@@ -770,23 +1039,18 @@ struct HeavyLds {
   int item;
 };
 
-// Ordering of one wave's global-memory stores before its later loads.
-__device__ __forceinline__ void wave_sync_global() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 struct GlobalSync {
   __device__ void operator()() const { wave_sync_global(); }
 };
 
 // Histogram/overflow fill, sort, compact list and finish of one replicate by
 // one wave.  fill(sink, flags) calls sink(x) for every value.
+// K = 0: the pure law; K > 0: the truncated law on 1..K (values above K are
+// invalid, like values below 1).
 template <class Fill>
 __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
-                           uint32_t* lc, const double* __restrict__ ln, double& a, double& D,
-                           uint32_t& flags, uint64_t& fp, int64_t& xmax, bool& ok) {
+                           uint32_t* lc, const double* __restrict__ ln, uint32_t K, double& a,
+                           double& D, uint32_t& flags, uint64_t& fp, int64_t& xmax, bool& ok) {
   const int lane = lane_id();
   for (int k = lane; k < kHeavyHist; k += 64) W->hist[k] = 0u;
   if (lane == 0) {
@@ -796,8 +1060,9 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
   wave_sync_global();
   uint32_t c1 = 0, fl = 0;
   bool bad = false;
+  const int64_t xhi = K ? (int64_t)K : INT64_MAX;
   auto sink = [&](int64_t x) {
-    if (x < 1) {
+    if (x < 1 || x > xhi) {
       bad = true;
     } else if (x == 1) {
       ++c1;
@@ -823,12 +1088,9 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
     wave_sync_global();
     wave_bitonic(gov, P, lane, GlobalSync{});
   }
-  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, GlobalSync{});
+  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln);
   wave_sync_global();
-  if (lane == 0) {
-    ListSrc src{lv, lc, s.len, 0};
-    finish_replicate(src, s.S, n, fl, ln, a, D, flags);
-  }
+  finish_replicate_wave(lv, lc, s.len, s.S, n, fl, ln, lane, K, a, D, flags);
   fp = s.fp;
   xmax = s.xmax;
 }
@@ -881,7 +1143,7 @@ __device__ void heavy_replicate(HeavyWave* W, const double* __restrict__ T,
   uint64_t fp;
   int64_t xmax;
   bool ok;
-  heavy_core(W, n, fill, gov, lv, lc, ln, a, D, flags, fp, xmax, ok);
+  heavy_core(W, n, fill, gov, lv, lc, ln, c.K, a, D, flags, fp, xmax, ok);
   if (lane == 0) write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
   wave_sync_global();
 }
@@ -954,7 +1216,7 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
                                            const double* __restrict__ ln, int64_t* scratch,
                                            int64_t scratch_stride, double* ahat_out,
                                            double* D_out, uint32_t* flags_out,
-                                           uint32_t* status_out) {
+                                           uint32_t* status_out, uint32_t K) {
   __shared__ HeavyWave W;
   int64_t* gov = scratch + (int64_t)blockIdx.x * scratch_stride;
   const int64_t half = scratch_stride / 2;
@@ -972,7 +1234,7 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
     uint64_t fp;
     int64_t xmax;
     bool ok;
-    heavy_core(&W, n, fill, gov, lv, lc, ln, a, D, flags, fp, xmax, ok);
+    heavy_core(&W, n, fill, gov, lv, lc, ln, K, a, D, flags, fp, xmax, ok);
     if (lane == 0) {
       ahat_out[set] = a;
       D_out[set] = D;
@@ -992,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
                                               const double* __restrict__ ln) {
   const int cell = (int)blockIdx.y;
   const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x) + 1;
-  if (k > kH) return;
+  if (k > kH || cells[cell].K != 0u) return;
   const double a = cells[cell].alpha;
   double suf[17];
   survival_head(a, ln, suf);
@@ -1002,6 +1264,38 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
     if (k == t) zk = suf[t];
   if (k > 16) zk = survival_next(a, (int64_t)k, ln);
   tables[(size_t)cell * kH + (k - 1)] = 1.0 - zk / suf[0];
+}
+
+// Table of the truncated law on 1..K (Sect. 1 with a finite upper limit):
+// T[k] = F(k) = 1 - Z(k)/Z(0) with Z(t) = sum_{j=t+1..K} j^-a, and T[k] = 1
+// for k >= K, so a uniform never reaches the tail sampler.  The terms are
+// computed in parallel; one thread forms the suffix sums from K down, in
+// the order of the definition.  One workgroup per cell (pure-law cells exit).
+__global__ __launch_bounds__(1024) void k_table_trunc(const DevCell* __restrict__ cells,
+                                                     double* __restrict__ tables,
+                                                     const double* __restrict__ ln) {
+  const int cell = (int)blockIdx.x;
+  const uint32_t K = cells[cell].K;
+  if (K == 0u) return;
+  __shared__ double w[kH + 2];  // w[j] = j^-a; then w[t + 1] = Z(t)
+  const double a = cells[cell].alpha;
+  const int tid = (int)threadIdx.x;
+  for (int j = tid + 1; j <= (int)K; j += (int)blockDim.x) w[j] = j == 1 ? 1.0 : pow_neg(a, ln[j]);
+  __syncthreads();
+  if (tid == 0) {
+    double z = 0.0;  // Z(K) = 0
+    for (int t = (int)K - 1; t >= 0; --t) {
+      const double wt = w[t + 1];
+      w[t + 2] = z;  // Z(t + 1)
+      z += wt;       // Z(t)
+    }
+    w[1] = z;
+  }
+  __syncthreads();
+  const double z0 = w[1];
+  double* T = tables + (size_t)cell * kH;
+  for (int k = tid + 1; k <= kH; k += (int)blockDim.x)
+    T[k - 1] = k >= (int)K ? 1.0 : 1.0 - w[k + 1] / z0;
 }
 
 // Guide entry b: the smallest k that a uniform in bin b can map to.  Bins
@@ -1078,6 +1372,7 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // the radix selection runs over all of D instead.  Both give the same element.
 // ---------------------------------------------------------------------------
 constexpr int kSelSample = 2048;
+static_assert(kHW % 256 == 0 && kHeavyHist % 256 == 0, "build_list reads 256 bins per step");
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
 #pragma unroll
@@ -1347,6 +1642,9 @@ hipError_t launch_tables(DevCell* cells, int n_cells, double* tables, uint16_t* 
   k_table<<<dim3(kH / 256, n_cells), 256, 0, s>>>(cells, tables, ln);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  k_table_trunc<<<n_cells, 1024, 0, s>>>(cells, tables, ln);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   k_guide<<<dim3((kGuide + 1 + 255) / 256, n_cells), 256, 0, s>>>(cells, tables, guides);
   return hipGetLastError();
 }
@@ -1378,9 +1676,9 @@ hipError_t launch_heavy(int grid, const DevCell* cells, const double* tables,
 
 hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int n_sets,
                       const double* ln, int64_t* scratch, int64_t stride, double* ahat,
-                      double* D, uint32_t* flags, uint32_t* status, hipStream_t s) {
+                      double* D, uint32_t* flags, uint32_t* status, uint32_t K, hipStream_t s) {
   if (n_sets <= 0) return hipSuccess;
-  k_fit<<<grid, 64, 0, s>>>(xs, ns, n_sets, ln, scratch, stride, ahat, D, flags, status);
+  k_fit<<<grid, 64, 0, s>>>(xs, ns, n_sets, ln, scratch, stride, ahat, D, flags, status, K);
   return hipGetLastError();
 }
 

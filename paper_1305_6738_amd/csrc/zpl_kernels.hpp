@@ -60,6 +60,8 @@ struct DevCell {
   uint32_t k0, k1;  // Philox key = seed
   uint32_t stream;  // Philox counter word 2
   uint32_t mode;    // Mode
+  uint32_t K;       // 0: the pure law; else the truncated law on 1..K
+  uint32_t pad;
 };
 
 struct Unit {

@@ -79,24 +79,41 @@ ZPL_HD uint64_t mix64(uint64_t z) {
 // ---------------------------------------------------------------------------
 // Hurwitz zeta by Euler-Maclaurin with no direct terms, valid for q >= 17:
 //   zeta(s,q) = q^-s [ q/(s-1) + 1/2 + sum_{i=1..8} c_i (s)_{2i-1} q^-(2i-1) ]
-// with c_i = B_2i/(2i)! and (s)_m the rising factorial.  The Bernoulli series
-// is evaluated innermost-first (smallest terms first).
+// with c_i = B_2i/(2i)! and (s)_m the rising factorial.  The factors that
+// depend on s alone, k_i = c_i (s)_{2i-1} and 1/(s-1), are computed once per
+// exponent (EmCoef); the series is then a polynomial in 1/q^2 evaluated
+// innermost-first (smallest terms first).
 // ---------------------------------------------------------------------------
-ZPL_HD double em_series(double s, double inv_q) {
-  const double c1 = 1.0 / 12.0, c2 = -1.0 / 720.0, c3 = 1.0 / 30240.0,
-               c4 = -1.0 / 1209600.0, c5 = 1.0 / 47900160.0,
-               c6 = -691.0 / 1307674368000.0, c7 = 1.0 / 74724249600.0,
-               c8 = -3617.0 / 10670622842880000.0;
-  const double iq2 = inv_q * inv_q;
-  double acc = c8;
-  acc = fma(acc * ((s + 13.0) * (s + 14.0)), iq2, c7);
-  acc = fma(acc * ((s + 11.0) * (s + 12.0)), iq2, c6);
-  acc = fma(acc * ((s + 9.0) * (s + 10.0)), iq2, c5);
-  acc = fma(acc * ((s + 7.0) * (s + 8.0)), iq2, c4);
-  acc = fma(acc * ((s + 5.0) * (s + 6.0)), iq2, c3);
-  acc = fma(acc * ((s + 3.0) * (s + 4.0)), iq2, c2);
-  acc = fma(acc * ((s + 1.0) * (s + 2.0)), iq2, c1);
-  return acc * (s * inv_q);
+struct EmCoef {
+  double s, ism1, k[8];
+};
+
+ZPL_HD EmCoef em_coef(double s) {
+  const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
+                       1.0 / 30240.0,      -1.0 / 1209600.0,
+                       1.0 / 47900160.0,   -691.0 / 1307674368000.0,
+                       1.0 / 74724249600.0, -3617.0 / 10670622842880000.0};
+  EmCoef e;
+  e.s = s;
+  e.ism1 = 1.0 / (s - 1.0);
+  double P = s;  // (s)_{2i-1}
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    e.k[i] = c[i] * P;
+    P *= (s + (double)(2 * i + 1)) * (s + (double)(2 * i + 2));
+  }
+  return e;
+}
+
+// 1/x to about one ulp: the hardware reciprocal refined by two Newton steps.
+ZPL_HD double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
 }
 
 // q^-s = exp(-s ln q) with the product s ln q kept exact (p + e), so the
@@ -109,9 +126,13 @@ ZPL_HD double pow_neg(double s, double lnq) {
 }
 
 // zeta(s, q) for q >= 17; lnq = ln q.
-ZPL_HD double hurwitz_tail(double s, double q, double lnq) {
-  const double qs = pow_neg(s, lnq);
-  return qs * (q / (s - 1.0) + 0.5 + em_series(s, 1.0 / q));
+ZPL_HD double hurwitz_tail(const EmCoef& E, double q, double lnq) {
+  const double qs = pow_neg(E.s, lnq);
+  const double iq = recip(q), iq2 = iq * iq;
+  double acc = E.k[7];
+#pragma unroll
+  for (int i = 6; i >= 0; --i) acc = fma(acc, iq2, E.k[i]);
+  return qs * (fma(q, E.ism1, 0.5) + acc * iq);
 }
 
 // Reciprocal for the small Euler-Maclaurin correction terms (they change
@@ -246,17 +267,86 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
 }
 
 // ---------------------------------------------------------------------------
+// Truncated law on 1..K (Sect. 1 with a finite upper limit): Z_K(s) =
+// sum_{k<=K} k^-s and its first two s-derivatives by direct summation, index
+// K down to 1.  Defined for every real s; |s| <= 64 and K <= 4097 keep every
+// term below 2^768.
+// ---------------------------------------------------------------------------
+ZPL_HD Z3 zeta3_trunc(double s, uint32_t K, const double* __restrict__ ln) {
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  for (int k = (int)K; k >= 2; --k) {
+    const double l = ln[k];
+    const double t = pow_neg(s, l);
+    z0 += t;
+    z1 = fma(-l, t, z1);
+    z2 = fma(l * l, t, z2);
+  }
+  z0 += 1.0;
+  return Z3{z0, z1, z2};
+}
+
+// MLE of eq. (2) with the finite sums: mu(s) = -Z_K'/Z_K decreases strictly
+// from ln K (s -> -inf) to 0 (s -> +inf).  The same safeguarded Newton
+// iteration as mle_alpha on [-64, 64]; an iterate ending at the bracket edge
+// is checked against mu at the edge, and when m has no root inside the
+// bracket the edge is returned with kFlagNoConv.
+ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ ln,
+                              uint32_t* flags) {
+  double lo = -64.0, hi = 64.0;
+  double a1 = 1.0 + 1.0 / (m + 0.5772156649015329);
+  double a2 = log2(ln[2] / m);
+  double a = a1 > a2 ? a1 : a2;
+  if (!(a > lo && a < hi)) a = 0.0;
+  const double lm = log(m);
+  int it = 0;
+  for (; it < 200; ++it) {
+    const Z3 z = zeta3_trunc(a, K, ln);
+    const double mu = -z.z1 / z.z0;
+    if (mu == m) break;
+    if (mu > m)
+      lo = a;
+    else
+      hi = a;
+    const double var = fma(-mu, mu, z.z2 / z.z0);
+    double an = a + (log(mu) - lm) * (mu / var);
+    if (!(an >= lo && an <= hi)) {
+      an = 0.5 * (lo + hi);
+      *flags |= kFlagBisect;
+    }
+    const double scale = fabs(a) > 1.0 ? fabs(a) : 1.0;
+    const bool done = fabs(an - a) <= 0x1p-40 * scale;
+    a = an;
+    if (done) break;
+  }
+  if (it == 200) *flags |= kFlagNoConv;
+  if (fabs(a) > 63.0) {  // near an edge: is the root inside the bracket?
+    const double e = a > 0.0 ? 64.0 : -64.0;
+    const Z3 z = zeta3_trunc(e, K, ln);
+    const double mue = -z.z1 / z.z0;
+    if (a > 0.0 ? !(m > mue) : !(m < mue)) {
+      *flags |= kFlagNoConv;
+      return e;
+    }
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
 // Unnormalised survival zeta(a, t+1) = sum_{k > t} k^-a, so that
 // F(t; a) = 1 - zeta(a,t+1)/zeta(a) (eq. 1 summed).  suf[t], t = 0..16, holds
 // it for small t (suf[0] = zeta(a)); larger t use hurwitz_tail.
 // ---------------------------------------------------------------------------
-ZPL_HD void survival_head(double a, const double* __restrict__ ln, double suf[17]) {
+ZPL_HD void survival_head(const EmCoef& E, const double* __restrict__ ln, double suf[17]) {
   double pw[17];
-  small_powers(a, ln, pw);
-  suf[16] = hurwitz_tail(a, 17.0, ln[17]);
+  small_powers(E.s, ln, pw);
+  suf[16] = hurwitz_tail(E, 17.0, ln[17]);
 #pragma unroll
   for (int t = 15; t >= 1; --t) suf[t] = suf[t + 1] + pw[t + 1];
   suf[0] = suf[1] + 1.0;
+}
+
+ZPL_HD void survival_head(double a, const double* __restrict__ ln, double suf[17]) {
+  survival_head(em_coef(a), ln, suf);
 }
 
 // ln of an integer value: from the table for v <= kH + 1, else computed.
@@ -264,16 +354,15 @@ ZPL_HD double ln_value(int64_t v, const double* __restrict__ ln) {
   return v <= (int64_t)(kH + 1) ? ln[v] : log((double)v);
 }
 
-// zeta(a, v) for an integer v >= 17, i.e. the unnormalised survival at v-1.
-ZPL_HD double survival_at(double a, int64_t v, const double* __restrict__ ln) {
-  return hurwitz_tail(a, (double)v, ln_value(v, ln));
+// zeta(a, v+1) for an integer 16 <= v < 2^63 (v + 1 may not fit in int64).
+ZPL_HD double survival_next(const EmCoef& E, int64_t v, const double* __restrict__ ln) {
+  if (v < (int64_t)kH + 1) return hurwitz_tail(E, (double)(v + 1), ln[v + 1]);
+  const double q = (double)v + 1.0;
+  return hurwitz_tail(E, q, log(q));
 }
 
-// zeta(a, v+1) for an integer 16 <= v < 2^63 (v + 1 may not fit in int64).
 ZPL_HD double survival_next(double a, int64_t v, const double* __restrict__ ln) {
-  if (v < (int64_t)kH + 1) return hurwitz_tail(a, (double)(v + 1), ln[v + 1]);
-  const double q = (double)v + 1.0;
-  return hurwitz_tail(a, q, log(q));
+  return survival_next(em_coef(a), v, ln);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,7 @@ class ZplError(RuntimeError):
 
 class Cell(C.Structure):
     _fields_ = [("alpha", C.c_double), ("n", C.c_int64), ("replicates", C.c_int64),
-                ("seed", C.c_uint64), ("stream", C.c_uint32), ("reserved", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("kmax", C.c_uint32)]
 
 
 class ServeOpts(C.Structure):
@@ -85,6 +85,8 @@ def lib() -> C.CDLL:
         L.zpl_get_timing.restype = i32
         L.zpl_fit.argtypes = [vp, vp, i64, i32, P(d), P(d), P(u32), vp]
         L.zpl_fit.restype = i32
+        L.zpl_fit_truncated.argtypes = [vp, vp, i64, i32, u32, P(d), P(d), P(u32), vp]
+        L.zpl_fit_truncated.restype = i32
         L.zpl_bootstrap_pvalue.argtypes = [vp, vp, i64, i32, i64, u64, u32, P(d), P(d), P(d),
                                            P(u32), vp]
         L.zpl_bootstrap_pvalue.restype = i32
@@ -96,9 +98,9 @@ def lib() -> C.CDLL:
         L.zpl_serve_poll.restype = i32
         L.zpl_serve_stop.argtypes = [vp]
         L.zpl_serve_stop.restype = i32
-        L.zpl_sample_draws.argtypes = [vp, d, i64, u64, u32, i64, i64, vp, vp, vp]
+        L.zpl_sample_draws.argtypes = [vp, d, u32, i64, u64, u32, i64, i64, vp, vp, vp]
         L.zpl_sample_draws.restype = i32
-        L.zpl_cdf_table.argtypes = [vp, d, vp, vp]
+        L.zpl_cdf_table.argtypes = [vp, d, u32, vp, vp]
         L.zpl_cdf_table.restype = i32
         L.zpl_autotune.argtypes = [vp, P(d), i32, P(i64), i32, P(TuneEntry), vp]
         L.zpl_autotune.restype = i32
@@ -115,7 +117,7 @@ def exported_symbols() -> list:
             "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
             "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
             "zpl_sample_draws", "zpl_cdf_table", "zpl_autotune", "zpl_set_tuning",
-            "zpl_plan_forms"]
+            "zpl_plan_forms", "zpl_fit_truncated"]
 
 
 FORM_NAMES = {FORM_LANE: "lane", FORM_WAVE: "wave", FORM_HEAVY: "heavy"}
@@ -191,6 +193,7 @@ class CellSpec:
     replicates: int
     seed: int = 0
     stream: int = 0
+    kmax: int = 0  # 0: pure law; K in 2..4096: truncated law on 1..K
 
 
 def _cells(cells: Sequence) -> C.Array:
@@ -200,7 +203,8 @@ def _cells(cells: Sequence) -> C.Array:
             c = CellSpec(**c)
         elif not isinstance(c, CellSpec):
             c = CellSpec(*c)
-        arr[i] = Cell(float(c.alpha), int(c.n), int(c.replicates), int(c.seed), int(c.stream), 0)
+        arr[i] = Cell(float(c.alpha), int(c.n), int(c.replicates), int(c.seed), int(c.stream),
+                      int(c.kmax))
     return arr
 
 
@@ -274,11 +278,16 @@ class Context:
         return {"tables": ms[0], "simulate": ms[1], "heavy": ms[2], "select": ms[3]}
 
     # -- zpl_fit ------------------------------------------------------------
-    def fit(self, x, stream=None) -> dict:
+    def fit(self, x, kmax: int = 0, stream=None) -> dict:
+        """zpl_fit (kmax = 0) or zpl_fit_truncated (kmax = K)."""
         ptr, n, on_dev, keep = _xarg(x)
         a, D, f = C.c_double(), C.c_double(), C.c_uint32()
-        st = lib().zpl_fit(self._h, ptr, n, on_dev, C.byref(a), C.byref(D), C.byref(f),
-                           _stream(stream))
+        if kmax:
+            st = lib().zpl_fit_truncated(self._h, ptr, n, on_dev, int(kmax), C.byref(a),
+                                         C.byref(D), C.byref(f), _stream(stream))
+        else:
+            st = lib().zpl_fit(self._h, ptr, n, on_dev, C.byref(a), C.byref(D), C.byref(f),
+                               _stream(stream))
         del keep
         if st not in (OK, ENOCONV):
             _check(st)
@@ -321,13 +330,14 @@ class Context:
 
     # -- zpl_sample_draws / zpl_cdf_table -----------------------------------
     def sample_draws(self, alpha: float, n: int, seed: int, stream_id: int, rep_lo: int,
-                     count: int, x_out, flags_out, stream=None):
-        _check(lib().zpl_sample_draws(self._h, float(alpha), int(n), int(seed), int(stream_id),
-                                      int(rep_lo), int(count), _dptr(x_out), _dptr(flags_out),
-                                      _stream(stream)))
+                     count: int, x_out, flags_out, kmax: int = 0, stream=None):
+        _check(lib().zpl_sample_draws(self._h, float(alpha), int(kmax), int(n), int(seed),
+                                      int(stream_id), int(rep_lo), int(count), _dptr(x_out),
+                                      _dptr(flags_out), _stream(stream)))
 
-    def cdf_table(self, alpha: float, T_out, stream=None):
-        _check(lib().zpl_cdf_table(self._h, float(alpha), _dptr(T_out), _stream(stream)))
+    def cdf_table(self, alpha: float, T_out, kmax: int = 0, stream=None):
+        _check(lib().zpl_cdf_table(self._h, float(alpha), int(kmax), _dptr(T_out),
+                                   _stream(stream)))
 
 
 def _xarg(x):

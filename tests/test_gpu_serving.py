@@ -95,10 +95,13 @@ def test_bad_request_fails_alone(ctx):
 
 
 def test_memory_admission_limits_batches(ctx):
-    xs = _datasets(9, 12)
+    # equal-size requests, and a budget with room for two of them but not
+    # three (a request is charged 32 B per data point, 8 B per bootstrap
+    # replicate and about 44 KB of table, guide and fixed scratch)
+    rng = np.random.default_rng(9)
+    xs = [rng.zipf(2.0, 3000).astype(np.int64) for _ in range(12)]
     B = 2000
-    # room for about two requests per iteration
-    per = max(x.size * 32 + B * 8 + 45000 for x in xs)
+    per = 3000 * 32 + B * 8 + 45000
     ctx.serve_start(mem_budget_bytes=2 * per + 1024)
     try:
         tickets = [ctx.serve_submit(x, B, 11, k) for k, x in enumerate(xs)]
@@ -106,6 +109,6 @@ def test_memory_admission_limits_batches(ctx):
         res = _collect(ctx, tickets + [huge])
     finally:
         ctx.serve_stop()
-    assert max(res[t]["batch_size"] for t in tickets) <= 2
+    assert max(res[t]["batch_size"] for t in tickets) == 2
     assert all(res[t]["status"] == 0 for t in tickets)
     assert res[huge]["status"] == -2

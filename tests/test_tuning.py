@@ -119,3 +119,17 @@ def test_save_load_roundtrip(tmp_path):
     assert load_tuning(p) == t
     cells = [(3.0, 300, 10, 1, 0), (2.6, 150, 10, 1, 1)]
     assert plan_forms(cells, load_tuning(p)) == plan_forms(cells, t)
+
+
+def test_truncated_cells_plan_and_validate():
+    # on 1..20 no value exceeds the lane form's 48-bin column: always lane
+    assert plan_forms([(0.25, 5000, 10, 1, 0, 20), (4.0, 10, 10, 1, 1, 20)]) == ["lane", "lane"]
+    # on 1..4096 with g = 0.25 most values exceed 1024: neither lane nor wave
+    assert plan_forms([(0.25, 10000, 10, 1, 0, 4096)]) == ["heavy"]
+    # the truncated law admits g <= 1 (and g <= 0)
+    assert plan_forms([(-0.5, 100, 10, 1, 0, 50)])[0] in ("lane", "wave", "heavy")
+    for bad in [(1.5, 10, 10, 1, 0, 1), (1.5, 10, 10, 1, 0, 4097), (-65.0, 10, 10, 1, 0, 20),
+                (0.5, 10, 10, 1, 0, 0)]:
+        with pytest.raises(ZplError) as e:
+            plan_forms([bad])
+        assert e.value.status == -1, bad
