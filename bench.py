@@ -132,6 +132,7 @@ def main(argv=None):
     ap.add_argument("--tune", default="measure",
                     help="'measure' (autotune before timing), 'none' (built-in rule) or "
                          "the path of a saved tuning table")
+    ap.add_argument("--tune-out", default=None, help="save the measured tuning table here")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -140,7 +141,7 @@ def main(argv=None):
 
     import torch
     from inputs import table_slice
-    from paper_1305_6738_amd import Context, load_tuning, plan_forms
+    from paper_1305_6738_amd import Context, load_tuning, plan_forms, save_tuning
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -157,6 +158,8 @@ def main(argv=None):
         tuning.update(seconds=time.perf_counter() - t0,
                       grid="%d alphas x %d n" % (len(TUNE_ALPHAS), len(TUNE_NS)))
         progress("autotune: %.2f s" % tuning["seconds"])
+        if args.tune_out:
+            save_tuning(args.tune_out, table)
     elif args.tune != "none":
         table = load_tuning(args.tune)
         ctx.set_tuning(table)
