@@ -78,24 +78,27 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 // to a per-wave queue and resolved 64 at a time.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int guide_index(double U) {
-  if (U < 0.5) return (int)(U * (double)(2 * kGA));
-  const double e = 1.0 - U;  // exact: U in (1/2, 1)
+  // both parts are computed and one selected: no divergent branch per draw
+  const int ia = (int)(U * (double)(2 * kGA));
+  const double e = 1.0 - U;  // exact: U in (1/2, 1) when this part is used
   const uint64_t b = (uint64_t)__double_as_longlong(e);
   const int E = (int)(b >> 52);                                  // 970..1021
   const int s = (int)((b >> (52 - kGBits)) & ((1u << kGBits) - 1));
-  return kGA + ((1021 - E) << kGBits) + (((1 << kGBits) - 1) - s);
+  const int ib = kGA + ((1021 - E) << kGBits) + (((1 << kGBits) - 1) - s);
+  return U < 0.5 ? ia : ib;
 }
 
 // Packed guide entry: bracket low in bits 0..15, high in bits 16..31.
-// Returns the draw, or 0 when it must be deferred.
+// Returns the draw, or 0 when it must be deferred.  Every U in (0,1) indexes
+// a valid guide entry and lo >= 1, so the table is read unconditionally and
+// the result selected (no divergent branch).
 __device__ __forceinline__ int fast_draw(double U, double tmax, const double* __restrict__ T,
                                          const uint32_t* __restrict__ guide) {
-  if (U > tmax) return 0;
   const uint32_t gg = guide[guide_index(U)];
   const int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
-  if (hi == lo) return lo;
-  if (T[lo - 1] >= U) return lo;
-  return (hi == lo + 1) ? hi : 0;
+  const double t = T[lo - 1];
+  const int x = (hi == lo || t >= U) ? lo : (hi == lo + 1 ? hi : 0);
+  return U > tmax ? 0 : x;
 }
 
 // Full search of a deferred body draw.
@@ -111,6 +114,15 @@ __device__ __forceinline__ int slow_search(double U, const double* __restrict__ 
       lo = mid + 1;
   }
   return lo;
+}
+
+// Deferred draw of the lane and wave forms in 8 bytes.  Bit 63 clear: a body
+// draw, bits 0..52 = U * 2^53 (exact: U is an odd multiple of 2^-53).  Bit
+// 63 set: a tail draw, bits 0..31 = its index in the replicate.  Bits 53..58:
+// the lane that owns the replicate (lane form).
+__device__ __forceinline__ uint64_t defer_entry(double U, double tmax, uint32_t i, int owner) {
+  const uint64_t o = (uint64_t)owner << 53;
+  return U > tmax ? ((1ull << 63) | o | i) : (o | (uint64_t)(U * 0x1p53));
 }
 
 // Deferred draw: its uniform, its index in the replicate (bit 31 = tail),
@@ -559,6 +571,45 @@ __device__ __forceinline__ int next_pow2(int v) {
   return p;
 }
 
+__device__ __forceinline__ int64_t resolve_entry(uint64_t e, uint32_t rep, const DevCell& c,
+                                                 const double* __restrict__ T,
+                                                 const uint32_t* __restrict__ guide,
+                                                 uint32_t& fl) {
+  if (e >> 63)
+    return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep, c.stream, &fl);
+  return (int64_t)slow_search((double)(e & ((1ull << 53) - 1)) * 0x1p-53, T, guide);
+}
+
+// Ring of deferred draws (lane and wave forms).  Before an iteration's
+// appends (at most 64 lanes x 4 draws) it holds fewer than 64 entries, so
+// 320 entries never overflow.
+constexpr int kRing = 320;
+
+// Appends the draws d with def[d] set (at most 4 per lane) to the ring at
+// head qh holding qn entries; qn is wave-uniform.  Positions come from a
+// wave prefix sum of the per-lane counts (three ballots of its bits).
+template <int ND, class Entry>
+__device__ __forceinline__ void ring_append(uint64_t* ring, uint32_t qh, uint32_t& qn,
+                                            const bool (&def)[ND], Entry entry, int lane) {
+  static_assert(ND <= 4, "per-lane count must fit in 3 bits");
+  uint32_t nd = 0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) nd += def[d] ? 1u : 0u;
+  if (__ballot(nd != 0u) == 0ull) return;
+  const uint64_t below = lanes_below(lane);
+  const uint64_t m0 = __ballot(nd & 1u), m1 = __ballot(nd & 2u), m2 = __ballot(nd & 4u);
+  uint32_t pos = qh + qn + (uint32_t)(__popcll(m0 & below) + 2 * __popcll(m1 & below) +
+                                      4 * __popcll(m2 & below));
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    if (def[d]) {
+      ring[pos >= (uint32_t)kRing ? pos - (uint32_t)kRing : pos] = entry(d);
+      ++pos;
+    }
+  }
+  qn += (uint32_t)(__popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2));
+}
+
 // ---------------------------------------------------------------------------
 // LDS of the simulation kernel: the cell's CDF table and packed guide, and one
 // region per wave (lane form or wave form).
@@ -566,18 +617,16 @@ __device__ __forceinline__ int next_pow2(int v) {
 struct alignas(16) LaneRegion {
   uint32_t hist[kHLB / 2 * 64];  // dword b of lane l at hist[b * 64 + l]
   int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
-  QEntry q[kQCap];
+  uint64_t ring[kRing];          // deferred draws
   uint32_t ovc[64];  // overflow count per lane (may exceed kCL)
   uint32_t fl[64];   // flags per lane
-  uint32_t qn;
 };
 
 struct alignas(16) WaveRegion {
-  uint32_t hist[kHW];
+  uint32_t hist[kHW + 64];  // values 1..kHW; then one zero-increment slot per lane
   int64_t ov[kCW];
-  QEntry q[kQCap];
+  uint64_t ring[kRing];     // deferred draws
   uint32_t ovc;
-  uint32_t qn;
 };
 
 union WaveLds {
@@ -630,25 +679,6 @@ __device__ __forceinline__ void queue_compact(Region* L, int m, int lane) {
   wave_sync();
 }
 
-// Moves queue entries [m, qn) to q[0, qn - m) when qn - m < 64 (one entry
-// per lane; fields copied one by one so the entry stays in registers).
-__device__ __forceinline__ void queue_shift(QEntry* q, int m, uint32_t qn, int lane) {
-  const bool ha = lane < (int)qn - m;
-  double u = 0.0;
-  uint32_t i = 0u, o = 0u;
-  if (ha) {
-    u = q[m + lane].U;
-    i = q[m + lane].i;
-    o = q[m + lane].owner;
-  }
-  wave_sync();
-  if (ha) {
-    q[lane].U = u;
-    q[lane].i = i;
-    q[lane].owner = o;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Lane form: one replicate per lane.  Fast-path draws go straight into the
 // lane's histogram column; deferred draws from all lanes are resolved 64 at a
@@ -664,25 +694,26 @@ __device__ __forceinline__ void lane_insert(LaneRegion* L, int owner, int64_t x)
   }
 }
 
-// Resolves queue entries [0, m) (one per lane, into the owner's column) and
-// moves entries [m, qn) to the front.  qn is the wave-uniform queue length;
-// the leading wave_sync makes entries written by other lanes visible.
-__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qn, int64_t rep0,
+// Resolves ring entries [qh, qh + m) (one per lane) into the owners'
+// columns.  The leading wave_sync makes entries written by other lanes
+// visible; every caller is in wave-uniform control flow.
+__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qh, int64_t rep0,
                                            const DevCell& c, const double* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int lane) {
   wave_sync();
   if (lane < m) {
-    const QEntry e = L->q[lane];
+    uint32_t p = qh + (uint32_t)lane;
+    if (p >= (uint32_t)kRing) p -= (uint32_t)kRing;
+    const uint64_t e = L->ring[p];
+    const int owner = (int)((e >> 53) & 63u);
     uint32_t fl = 0;
-    const int64_t x = resolve(e, (uint32_t)(rep0 + e.owner), c, T, guide, fl);
-    if (fl) atomicOr(&L->fl[e.owner], fl);
-    lane_insert(L, (int)e.owner, x);
+    const int64_t x = resolve_entry(e, (uint32_t)(rep0 + owner), c, T, guide, fl);
+    if (fl) atomicOr(&L->fl[owner], fl);
+    lane_insert(L, owner, x);
   }
-  queue_shift(L->q, m, qn, lane);
 }
 
-// Draw blocks per iteration of the lane form's loop: their guide and table
-// reads are independent, so their LDS latencies overlap.
+// Draw blocks per iteration of the lane form's loop (two draws each).
 constexpr int kLaneBlocks = 2;
 
 __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int64_t rep0,
@@ -701,10 +732,8 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   const int64_t n = c.n;
   const uint32_t r = (uint32_t)(rep0 + lane);
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
-  // Queue length, identical on every lane (ballot counts).  It is below 64
-  // before each append of at most 64 entries, so it never exceeds 127 and
-  // the queue (kQCap = 192 entries) cannot overflow.
-  uint32_t qn = 0;
+  // Deferred draws wait in a ring (head qh, qn entries, both wave-uniform).
+  uint32_t qh = 0, qn = 0;
   for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
     double U[2 * kLaneBlocks];
 #pragma unroll
@@ -714,33 +743,35 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       U[2 * b + 1] = u53(w.w2, w.w3);
     }
     int x[2 * kLaneBlocks];
+    bool def[2 * kLaneBlocks];
+    bool big = false;
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) {
       const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
-      x[d] = valid ? fast_draw(U[d], c.tmax, T, guide) : -1;
+      const int xd = fast_draw(U[d], c.tmax, T, guide);
+      x[d] = valid ? xd : -1;
+      def[d] = valid && xd == 0;
+      big = big || x[d] > kHLB;
+      // own column, no branch: values outside 1..kHLB add zero to dword 0
+      const bool col = x[d] >= 1 && x[d] <= kHLB;
+      const int v = col ? x[d] - 1 : 0;
+      atomicAdd(&L->hist[(v >> 1) * 64 + lane], col ? 1u << ((v & 1) * 16) : 0u);
     }
+    if (__ballot(big) != 0ull) {  // values above the column (rare)
 #pragma unroll
-    for (int d = 0; d < 2 * kLaneBlocks; ++d) {
-      if (x[d] > 0) lane_insert(L, lane, x[d]);
-      const bool def = x[d] == 0;
-      const uint64_t m = __ballot(def);
-      if (def) {
-        const uint32_t i = 2u * j + (uint32_t)d;
-        const uint32_t slot = qn + (uint32_t)__popcll(m & lanes_below(lane));
-        L->q[slot] = QEntry{U[d], U[d] > c.tmax ? (i | kTailBit) : i, (uint32_t)lane};
-      }
-      qn += (uint32_t)__popcll(m);
-      if (qn >= 64u) {
-        lane_drain(L, 64, qn, rep0, c, T, guide, lane);
-        qn -= 64u;
-      }
+      for (int d = 0; d < 2 * kLaneBlocks; ++d)
+        if (x[d] > kHLB) lane_insert(L, lane, x[d]);
+    }
+    ring_append(L->ring, qh, qn, def, [&](int d) {
+      return defer_entry(U[d], c.tmax, 2u * j + (uint32_t)d, lane);
+    }, lane);
+    while (qn >= 64u) {
+      lane_drain(L, 64, qh, rep0, c, T, guide, lane);
+      qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
+      qn -= 64u;
     }
   }
-  while (qn > 0u) {
-    const int m = qn < 64u ? (int)qn : 64;
-    lane_drain(L, m, qn, rep0, c, T, guide, lane);
-    qn -= (uint32_t)m;
-  }
+  if (qn > 0u) lane_drain(L, (int)qn, qh, rep0, c, T, guide, lane);
   wave_sync();
   if (!active) return;
   const int oc = (int)L->ovc[lane];
@@ -818,18 +849,18 @@ __device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
   }
 }
 
-// Resolves queue entries [0, m) (one per lane) into the histogram and moves
-// entries [m, qn) to the front (qn wave-uniform; see lane_drain).
-__device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qn, uint32_t rep,
+// Resolves ring entries [qh, qh + m) (one per lane) into the histogram (see
+// lane_drain).
+__device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qh, uint32_t rep,
                                            const DevCell& c, const double* __restrict__ T,
                                            const uint32_t* __restrict__ guide, uint32_t& fl,
                                            int lane) {
   wave_sync();
   if (lane < m) {
-    const QEntry e = L->q[lane];
-    wave_insert(L, resolve(e, rep, c, T, guide, fl));
+    uint32_t p = qh + (uint32_t)lane;
+    if (p >= (uint32_t)kRing) p -= (uint32_t)kRing;
+    wave_insert(L, resolve_entry(L->ring[p], rep, c, T, guide, fl));
   }
-  queue_shift(L->q, m, qn, lane);
 }
 
 // Draw blocks per lane per iteration of the wave form's loop.
@@ -857,7 +888,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       wave_sync();
       // values 1..3 take most draws: counted in registers, not LDS atomics
       uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
-      uint32_t qn = 0;  // queue length, wave-uniform; below 64 before each append
+      uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
       for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
         double U[2 * kWaveBlocks];
 #pragma unroll
@@ -868,41 +899,42 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           U[2 * b + 1] = u53(w.w2, w.w3);
         }
         int x[2 * kWaveBlocks];
+        bool def[2 * kWaveBlocks];
+        bool big = false;
 #pragma unroll
         for (int d = 0; d < 2 * kWaveBlocks; ++d) {
           const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
-          x[d] = (int64_t)i < n ? fast_draw(U[d], c.tmax, T, guide) : -1;
+          const bool valid = (int64_t)i < n;
+          const int xd = fast_draw(U[d], c.tmax, T, guide);
+          x[d] = valid ? xd : -1;
+          def[d] = valid && xd == 0;
+          big = big || x[d] > kHW;
+          // values 1..3 take most draws: counted in registers, not LDS
+          // atomics; the others add 1 to their bin, and lanes with nothing to
+          // add put a zero into their own pad slot (no divergent branch)
+          c1 += x[d] == 1 ? 1u : 0u;
+          c2 += x[d] == 2 ? 1u : 0u;
+          c3 += x[d] == 3 ? 1u : 0u;
+          const bool hb = x[d] > 3 && x[d] <= kHW;
+          atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], hb ? 1u : 0u);
         }
+        if (__ballot(big) != 0ull) {  // values above the histogram
 #pragma unroll
-        for (int d = 0; d < 2 * kWaveBlocks; ++d) {
-          const int xd = x[d];
-          if (xd == 1)
-            ++c1;
-          else if (xd == 2)
-            ++c2;
-          else if (xd == 3)
-            ++c3;
-          else if (xd > 0)
-            wave_insert(L, xd);
-          const bool def = xd == 0;
-          const uint64_t m = __ballot(def);
-          if (def) {
-            const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
-            const uint32_t slot = qn + (uint32_t)__popcll(m & lanes_below(lane));
-            L->q[slot] = QEntry{U[d], U[d] > c.tmax ? (i | kTailBit) : i, 0u};
-          }
-          qn += (uint32_t)__popcll(m);
-          if (qn >= 64u) {
-            wave_drain(L, 64, qn, r, c, T, guide, fl, lane);
-            qn -= 64u;
-          }
+          for (int d = 0; d < 2 * kWaveBlocks; ++d)
+            if (x[d] > kHW) wave_insert(L, x[d]);
+        }
+        ring_append(L->ring, qh, qn, def, [&](int d) {
+          return defer_entry(U[d], c.tmax,
+                             2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1),
+                             0);
+        }, lane);
+        while (qn >= 64u) {
+          wave_drain(L, 64, qh, r, c, T, guide, fl, lane);
+          qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
+          qn -= 64u;
         }
       }
-      while (qn > 0u) {
-        const int m = qn < 64u ? (int)qn : 64;
-        wave_drain(L, m, qn, r, c, T, guide, fl, lane);
-        qn -= (uint32_t)m;
-      }
+      if (qn > 0u) wave_drain(L, (int)qn, qh, r, c, T, guide, fl, lane);
       c1 = wave_sum_u32(c1);
       c2 = wave_sum_u32(c2);
       c3 = wave_sum_u32(c3);
