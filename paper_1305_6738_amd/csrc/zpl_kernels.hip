@@ -96,9 +96,33 @@ __device__ __forceinline__ int fast_draw(double U, double tmax, const double* __
                                          const uint32_t* __restrict__ guide) {
   const uint32_t gg = guide[guide_index(U)];
   const int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
-  const double t = T[lo - 1];
+  double t = T[lo - 1];
+  asm volatile("" : "+v"(t));  // keep the read unconditional (no divergent branch)
   const int x = (hi == lo || t >= U) ? lo : (hi == lo + 1 ? hi : 0);
   return U > tmax ? 0 : x;
+}
+
+// fast_draw for N draws at once, in phases (all guide reads, then all table
+// reads, then the selections) so that the N reads of each phase are in
+// flight together: two LDS round trips per N draws instead of 2N.
+template <int N>
+__device__ __forceinline__ void fast_draw_n(const double (&U)[N], double tmax,
+                                            const double* __restrict__ T,
+                                            const uint32_t* __restrict__ guide, int (&x)[N]) {
+  uint32_t gg[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) gg[d] = guide[guide_index(U[d])];
+  double t[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
+  static_assert(N == 4, "the register pin below names four values");
+  asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));  // reads stay unconditional
+#pragma unroll
+  for (int d = 0; d < N; ++d) {
+    const int lo = (int)(gg[d] & 0xffffu), hi = (int)(gg[d] >> 16);
+    const int v = (hi == lo || t[d] >= U[d]) ? lo : (hi == lo + 1 ? hi : 0);
+    x[d] = U[d] > tmax ? 0 : v;
+  }
 }
 
 // Full search of a deferred body draw.
@@ -735,20 +759,26 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   // Deferred draws wait in a ring (head qh, qn entries, both wave-uniform).
   uint32_t qh = 0, qn = 0;
   for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
+    // the round keys are recomputed per block with scalar adds rather than
+    // kept live across the loop (where they would be spilled)
+    uint32_t k0 = c.k0, k1 = c.k1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
     double U[2 * kLaneBlocks];
 #pragma unroll
     for (int b = 0; b < kLaneBlocks; ++b) {
-      const Words4 w = philox4x32_10(j + (uint32_t)b, r, c.stream, 0u, c.k0, c.k1);
+      const Words4 w = philox4x32_10(j + (uint32_t)b, r, c.stream, 0u, k0, k1);
       U[2 * b] = u53(w.w0, w.w1);
       U[2 * b + 1] = u53(w.w2, w.w3);
     }
     int x[2 * kLaneBlocks];
     bool def[2 * kLaneBlocks];
     bool big = false;
+    int xf[2 * kLaneBlocks];
+    fast_draw_n(U, c.tmax, T, guide, xf);
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) {
       const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
-      const int xd = fast_draw(U[d], c.tmax, T, guide);
+      const int xd = xf[d];
       x[d] = valid ? xd : -1;
       def[d] = valid && xd == 0;
       big = big || x[d] > kHLB;
@@ -890,22 +920,26 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
       uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
       for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
+        uint32_t k0 = c.k0, k1 = c.k1;  // round keys per block (see lane_wave)
+        asm volatile("" : "+s"(k0), "+s"(k1));
         double U[2 * kWaveBlocks];
 #pragma unroll
         for (int b = 0; b < kWaveBlocks; ++b) {
           const Words4 w = philox4x32_10(j0 + 64u * (uint32_t)b + (uint32_t)lane, r, c.stream,
-                                         0u, c.k0, c.k1);
+                                         0u, k0, k1);
           U[2 * b] = u53(w.w0, w.w1);
           U[2 * b + 1] = u53(w.w2, w.w3);
         }
         int x[2 * kWaveBlocks];
         bool def[2 * kWaveBlocks];
         bool big = false;
+        int xf[2 * kWaveBlocks];
+        fast_draw_n(U, c.tmax, T, guide, xf);
 #pragma unroll
         for (int d = 0; d < 2 * kWaveBlocks; ++d) {
           const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
           const bool valid = (int64_t)i < n;
-          const int xd = fast_draw(U[d], c.tmax, T, guide);
+          const int xd = xf[d];
           x[d] = valid ? xd : -1;
           def[d] = valid && xd == 0;
           big = big || x[d] > kHW;
