@@ -72,67 +72,78 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 
 // ---------------------------------------------------------------------------
 // Inverse-CDF sampling: x = min{k in 1..kH : T[k] >= U} (the ">=" rule of
-// the paper's sampler).  The guide brackets the answer in [g[b], g[b+1]];
-// most brackets are a single value or two, resolved with at most one table
-// probe ("fast path").  Wider brackets and U > T[kH] (the tail) are deferred
-// to a per-wave queue and resolved 64 at a time.
+// the paper's sampler).  U = m 2^-53 with m = (w >> 11) | 1 an odd 53-bit
+// integer, and the LDS copy of the table holds TI[k] = floor(T[k] 2^53), so
+// T[k] >= U exactly when TI[k] >= m: every comparison is a 64-bit integer
+// one and U is never formed.  The guide brackets the answer in
+// [g[b], g[b+1]]; most brackets are one or two values wide, resolved with at
+// most one table probe ("fast path").  Wider brackets and U > T[kH] (the
+// tail) are deferred and resolved 64 at a time.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int guide_index(double U) {
-  // both parts are computed and one selected: no divergent branch per draw
-  const int ia = (int)(U * (double)(2 * kGA));
-  const double e = 1.0 - U;  // exact: U in (1/2, 1) when this part is used
-  const uint64_t b = (uint64_t)__double_as_longlong(e);
-  const int E = (int)(b >> 52);                                  // 970..1021
-  const int s = (int)((b >> (52 - kGBits)) & ((1u << kGBits) - 1));
-  const int ib = kGA + ((1021 - E) << kGBits) + (((1 << kGBits) - 1) - s);
-  return U < 0.5 ? ia : ib;
+__device__ __forceinline__ uint64_t m53(uint32_t hi, uint32_t lo) {
+  return ((((uint64_t)hi) << 32 | (uint64_t)lo) >> 11) | 1ull;
+}
+
+// Guide bin of U = m 2^-53.  U < 1/2: kGA bins uniform in U, bin m >> 44.
+// U > 1/2: e = 1 - U = (2^53 - m) 2^-53 exactly; the bin is given by the
+// octave and the top kGBits mantissa bits of e, which are the biased
+// exponent and mantissa fields of the double (2^53 - m) (exact, < 2^53)
+// shifted by 53 octaves.  Both parts are computed and one selected.
+__device__ __forceinline__ int guide_index(uint64_t m) {
+  const uint32_t mh = (uint32_t)(m >> 32);
+  const int ia = (int)(mh >> 12);
+  const double e = (double)((1ull << 53) - m);
+  const int q = (int)((uint32_t)(__double_as_longlong(e) >> 32) >> (20 - kGBits));
+  // bin = kGA + ((1021 - E) << kGBits) + (2^kGBits - 1 - s) for e = 2^(E-1023)(1.s...),
+  // and q = ((E + 53) << kGBits) | s
+  const int ib = kGA + ((1074 << kGBits) + ((1 << kGBits) - 1)) - q;
+  return mh < (1u << 20) ? ia : ib;
 }
 
 // Packed guide entry: bracket low in bits 0..15, high in bits 16..31.
-// Returns the draw, or 0 when it must be deferred.  Every U in (0,1) indexes
-// a valid guide entry and lo >= 1, so the table is read unconditionally and
-// the result selected (no divergent branch).
-__device__ __forceinline__ int fast_draw(double U, double tmax, const double* __restrict__ T,
-                                         const uint32_t* __restrict__ guide) {
-  const uint32_t gg = guide[guide_index(U)];
+// Returns the draw, or 0 when it must be deferred.  A bracket with lo == hi
+// always has TI[lo] >= m, so the result is lo when TI[lo] >= m, hi when the
+// bracket is two wide, else deferred; tail uniforms (m > TI[kH]) are
+// deferred.  Every m indexes a valid guide entry and lo >= 1.
+__device__ __forceinline__ int fast_select(uint32_t gg, uint64_t ti, uint64_t m, uint64_t timax) {
   const int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
-  double t = T[lo - 1];
-  asm volatile("" : "+v"(t));  // keep the read unconditional (no divergent branch)
-  const int x = (hi == lo || t >= U) ? lo : (hi == lo + 1 ? hi : 0);
-  return U > tmax ? 0 : x;
+  const int x = ti >= m ? lo : (hi == lo + 1 ? hi : 0);
+  return m > timax ? 0 : x;
 }
 
-// fast_draw for N draws at once, in phases (all guide reads, then all table
-// reads, then the selections) so that the N reads of each phase are in
-// flight together: two LDS round trips per N draws instead of 2N.
-template <int N>
-__device__ __forceinline__ void fast_draw_n(const double (&U)[N], double tmax,
-                                            const double* __restrict__ T,
-                                            const uint32_t* __restrict__ guide, int (&x)[N]) {
-  uint32_t gg[N];
+__device__ __forceinline__ int fast_draw(uint64_t m, uint64_t timax, const uint64_t* __restrict__ T,
+                                         const uint32_t* __restrict__ guide) {
+  const uint32_t gg = guide[guide_index(m)];
+  uint64_t ti = T[(int)(gg & 0xffffu) - 1];
+  asm volatile("" : "+v"(ti));  // keep the read unconditional (no divergent branch)
+  return fast_select(gg, ti, m, timax);
+}
+
+// fast_draw for four draws at once, in phases (all guide reads, then all
+// table reads, then the selections) so that the reads of each phase are in
+// flight together: two LDS round trips per four draws instead of eight.
+__device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], uint64_t timax,
+                                           const uint64_t* __restrict__ T,
+                                           const uint32_t* __restrict__ guide, int (&x)[4]) {
+  uint32_t gg[4];
 #pragma unroll
-  for (int d = 0; d < N; ++d) gg[d] = guide[guide_index(U[d])];
-  double t[N];
+  for (int d = 0; d < 4; ++d) gg[d] = guide[guide_index(m[d])];
+  uint64_t t[4];
 #pragma unroll
-  for (int d = 0; d < N; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
-  static_assert(N == 4, "the register pin below names four values");
+  for (int d = 0; d < 4; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
   asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));  // reads stay unconditional
 #pragma unroll
-  for (int d = 0; d < N; ++d) {
-    const int lo = (int)(gg[d] & 0xffffu), hi = (int)(gg[d] >> 16);
-    const int v = (hi == lo || t[d] >= U[d]) ? lo : (hi == lo + 1 ? hi : 0);
-    x[d] = U[d] > tmax ? 0 : v;
-  }
+  for (int d = 0; d < 4; ++d) x[d] = fast_select(gg[d], t[d], m[d], timax);
 }
 
 // Full search of a deferred body draw.
-__device__ __forceinline__ int slow_search(double U, const double* __restrict__ T,
+__device__ __forceinline__ int slow_search(uint64_t m, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide) {
-  const uint32_t gg = guide[guide_index(U)];
+  const uint32_t gg = guide[guide_index(m)];
   int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (T[mid - 1] >= U)
+    if (T[mid - 1] >= m)
       hi = mid;
     else
       lo = mid + 1;
@@ -140,19 +151,21 @@ __device__ __forceinline__ int slow_search(double U, const double* __restrict__ 
   return lo;
 }
 
+// Integer form of the table value F(kH) above which a uniform is a tail draw.
+__device__ __forceinline__ uint64_t table_int(double t) { return (uint64_t)(t * 0x1p53); }
+
 // Deferred draw of the lane and wave forms in 8 bytes.  Bit 63 clear: a body
-// draw, bits 0..52 = U * 2^53 (exact: U is an odd multiple of 2^-53).  Bit
-// 63 set: a tail draw, bits 0..31 = its index in the replicate.  Bits 53..58:
-// the lane that owns the replicate (lane form).
-__device__ __forceinline__ uint64_t defer_entry(double U, double tmax, uint32_t i, int owner) {
+// draw, bits 0..52 = m.  Bit 63 set: a tail draw, bits 0..31 = its index in
+// the replicate.  Bits 53..58: the lane that owns the replicate (lane form).
+__device__ __forceinline__ uint64_t defer_entry(uint64_t m, uint64_t timax, uint32_t i, int owner) {
   const uint64_t o = (uint64_t)owner << 53;
-  return U > tmax ? ((1ull << 63) | o | i) : (o | (uint64_t)(U * 0x1p53));
+  return m > timax ? ((1ull << 63) | o | i) : (o | m);
 }
 
-// Deferred draw: its uniform, its index in the replicate (bit 31 = tail),
-// and the lane that owns the replicate (lane form).
+// Deferred draw of the heavy form: its uniform's integer m, its index in the
+// replicate (bit 31 = tail).
 struct QEntry {
-  double U;
+  uint64_t m;
   uint32_t i;
   uint32_t owner;
 };
@@ -166,11 +179,11 @@ __device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k
 
 // Resolves a deferred draw.
 __device__ __forceinline__ int64_t resolve(const QEntry& e, uint32_t rep, const DevCell& c,
-                                           const double* __restrict__ T,
+                                           const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, uint32_t& fl) {
   if (e.i & kTailBit)
     return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, e.i & ~kTailBit, rep, c.stream, &fl);
-  return (int64_t)slow_search(e.U, T, guide);
+  return (int64_t)slow_search(e.m, T, guide);
 }
 
 // ---------------------------------------------------------------------------
@@ -596,12 +609,12 @@ __device__ __forceinline__ int next_pow2(int v) {
 }
 
 __device__ __forceinline__ int64_t resolve_entry(uint64_t e, uint32_t rep, const DevCell& c,
-                                                 const double* __restrict__ T,
+                                                 const uint64_t* __restrict__ T,
                                                  const uint32_t* __restrict__ guide,
                                                  uint32_t& fl) {
   if (e >> 63)
     return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep, c.stream, &fl);
-  return (int64_t)slow_search((double)(e & ((1ull << 53) - 1)) * 0x1p-53, T, guide);
+  return (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide);
 }
 
 // Ring of deferred draws (lane and wave forms).  Before an iteration's
@@ -659,18 +672,19 @@ union WaveLds {
 };
 
 struct SimLds {
-  alignas(16) double T[kH];
+  alignas(16) uint64_t T[kH];  // floor(F(k) 2^53)
   uint32_t guide[kGuide];
   WaveLds w[kWaves];
   int unit;
 };
 
-// Stages the cell's table and packed guide (g[b] | g[b+1] << 16) into LDS.
-__device__ __forceinline__ void load_cell_tables(double* T, uint32_t* guide,
+// Stages the cell's table, as integers floor(F(k) 2^53), and packed guide
+// (g[b] | g[b+1] << 16) into LDS.
+__device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
                                                  const double* __restrict__ Tg,
                                                  const uint16_t* __restrict__ g, int tid,
                                                  int nthreads) {
-  for (int k = tid; k < kH; k += nthreads) T[k] = Tg[k];
+  for (int k = tid; k < kH; k += nthreads) T[k] = table_int(Tg[k]);
   for (int b = tid; b < kGuide; b += nthreads)
     guide[b] = (uint32_t)g[b] | ((uint32_t)g[b + 1] << 16);
 }
@@ -680,23 +694,23 @@ template <class Region>
 __device__ __forceinline__ void queue_compact(Region* L, int m, int lane) {
   const int rem = (int)L->qn - m;
   const bool ha = lane < rem, hb = lane + 64 < rem;
-  double ua = 0.0, ub = 0.0;
+  uint64_t ua = 0u, ub = 0u;
   uint32_t ia = 0u, ib = 0u;
   if (ha) {
-    ua = L->q[m + lane].U;
+    ua = L->q[m + lane].m;
     ia = L->q[m + lane].i;
   }
   if (hb) {
-    ub = L->q[m + 64 + lane].U;
+    ub = L->q[m + 64 + lane].m;
     ib = L->q[m + 64 + lane].i;
   }
   wave_sync();
   if (ha) {
-    L->q[lane].U = ua;
+    L->q[lane].m = ua;
     L->q[lane].i = ia;
   }
   if (hb) {
-    L->q[64 + lane].U = ub;
+    L->q[64 + lane].m = ub;
     L->q[64 + lane].i = ib;
   }
   if (lane == 0) L->qn = (uint32_t)rem;
@@ -722,7 +736,7 @@ __device__ __forceinline__ void lane_insert(LaneRegion* L, int owner, int64_t x)
 // columns.  The leading wave_sync makes entries written by other lanes
 // visible; every caller is in wave-uniform control flow.
 __device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qh, int64_t rep0,
-                                           const DevCell& c, const double* __restrict__ T,
+                                           const DevCell& c, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int lane) {
   wave_sync();
   if (lane < m) {
@@ -742,7 +756,7 @@ constexpr int kLaneBlocks = 2;
 
 __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int64_t rep0,
                                           int count, LaneRegion* L, int lane,
-                                          const double* __restrict__ T,
+                                          const uint64_t* __restrict__ T,
                                           const uint32_t* __restrict__ guide,
                                           const double* __restrict__ ln, const Outputs& out,
                                           uint64_t* esc_list, uint32_t* esc_count,
@@ -758,23 +772,24 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   // Deferred draws wait in a ring (head qh, qn entries, both wave-uniform).
   uint32_t qh = 0, qn = 0;
+  const uint64_t timax = table_int(c.tmax);
   for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
     // the round keys are recomputed per block with scalar adds rather than
     // kept live across the loop (where they would be spilled)
     uint32_t k0 = c.k0, k1 = c.k1;
     asm volatile("" : "+s"(k0), "+s"(k1));
-    double U[2 * kLaneBlocks];
+    uint64_t U[2 * kLaneBlocks];  // uniforms as 53-bit integers m
 #pragma unroll
     for (int b = 0; b < kLaneBlocks; ++b) {
       const Words4 w = philox4x32_10(j + (uint32_t)b, r, c.stream, 0u, k0, k1);
-      U[2 * b] = u53(w.w0, w.w1);
-      U[2 * b + 1] = u53(w.w2, w.w3);
+      U[2 * b] = m53(w.w0, w.w1);
+      U[2 * b + 1] = m53(w.w2, w.w3);
     }
     int x[2 * kLaneBlocks];
     bool def[2 * kLaneBlocks];
     bool big = false;
     int xf[2 * kLaneBlocks];
-    fast_draw_n(U, c.tmax, T, guide, xf);
+    fast_draw4(U, timax, T, guide, xf);
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) {
       const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
@@ -793,7 +808,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
         if (x[d] > kHLB) lane_insert(L, lane, x[d]);
     }
     ring_append(L->ring, qh, qn, def, [&](int d) {
-      return defer_entry(U[d], c.tmax, 2u * j + (uint32_t)d, lane);
+      return defer_entry(U[d], timax, 2u * j + (uint32_t)d, lane);
     }, lane);
     while (qn >= 64u) {
       lane_drain(L, 64, qh, rep0, c, T, guide, lane);
@@ -882,7 +897,7 @@ __device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
 // Resolves ring entries [qh, qh + m) (one per lane) into the histogram (see
 // lane_drain).
 __device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qh, uint32_t rep,
-                                           const DevCell& c, const double* __restrict__ T,
+                                           const DevCell& c, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, uint32_t& fl,
                                            int lane) {
   wave_sync();
@@ -899,7 +914,7 @@ constexpr int kWaveBlocks = 2;
 __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0,
                                            int nrep, WaveRegion* L, WaveSlot* slots,
                                            int64_t* __restrict__ lv, uint32_t* __restrict__ lc,
-                                           int lane, const double* __restrict__ T,
+                                           int lane, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide,
                                            const double* __restrict__ ln, const Outputs& out,
                                            uint64_t* esc_list, uint32_t* esc_count,
@@ -919,22 +934,23 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       // values 1..3 take most draws: counted in registers, not LDS atomics
       uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
       uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
+      const uint64_t timax = table_int(c.tmax);
       for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
         uint32_t k0 = c.k0, k1 = c.k1;  // round keys per block (see lane_wave)
         asm volatile("" : "+s"(k0), "+s"(k1));
-        double U[2 * kWaveBlocks];
+        uint64_t U[2 * kWaveBlocks];  // uniforms as 53-bit integers m
 #pragma unroll
         for (int b = 0; b < kWaveBlocks; ++b) {
           const Words4 w = philox4x32_10(j0 + 64u * (uint32_t)b + (uint32_t)lane, r, c.stream,
                                          0u, k0, k1);
-          U[2 * b] = u53(w.w0, w.w1);
-          U[2 * b + 1] = u53(w.w2, w.w3);
+          U[2 * b] = m53(w.w0, w.w1);
+          U[2 * b + 1] = m53(w.w2, w.w3);
         }
         int x[2 * kWaveBlocks];
         bool def[2 * kWaveBlocks];
         bool big = false;
         int xf[2 * kWaveBlocks];
-        fast_draw_n(U, c.tmax, T, guide, xf);
+        fast_draw4(U, timax, T, guide, xf);
 #pragma unroll
         for (int d = 0; d < 2 * kWaveBlocks; ++d) {
           const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
@@ -958,7 +974,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
             if (x[d] > kHW) wave_insert(L, x[d]);
         }
         ring_append(L->ring, qh, qn, def, [&](int d) {
-          return defer_entry(U[d], c.tmax,
+          return defer_entry(U[d], timax,
                              2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1),
                              0);
         }, lane);
@@ -1099,7 +1115,7 @@ struct alignas(16) HeavyWave {
 };
 
 struct HeavyLds {
-  double T[kH];
+  uint64_t T[kH];  // floor(F(k) 2^53)
   uint32_t guide[kGuide];
   HeavyWave w[kHeavyWaves];
   int item;
@@ -1161,13 +1177,14 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
   xmax = s.xmax;
 }
 
-__device__ void heavy_replicate(HeavyWave* W, const double* __restrict__ T,
+__device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
                                 const uint32_t* __restrict__ guide, const DevCell& c,
                                 uint32_t rep, int64_t* gov, int64_t* lv, uint32_t* lc,
                                 const double* __restrict__ ln, const Outputs& out) {
   const int lane = lane_id();
   const int64_t n = c.n;
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
+  const uint64_t timax = table_int(c.tmax);
   auto fill = [&](auto sink, uint32_t& fl) {
     for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
       const uint32_t j = j0 + (uint32_t)lane;
@@ -1177,13 +1194,13 @@ __device__ void heavy_replicate(HeavyWave* W, const double* __restrict__ T,
         for (int half = 0; half < 2; ++half) {
           const uint32_t i = 2u * j + (uint32_t)half;
           if (half == 1 && (int64_t)i >= n) break;
-          const double U = half ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
-          const int x = fast_draw(U, c.tmax, T, guide);
+          const uint64_t m = half ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
+          const int x = fast_draw(m, timax, T, guide);
           if (x) {
             sink(x);
           } else {
             const uint32_t slot = atomicAdd(&W->qn, 1u);
-            W->q[slot] = QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u};
+            W->q[slot] = QEntry{m, m > timax ? (i | kTailBit) : i, 0u};
           }
         }
       }
@@ -1663,7 +1680,7 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
                                               int64_t rep_lo, int64_t count,
                                               int64_t* __restrict__ x,
                                               uint32_t* __restrict__ flags) {
-  __shared__ double T[kH];
+  __shared__ uint64_t T[kH];
   __shared__ uint32_t guide[kGuide];
   load_cell_tables(T, guide, tables, guides, (int)threadIdx.x, 256);
   __syncthreads();
@@ -1675,10 +1692,11 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
     const uint32_t i = (uint32_t)(t - rr * c.n);
     const uint32_t rep = (uint32_t)(rep_lo + rr);
     const Words4 w = philox4x32_10(i >> 1, rep, c.stream, 0u, c.k0, c.k1);
-    const double U = (i & 1u) ? u53(w.w2, w.w3) : u53(w.w0, w.w1);
+    const uint64_t m = (i & 1u) ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
+    const uint64_t timax = table_int(c.tmax);
     uint32_t fl = 0;
-    int64_t v = fast_draw(U, c.tmax, T, guide);
-    if (v == 0) v = resolve(QEntry{U, U > c.tmax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
+    int64_t v = fast_draw(m, timax, T, guide);
+    if (v == 0) v = resolve(QEntry{m, m > timax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
     x[t] = v;
     if (fl) atomicOr(&flags[rr], fl);
   }
