@@ -43,25 +43,60 @@ def progress(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+PROFILE = ROOT / "profiles" / "k_simulate_table_n1000.md"
+KERNEL_SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
+                  "paper_1305_6738_amd/csrc/zpl_math.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update((ROOT / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the simulation kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
+    known size), or None when the kernel sources changed since it was taken."""
+    if not PROFILE.exists():
+        return None
+    vals = {}
+    for line in PROFILE.read_text().splitlines():
+        if line.startswith("traffic_bytes_per_launch:") or line.startswith("kernel_source_sha256:"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def percentile(v, p):
     import numpy as np
     return float(np.percentile(np.asarray(v), p)) if len(v) else None
 
 
-def cpu_baseline(cells, target_s=12.0):
-    """The oracle on a bounded sample of the same cells (all host cores)."""
+def cpu_baseline(cells, target_s=15.0):
+    """The oracle on a bounded sample of the same cells (all host cores):
+    the first replicates of every cell, sized by a pilot run to take about
+    target_s seconds (at most the whole workload)."""
     import oracle
     oracle.build(force=False)
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    pilot = 64
+    pilot = 256
     t0 = time.perf_counter()
     for (a, n, R, seed, st) in cells:
         oracle.simulate(a, n, seed, st, 0, pilot, nthreads=cores)
     tp = time.perf_counter() - t0
-    reps = int(max(pilot, min(20000, pilot * target_s / max(tp, 1e-3))))
+    rmax = min(c[2] for c in cells)
+    reps = int(max(pilot, min(rmax, pilot * target_s / max(tp, 1e-3))))
     t0 = time.perf_counter()
     for (a, n, R, seed, st) in cells:
         oracle.simulate(a, n, seed, st, 0, reps, nthreads=cores)
@@ -133,6 +168,9 @@ def main(argv=None):
                     help="'measure' (autotune before timing), 'none' (built-in rule) or "
                          "the path of a saved tuning table")
     ap.add_argument("--tune-out", default=None, help="save the measured tuning table here")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device once (a kernel of known "
+                         "traffic that scales the profiler's FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -146,6 +184,11 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        progress("copy probe: %d MiB" % args.copy_probe_mib)
     cells = table_slice(n=1000, R=args.replicates)
     total_R = sum(c[2] for c in cells)
     ctx = Context(0)
@@ -190,7 +233,8 @@ def main(argv=None):
     ops = sum(R * (n * OPS_PER_DRAW + OPS_PER_REPLICATE) for (a, n, R, s, st) in cells)
     achieved = ops / (sim_avg_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / PEAK_OPS, "traffic": None,
+                "unit": "Tops/s", "frac": achieved / PEAK_OPS, "traffic": profiled_traffic(),
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 "kernel": "k_simulate", "kernel_ms": sim_avg_ms,
                 "ops_per_launch": ops}
 

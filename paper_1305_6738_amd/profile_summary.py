@@ -1,0 +1,112 @@
+"""Summarise the output of profile.sh (rocprofv3 CSV files) as Markdown: the
+simulation kernel's average duration, its HBM traffic per launch (FETCH_SIZE
+and WRITE_SIZE scaled by a copy of known size), and VALU / FP64 / LDS /
+occupancy fractions from the SQ counters.
+
+    python profile_summary.py OUT_DIR > summary.md
+"""
+import collections
+import csv
+import hashlib
+import sys
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent.parent
+KERNEL = "k_simulate"
+COPY_MIB = 256
+CLOCK_HZ = 2.4e9
+N_CU, SIMD_PER_CU = 256, 4
+SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
+           "paper_1305_6738_amd/csrc/zpl_math.hpp"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in SOURCES:
+        h.update((ROOT / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def counters(d):
+    """{dispatch id: (kernel name, {counter: value})}"""
+    out = collections.OrderedDict()
+    for r in csv.DictReader(open(Path(d) / "run_counter_collection.csv")):
+        k = int(r["Dispatch_Id"])
+        name, c = out.get(k, (r["Kernel_Name"], {}))
+        c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        out[k] = (name, c)
+    return out
+
+
+def last_dispatches(cs, key, count):
+    sel = [(k, c) for k, (n, c) in cs.items() if key in n]
+    return [c for _, c in sel[-count:]]
+
+
+def main(out_dir):
+    out = Path(out_dir)
+    trace = list(csv.DictReader(open(out / "trace" / "run_kernel_trace.csv")))
+    sim = [r for r in trace if KERNEL in r["Kernel_Name"]]
+    steps = 5  # the timed steps of profile.sh's bench command
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in sim[-steps:]]
+    dur = sum(durs) / len(durs)
+    stats = list(csv.DictReader(open(out / "trace" / "run_kernel_stats.csv")))
+    fetch, write = counters(out / "fetch"), counters(out / "write")
+    copy_f = [c for _, (n, c) in fetch.items() if "copyBuffer" in n and c.get("FETCH_SIZE", 0) > 1e5]
+    copy_w = [c for _, (n, c) in write.items() if "copyBuffer" in n and c.get("WRITE_SIZE", 0) > 1e5]
+    kib = COPY_MIB * 1024.0
+    sf = kib / copy_f[0]["FETCH_SIZE"] if copy_f else 1.0
+    sw = kib / copy_w[0]["WRITE_SIZE"] if copy_w else 1.0
+    f_k = [c["FETCH_SIZE"] for c in last_dispatches(fetch, KERNEL, steps)]
+    w_k = [c["WRITE_SIZE"] for c in last_dispatches(write, KERNEL, steps)]
+    fb = sum(f_k) / len(f_k) * sf * 1024.0
+    wb = sum(w_k) / len(w_k) * sw * 1024.0
+    sq = last_dispatches(counters(out / "sq"), KERNEL, steps)[-1]
+    sq2 = last_dispatches(counters(out / "sq2"), KERNEL, steps)[-1]
+    simd_cycles = dur * CLOCK_HZ * N_CU * SIMD_PER_CU
+    cu_cycles = dur * CLOCK_HZ * N_CU
+    valu_busy = sq["SQ_ACTIVE_INST_VALU"] * 4.0 / simd_cycles
+    lane_util = sq["SQ_THREAD_CYCLES_VALU"] / (sq["SQ_ACTIVE_INST_VALU"] * 64.0)
+    fp64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] / dur / 78.6e12
+    lds_busy = sq["SQ_LDS_IDX_ACTIVE"] / cu_cycles
+    conflict = sq["SQ_LDS_BANK_CONFLICT"] / max(sq["SQ_LDS_IDX_ACTIVE"], 1.0)
+    waves_per_simd = sq["SQ_WAVE_CYCLES"] * 4.0 / simd_cycles
+    p = print
+    p("# %s on the n = 1000 table slice (9 cells x 100,000 replicates), MI355X" % KERNEL)
+    p()
+    p("Made by `paper_1305_6738_amd/profile.sh` (rocprofv3 on `bench.py --steps 5 --warmup 2 "
+      "--no-extras --no-cpu-baseline --tune paper_1305_6738_amd/tuning/mi355x.json "
+      "--copy-probe-mib 256`), summarised by `paper_1305_6738_amd/profile_summary.py`.")
+    p()
+    p("kernel_source_sha256: `%s`" % source_hash())
+    p()
+    p("| Figure | Value |")
+    p("|---|---|")
+    p("| %s average duration, timed steps (kernel trace) | %.3f ms |" % (KERNEL, dur * 1e3))
+    for r in stats:
+        if KERNEL in r["Name"]:
+            p("| %s average over all dispatches (rocprofv3 --stats) | %.3f ms (%s calls) |"
+              % (KERNEL, float(r["AverageNs"]) * 1e-6, r["Calls"]))
+    p("| copy probe: FETCH_SIZE / WRITE_SIZE read for %d MiB | %.0f / %.0f KiB (scale %.3f / %.3f) |"
+      % (COPY_MIB, copy_f[0]["FETCH_SIZE"] if copy_f else 0, copy_w[0]["WRITE_SIZE"] if copy_w else 0, sf, sw))
+    p("| HBM bytes fetched per launch (scaled) | %.4g |" % fb)
+    p("| HBM bytes written per launch (scaled) | %.4g |" % wb)
+    p("| VALU busy (active VALU cycles / SIMD cycles) | %.1f %% |" % (100 * valu_busy))
+    p("| VALU lane utilisation (thread cycles / 64 per active cycle) | %.1f %% |" % (100 * lane_util))
+    p("| FP64 FLOP rate / 78.6 TFLOP/s | %.2f %% |" % (100 * fp64))
+    p("| LDS busy (SQ_LDS_IDX_ACTIVE / CU cycles) | %.1f %% |" % (100 * lds_busy))
+    p("| LDS bank-conflict cycles / LDS active cycles | %.1f %% |" % (100 * conflict))
+    p("| waves resident per SIMD (occupancy; LDS allows 2) | %.2f |" % waves_per_simd)
+    p("| VALU / SALU / LDS instructions per launch (wave-level) | %.4g / %.4g / %.4g |"
+      % (sq["SQ_INSTS_VALU"], sq2["SQ_INSTS_SALU"], sq2["SQ_INSTS_LDS"]))
+    p("| INT32 / INT64 VALU instructions | %.4g / %.4g |"
+      % (sq2["SQ_INSTS_VALU_INT32"], sq2["SQ_INSTS_VALU_INT64"]))
+    p()
+    p("traffic_bytes_per_launch: `%.6g`" % (fb + wb))
+    p()
+    p("Clock assumed 2.4 GHz for the cycle-based fractions; SQ counters from the last timed "
+      "launch, traffic averaged over the timed launches.")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])
