@@ -541,7 +541,11 @@ __device__ __forceinline__ void wave_sync_global() {
 // Builds the compact (value, count) list of one replicate from a histogram
 // of values 1..nbins (hist[v-1]) and a sorted overflow array ov[0..oc),
 // appending at lv/lc (length returned).  Also returns, identical on every
-// lane, the exact 128-bit sum of ln x, the multiset fingerprint and the max.
+// lane, the exact 128-bit sum of ln x and, when want_fp, the multiset
+// fingerprint and the largest value.  The histogram is consumed: when every
+// count fits in 21 bits (n < 2^21) its nonzero bins are also packed as
+// (v << 21 | count) into hist[0..) in list order, so the sums read them from
+// LDS instead of reading the global list back.
 struct Summary {
   U128 S;
   uint64_t fp;
@@ -549,26 +553,40 @@ struct Summary {
   int len;
 };
 
-__device__ Summary build_list(const uint32_t* hist, int nbins, const int64_t* ov, int oc,
-                              int64_t* lv, uint32_t* lc, int lane,
-                              const double* __restrict__ ln) {
+__device__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int oc, int64_t* lv,
+                              uint32_t* lc, int lane, const double* __restrict__ ln, int64_t n,
+                              bool want_fp) {
   const uint64_t below = lanes_below(lane);
+  const bool packed = n < ((int64_t)1 << 21);
+  U128 S = {0, 0};
+  uint64_t fp = 0;
+  int64_t xmax = 0;
   int len = 0;
   // 1. non-zero histogram bins, four per lane per step (16-byte LDS reads;
-  //    nbins is a multiple of 256), compacted in ascending order
+  //    nbins is a multiple of 256), compacted in ascending order.  A bin's
+  //    list position never exceeds its own index, so the packed copy only
+  //    overwrites bins that have been read.
   for (int b0 = 0; b0 < nbins; b0 += 256) {
     const uint4 h = *reinterpret_cast<const uint4*>(hist + b0 + 4 * lane);
     const uint32_t nz = (h.x != 0u) + (h.y != 0u) + (h.z != 0u) + (h.w != 0u);
     const uint64_t m0 = __ballot(nz & 1u), m1 = __ballot(nz & 2u), m2 = __ballot(nz & 4u);
     int pos = len + __popcll(m0 & below) + 2 * __popcll(m1 & below) + 4 * __popcll(m2 & below);
-    const int64_t v0 = b0 + 4 * lane + 1;
-    if (h.x) { lv[pos] = v0;     lc[pos] = h.x; ++pos; }
-    if (h.y) { lv[pos] = v0 + 1; lc[pos] = h.y; ++pos; }
-    if (h.z) { lv[pos] = v0 + 2; lc[pos] = h.z; ++pos; }
-    if (h.w) { lv[pos] = v0 + 3; lc[pos] = h.w; }
+    const uint32_t v0 = (uint32_t)(b0 + 4 * lane + 1);
+    const uint32_t cs[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (cs[k]) {
+        lv[pos] = (int64_t)(v0 + k);
+        lc[pos] = cs[k];
+        if (packed) hist[pos] = ((v0 + k) << 21) | cs[k];
+        ++pos;
+      }
+    }
     len += __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
   }
-  // 2. runs of equal values in the sorted overflow array
+  const int hlen = len;
+  // 2. runs of equal values in the sorted overflow array; the last lane of a
+  //    run adds the run's terms
   for (int p0 = 0; p0 < oc; p0 += 64) {
     const int p = p0 + lane;
     const bool valid = p < oc;
@@ -577,29 +595,65 @@ __device__ Summary build_list(const uint32_t* hist, int nbins, const int64_t* ov
     const uint64_t m = __ballot(end);
     if (end) {
       const int pos = len + __popcll(m & below);
+      const uint32_t cnt = (uint32_t)(p + 1 - lower_bound_i64(ov, oc, v));
       lv[pos] = v;
-      lc[pos] = (uint32_t)(p + 1 - lower_bound_i64(ov, oc, v));
+      lc[pos] = cnt;
+      u128_add_mul(S, cnt, ln_fixed(v, ln));
+      if (want_fp) {
+        fp += (uint64_t)cnt * mix64((uint64_t)v);
+        xmax = v > xmax ? v : xmax;
+      }
     }
     len += __popcll(m);
   }
-  wave_sync_global();  // the list is in global memory
-  // 3. exact S, fingerprint and maximum over the compact list
-  U128 S = {0, 0};
-  uint64_t fp = 0;
-  int64_t xmax = 0;
-  for (int q = lane; q < len; q += 64) {
-    const int64_t v = lv[q];
-    const uint32_t c = lc[q];
-    u128_add_mul(S, c, ln_fixed(v, ln));
-    fp += (uint64_t)c * mix64((uint64_t)v);
-    xmax = v > xmax ? v : xmax;
+  // 3. exact S (and fingerprint, max) over the histogram part of the list
+  if (packed) {
+    wave_sync();
+    for (int q = lane; q < hlen; q += 64) {
+      const uint32_t e = hist[q];
+      const int64_t v = (int64_t)(e >> 21);
+      const uint32_t c = e & ((1u << 21) - 1u);
+      u128_add_mul(S, c, ln_fixed(v, ln));
+      if (want_fp) {
+        fp += (uint64_t)c * mix64((uint64_t)v);
+        xmax = v > xmax ? v : xmax;
+      }
+    }
+  } else {
+    wave_sync_global();  // the list is in global memory
+    for (int q = lane; q < hlen; q += 64) {
+      const int64_t v = lv[q];
+      const uint32_t c = lc[q];
+      u128_add_mul(S, c, ln_fixed(v, ln));
+      if (want_fp) {
+        fp += (uint64_t)c * mix64((uint64_t)v);
+        xmax = v > xmax ? v : xmax;
+      }
+    }
   }
   Summary s;
   s.S = wave_sum_u128(S);
-  s.fp = wave_sum_u64(fp);
-  s.xmax = wave_max_i64(xmax);
+  s.fp = want_fp ? wave_sum_u64(fp) : 0ull;
+  s.xmax = want_fp ? wave_max_i64(xmax) : 0;
   s.len = len;
   return s;
+}
+
+// Ascending sort of up to 64 values held one per lane (unused lanes hold
+// INT64_MAX): a bitonic network over lane shuffles, no memory traffic.
+__device__ __forceinline__ int64_t wave_sort64(int64_t v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int64_t o = (int64_t)shfl_xor_u64((uint64_t)v, j);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      const int64_t lo = o < v ? o : v, hi = o < v ? v : o;
+      v = (lower == up) ? lo : hi;
+    }
+  }
+  return v;
 }
 
 __device__ __forceinline__ int next_pow2(int v) {
@@ -1010,14 +1064,18 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         ++q;
         continue;
       }
-      if (oc > 1) {
+      if (oc > 1 && oc <= 64u) {
+        const int64_t v = wave_sort64(lane < (int)oc ? L->ov[lane] : INT64_MAX, lane);
+        if (lane < (int)oc) L->ov[lane] = v;
+        wave_sync();
+      } else if (oc > 64u) {
         const int P = next_pow2((int)oc);
         for (int k = (int)oc + lane; k < P; k += 64) L->ov[k] = INT64_MAX;
         wave_sync();
         wave_bitonic(L->ov, P, lane, WaveSync{});
       }
       const Summary s = build_list(L->hist, kHW, L->ov, (int)oc, lv + used, lc + used, lane,
-                                   ln);
+                                   ln, n, out.fp != nullptr || out.xmax != nullptr);
       if (lane == 0) {
         WaveSlot sl;
         sl.S = s.S;
@@ -1131,8 +1189,9 @@ struct GlobalSync {
 // invalid, like values below 1).
 template <class Fill>
 __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
-                           uint32_t* lc, const double* __restrict__ ln, uint32_t K, double& a,
-                           double& D, uint32_t& flags, uint64_t& fp, int64_t& xmax, bool& ok) {
+                           uint32_t* lc, const double* __restrict__ ln, uint32_t K, bool want_fp,
+                           double& a, double& D, uint32_t& flags, uint64_t& fp, int64_t& xmax,
+                           bool& ok) {
   const int lane = lane_id();
   for (int k = lane; k < kHeavyHist; k += 64) W->hist[k] = 0u;
   if (lane == 0) {
@@ -1164,13 +1223,17 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
   ok = (anybad == 0u);
   if (!ok) return;
   const int oc = (int)W->ovc;
-  if (oc > 1) {
+  if (oc > 1 && oc <= 64) {
+    const int64_t v = wave_sort64(lane < oc ? gov[lane] : INT64_MAX, lane);
+    if (lane < oc) gov[lane] = v;
+    wave_sync_global();
+  } else if (oc > 64) {
     const int P = next_pow2(oc);
     for (int k = oc + lane; k < P; k += 64) gov[k] = INT64_MAX;
     wave_sync_global();
     wave_bitonic(gov, P, lane, GlobalSync{});
   }
-  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln);
+  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, want_fp);
   wave_sync_global();
   finish_replicate_wave(lv, lc, s.len, s.S, n, fl, ln, lane, K, a, D, flags);
   fp = s.fp;
@@ -1226,7 +1289,8 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
   uint64_t fp;
   int64_t xmax;
   bool ok;
-  heavy_core(W, n, fill, gov, lv, lc, ln, c.K, a, D, flags, fp, xmax, ok);
+  heavy_core(W, n, fill, gov, lv, lc, ln, c.K, out.fp != nullptr || out.xmax != nullptr, a, D,
+             flags, fp, xmax, ok);
   if (lane == 0) write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
   wave_sync_global();
 }
@@ -1317,7 +1381,7 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
     uint64_t fp;
     int64_t xmax;
     bool ok;
-    heavy_core(&W, n, fill, gov, lv, lc, ln, K, a, D, flags, fp, xmax, ok);
+    heavy_core(&W, n, fill, gov, lv, lc, ln, K, false, a, D, flags, fp, xmax, ok);
     if (lane == 0) {
       ahat_out[set] = a;
       D_out[set] = D;
