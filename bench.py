@@ -154,6 +154,38 @@ def serving(ctx, qps=200.0, seconds=10.0, B=2500):
                     "fit + B=2500 bootstrap per request, continuous batching"}
 
 
+def config_runs(ctx, stream, torch):
+    """One timed call (after one untimed) of each configuration beside the
+    headline: the full table, the uneven batch, the heavy tails, and two
+    slices of the truncated law's tables (n = 1000, 12 exponents)."""
+    from inputs import table_cells, uneven_cells, heavy_tail
+    gammas = [0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 3.5, 4.0]
+    runs = {
+        "full_table": ("9 alphas x n in {10..10000}, R = 100,000", table_cells(R=100000)),
+        "uneven_batch": ("4,096 cells, n log-uniform [10, 1e5], alpha U(1.5, 3.5), R = 10,000",
+                         uneven_cells(count=4096, R=10000)),
+        "heavy_tail": ("alpha in {1.2, 1.3, 1.4, 1.5}, n = 10,000, R = 100,000", heavy_tail(R=100000)),
+        "truncated_K20": ("truncated law K = 20: 12 exponents 0.25..4, n = 1000, R = 100,000",
+                          [(g, 1000, 100000, 42, i, 20) for i, g in enumerate(gammas)]),
+        "truncated_K1000": ("truncated law K = 1000: 12 exponents 0.25..4, n = 1000, R = 100,000",
+                            [(g, 1000, 100000, 42, i, 1000) for i, g in enumerate(gammas)]),
+    }
+    out = {}
+    for name, (what, cells) in runs.items():
+        R = sum(c[2] for c in cells)
+        ctx.simulate_cells(cells, quantiles=QS, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.simulate_cells(cells, quantiles=QS, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        draws = sum(c[1] * c[2] for c in cells)
+        out[name] = {"what": what, "cells": len(cells), "replicates": R, "ms": ms,
+                     "replicates_per_s": R / (ms / 1e3), "draws_per_s": draws / (ms / 1e3)}
+        progress("%s: %.1f ms" % (name, ms))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +320,7 @@ def main(argv=None):
             out["untuned_forms"] = plan_forms(cells)
             ctx.set_tuning(table)
             progress("built-in form rule: %.3f ms/step" % u_ms)
+        out["configs"] = config_runs(ctx, stream, torch)
         out["fit_latency"] = fit_latency(ctx)
         progress("fit latency done")
         if args.serve_seconds > 0:
