@@ -1088,11 +1088,12 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         slots[q] = sl;
       }
       used += (uint32_t)s.len;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      wave_sync();
       ++q;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // the batch's lists and slots (global stores by various lanes) become
+    // visible to every lane once, here, before the finishes read them; each
+    // replicate wrote disjoint positions, so no ordering is needed earlier
+    wave_sync_global();
     // deferred finishes, one replicate per lane
     if (lane < q) {
       const WaveSlot sl = slots[lane];
