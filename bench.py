@@ -186,6 +186,46 @@ def config_runs(ctx, stream, torch):
     return out
 
 
+PAPER_NS = [10, 20, 30, 40, 50, 100, 500, 1000, 2000, 3000, 4000, 5000, 10000, 20000, 50000]
+
+
+def paper_tables(ctx, torch):
+    """Every table of the paper at its own size: Table 1 (pure law, 8
+    exponents) and Tables 2-6 (K = 20, 50, 100, 500, 1000; 12 exponents),
+    15 sample sizes each, 10 runs of 50,000 replicates per entry, quantiles
+    .90/.95/.99/.999 averaged over the runs (one zpl_critical_table call per
+    table, timed end to end on the host)."""
+    g1 = [1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 3.5, 4.0]
+    gt = [0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 3.5, 4.0]
+    qs = ((9, 10), (95, 100), (99, 100), (999, 1000))
+    ctx.critical_table([2.0], [10], kmax=0, seeds=1, replicates=1000, quantiles=qs)
+    torch.cuda.synchronize()
+    out = {"tables": {}}
+    total_s, total_r, total_d = 0.0, 0, 0
+    for name, K, gs in [("table1", 0, g1), ("table2_K20", 20, gt), ("table3_K50", 50, gt),
+                        ("table4_K100", 100, gt), ("table5_K500", 500, gt),
+                        ("table6_K1000", 1000, gt)]:
+        t0 = time.perf_counter()
+        ctx.critical_table(gs, PAPER_NS, kmax=K, seeds=10, seed0=1, replicates=50000,
+                           quantiles=qs)
+        dt = time.perf_counter() - t0
+        reps = len(gs) * len(PAPER_NS) * 10 * 50000
+        draws = len(gs) * sum(PAPER_NS) * 10 * 50000
+        out["tables"][name] = {"s": dt, "replicates_per_s": reps / dt}
+        total_s += dt
+        total_r += reps
+        total_d += draws
+        progress("%s: %.2f s" % (name, dt))
+    out.update({"what": "Tables 1-6 at the paper's size: 1,020 entries x 10 runs x 50,000 "
+                        "replicates, quantiles .90/.95/.99/.999",
+                "seconds": total_s, "replicates": total_r, "draws": total_d,
+                "replicates_per_s": total_r / total_s,
+                "paper_context": "the paper reports just over 373 hours for these runs on "
+                                 "two GeForce GTX 590 (context only: other hardware, other "
+                                 "sampler and KS scan)"})
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +235,8 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true",
                     help="only the batched timed region (for profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-tables", action="store_true",
+                    help="skip the timed run of all six tables at the paper's size")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--tune", default="measure",
                     help="'measure' (autotune before timing), 'none' (built-in rule) or "
@@ -321,6 +363,8 @@ def main(argv=None):
             ctx.set_tuning(table)
             progress("built-in form rule: %.3f ms/step" % u_ms)
         out["configs"] = config_runs(ctx, stream, torch)
+        if not args.no_paper_tables:
+            out["paper_tables"] = paper_tables(ctx, torch)
         out["fit_latency"] = fit_latency(ctx)
         progress("fit latency done")
         if args.serve_seconds > 0:

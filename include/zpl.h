@@ -140,6 +140,32 @@ zpl_status zpl_simulate_cells(zpl_ctx *ctx, const zpl_cell *cells, int32_t n_cel
                               uint32_t *flags_out, uint64_t *fingerprint_out,
                               const zpl_sim_opts *opts, void *stream);
 
+/* A whole critical-value table as the paper builds its Tables 1-6 (Sect. 3):
+ * every entry is the mean, over n_seeds independent runs, of the quantile
+ * order statistic of `replicates` simulated D values (the paper: 10 runs of
+ * 50,000 at each (N, gamma), quantiles .90/.95/.99/.999).
+ *   gammas[n_gamma], ns[n_n]  host; the table's columns (exponent) and rows
+ *                             (sample size N); each (gamma, N) must be a
+ *                             valid zpl_cell with this kmax.
+ *   kmax                      0 = pure law (Table 1), else K (Tables 2-6).
+ *   run s of entry (i_n, i_g) is the cell {gammas[i_g], ns[i_n], replicates,
+ *   seed0 + s, stream = i_n * n_gamma + i_g, kmax}, so every entry and run
+ *   can be recomputed alone with zpl_simulate_cells.
+ *   table_out   host [n_n * n_gamma * n_q], entry (i_n, i_g, q) at
+ *               (i_n * n_gamma + i_g) * n_q + q: the runs' quantiles summed
+ *               in run order in FP64, then divided by n_seeds.
+ *   per_run_out host [n_n * n_gamma * n_seeds * n_q] or NULL: the quantile of
+ *               each run, (i_n, i_g, s, q) at ((i_n * n_gamma + i_g) *
+ *               n_seeds + s) * n_q + q.
+ * The runs go through the batched persistent launch in groups of cells
+ * sized to the context's budget.  1 <= n_seeds <= 1024.  Synchronises the
+ * stream. */
+zpl_status zpl_critical_table(zpl_ctx *ctx, const double *gammas, int32_t n_gamma,
+                              const int64_t *ns, int32_t n_n, uint32_t kmax, int32_t n_seeds,
+                              uint64_t seed0, int64_t replicates, const uint32_t *q_num,
+                              const uint32_t *q_den, int32_t n_q, double *table_out,
+                              double *per_run_out, void *stream);
+
 /* --------------------------------------------------------------------------
  * Autotuning of the execution form (the batched launch of Sect. 3's
  * simulations over cells of uneven n).  Every form computes the same bits;

@@ -280,3 +280,37 @@ def tz_simulate(g: float, K: int, n: int, seed: int, stream: int, rep_lo: int, c
     if rc != 0:
         raise ValueError("oracle tz_simulate: invalid cell")
     return {"D": D, "alpha_hat": A, "S": S, "flags": F, "fp": FP, "xmax": XM}
+
+
+# ---- a whole table (Sect. 3: how Tables 1-6 are built) ---------------------
+
+def critical_table(gammas, ns, K: int = 0, seeds: int = 10, seed0: int = 1, R: int = 50000,
+                   quantiles=((9, 10), (95, 100), (99, 100), (999, 1000)),
+                   nthreads: int = 0):
+    """Sect. 3's construction of a table: at every (N, gamma) entry, `seeds`
+    independent runs of R replicates (run s: seed seed0 + s, stream
+    i_n * len(gammas) + i_g), the quantile order statistic of each run's D
+    values, and their mean over the runs (summed in run order, then divided
+    by the number of runs).  K = 0 is the pure law (Table 1), else the law
+    truncated to 1..K (Tables 2-6).  Returns (table [len(ns), len(gammas),
+    n_q], per_run [len(ns), len(gammas), seeds, n_q])."""
+    q = list(quantiles)
+    runs = np.zeros((len(ns), len(gammas), seeds, len(q)))
+    for i_n, n in enumerate(ns):
+        for i_g, g in enumerate(gammas):
+            stream = i_n * len(gammas) + i_g
+            for s in range(seeds):
+                if K:
+                    D = tz_simulate(g, K, n, seed0 + s, stream, 0, R, nthreads)["D"]
+                else:
+                    D = simulate(g, n, seed0 + s, stream, 0, R, nthreads)["D"]
+                runs[i_n, i_g, s] = [quantile(D, a, b) for a, b in q]
+    table = np.zeros((len(ns), len(gammas), len(q)))
+    for i_n in range(len(ns)):
+        for i_g in range(len(gammas)):
+            for k in range(len(q)):
+                acc = 0.0
+                for s in range(seeds):
+                    acc += runs[i_n, i_g, s, k]
+                table[i_n, i_g, k] = acc / seeds
+    return table, runs

@@ -1030,6 +1030,60 @@ zpl_status zpl_simulate_cells(zpl_ctx* c, const zpl_cell* cells, int32_t n_cells
                    (hipStream_t)stream);
 }
 
+zpl_status zpl_critical_table(zpl_ctx* c, const double* gammas, int32_t n_gamma,
+                              const int64_t* ns, int32_t n_n, uint32_t kmax, int32_t n_seeds,
+                              uint64_t seed0, int64_t replicates, const uint32_t* q_num,
+                              const uint32_t* q_den, int32_t n_q, double* table_out,
+                              double* per_run_out, void* stream) {
+  g_err.clear();
+  if (!c) return fail(ZPL_EINVAL, "ctx is NULL");
+  if (!gammas || !ns || n_gamma < 1 || n_n < 1)
+    return fail(ZPL_EINVAL, "need at least one exponent and one sample size");
+  if ((int64_t)n_gamma * n_n > ((int64_t)1 << 20))
+    return fail(ZPL_EINVAL, "table of %d x %d entries is too large", n_n, n_gamma);
+  if (n_seeds < 1 || n_seeds > 1024)
+    return fail(ZPL_EINVAL, "n_seeds must be in [1, 1024], got %d", n_seeds);
+  if (n_q < 1 || !q_num || !q_den || !table_out)
+    return fail(ZPL_EINVAL, "need at least one quantile and table_out");
+  HIP_TRY(hipSetDevice(c->device));
+  const hipStream_t s = (hipStream_t)stream;
+  // the runs in entry-major order: (i_n, i_g, s)
+  const int64_t n_runs = (int64_t)n_n * n_gamma * n_seeds;
+  std::vector<zpl_cell> runs((size_t)n_runs);
+  for (int in = 0; in < n_n; ++in)
+    for (int ig = 0; ig < n_gamma; ++ig)
+      for (int sd = 0; sd < n_seeds; ++sd) {
+        zpl_cell& z = runs[((size_t)in * n_gamma + ig) * n_seeds + sd];
+        z.alpha = gammas[ig];
+        z.n = ns[in];
+        z.replicates = replicates;
+        z.seed = seed0 + (uint64_t)sd;
+        z.stream = (uint32_t)(in * n_gamma + ig);
+        z.kmax = kmax;
+      }
+  // groups of whole runs whose D values, selection scratch and tables fit in
+  // a quarter of the budget (at least one run per group)
+  const int64_t per_run = replicates * 8 +
+                          (int64_t)kSelQ * std::min<int64_t>(kSelGather, replicates * 3 / 20 + 1024) * 8 +
+                          (int64_t)kH * 8 + (int64_t)(kGuide + 1) * 2;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((int64_t)(c->budget / 4) / per_run, 4096));
+  std::vector<double> q((size_t)n_runs * n_q);
+  for (int64_t r0 = 0; r0 < n_runs; r0 += cap) {
+    const int nr = (int)std::min<int64_t>(cap, n_runs - r0);
+    Outputs out{nullptr, nullptr, nullptr, nullptr, nullptr};
+    ZPL_TRY(run_cells(c, runs.data() + r0, nr, q_num, q_den, n_q, q.data() + r0 * n_q, out,
+                      nullptr, s));
+  }
+  for (int64_t e = 0; e < (int64_t)n_n * n_gamma; ++e)
+    for (int k = 0; k < n_q; ++k) {
+      double sum = 0.0;
+      for (int sd = 0; sd < n_seeds; ++sd) sum += q[((size_t)e * n_seeds + sd) * n_q + k];
+      table_out[e * n_q + k] = sum / (double)n_seeds;
+    }
+  if (per_run_out) std::memcpy(per_run_out, q.data(), sizeof(double) * q.size());
+  return ZPL_OK;
+}
+
 zpl_status zpl_autotune(zpl_ctx* c, const double* alphas, int32_t n_alpha, const int64_t* ns,
                         int32_t n_n, zpl_tune_entry* table_out, void* stream) {
   g_err.clear();

@@ -108,6 +108,9 @@ def lib() -> C.CDLL:
         L.zpl_set_tuning.restype = i32
         L.zpl_plan_forms.argtypes = [P(TuneEntry), i32, P(Cell), i32, P(i32)]
         L.zpl_plan_forms.restype = i32
+        L.zpl_critical_table.argtypes = [vp, P(d), i32, P(i64), i32, u32, i32, u64, i64, P(u32),
+                                         P(u32), i32, P(d), P(d), vp]
+        L.zpl_critical_table.restype = i32
         _lib = L
     return _lib
 
@@ -117,7 +120,7 @@ def exported_symbols() -> list:
             "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
             "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
             "zpl_sample_draws", "zpl_cdf_table", "zpl_autotune", "zpl_set_tuning",
-            "zpl_plan_forms", "zpl_fit_truncated"]
+            "zpl_plan_forms", "zpl_fit_truncated", "zpl_critical_table"]
 
 
 FORM_NAMES = {FORM_LANE: "lane", FORM_WAVE: "wave", FORM_HEAVY: "heavy"}
@@ -252,6 +255,28 @@ class Context:
             _dptr(d_out), _dptr(alpha_hat_out), _dptr(flags_out), _dptr(fingerprint_out),
             C.byref(opts), _stream(stream)))
         return out[:, :nq] if nq else None
+
+    # -- zpl_critical_table -------------------------------------------------
+    def critical_table(self, gammas: Sequence[float], ns: Sequence[int], kmax: int = 0,
+                       seeds: int = 10, seed0: int = 1, replicates: int = 50000,
+                       quantiles: Iterable = ((9, 10), (95, 100), (99, 100), (999, 1000)),
+                       per_run: bool = False, stream=None):
+        """A critical-value table as the paper's Tables 1-6 (zpl_critical_table):
+        array [len(ns), len(gammas), n_q] of quantiles averaged over `seeds`
+        runs; with per_run also the runs' own quantiles [.., .., seeds, n_q]."""
+        g = (C.c_double * len(gammas))(*[float(v) for v in gammas])
+        n = (C.c_int64 * len(ns))(*[int(v) for v in ns])
+        q = list(quantiles)
+        qn = (C.c_uint32 * len(q))(*[a for a, _ in q])
+        qd = (C.c_uint32 * len(q))(*[b for _, b in q])
+        tab = np.zeros((len(ns), len(gammas), len(q)))
+        runs = np.zeros((len(ns), len(gammas), int(seeds), len(q))) if per_run else None
+        dp = C.POINTER(C.c_double)
+        _check(lib().zpl_critical_table(
+            self._h, g, len(gammas), n, len(ns), int(kmax), int(seeds), int(seed0),
+            int(replicates), qn, qd, len(q), tab.ctypes.data_as(dp),
+            runs.ctypes.data_as(dp) if per_run else None, _stream(stream)))
+        return (tab, runs) if per_run else tab
 
     # -- timing ---------------------------------------------------------------
     def autotune(self, alphas: Sequence[float], ns: Sequence[int], stream=None) -> list:

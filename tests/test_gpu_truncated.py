@@ -92,7 +92,9 @@ def test_draws_bit_exact(ctx, orc, g, K, n):
 @pytest.mark.parametrize("form", ["auto", "lane", "wave", "heavy"])
 def test_simulate_all_forms(ctx, orc, form):
     cells = [(0.25, 100, 300, 42, 0, 20), (1.0, 37, 200, 42, 1, 50), (2.5, 10, 520, 7, 2, 20),
-             (4.0, 10, 300, 7, 3, 1000), (1.5, 300, 130, 9, 4, 500), (-0.2, 60, 70, 9, 5, 100)]
+             (4.0, 10, 300, 7, 3, 1000), (1.5, 300, 130, 9, 4, 500), (-0.2, 60, 70, 9, 5, 100),
+             # spread over a large support: most draws take the deferred path
+             (0.5, 150, 130, 9, 6, 1000), (0.0, 40, 90, 3, 7, 2000)]
     say("simulate truncated", form)
     g = run_cells(ctx, cells, form=form)
     lo = 0
