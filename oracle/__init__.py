@@ -119,6 +119,18 @@ def _bind(L):
         L.orc_tz_simulate.argtypes = [d, ci, i64, u64, u32, i64, i64, P(d), P(d), P(d),
                                       P(u32), P(u64), P(i64), ci]
         L.orc_tz_simulate.restype = ci
+        L.orc_hz_cdf_table.argtypes = [d, i64, P(d)]
+        L.orc_hz_draw.argtypes = [d, i64, P(d), u64, u32, u32, u32, P(u32)]
+        L.orc_hz_draw.restype = i64
+        L.orc_hz_mle.argtypes = [d, i64, P(u32)]
+        L.orc_hz_mle.restype = d
+        L.orc_hz_fit.argtypes = [P(i64), i64, i64, P(i64), P(d), P(d), P(d), P(u32)]
+        L.orc_hz_fit.restype = ci
+        L.orc_hz_scan.argtypes = [P(i64), i64, P(i64), ci, P(d), P(d), P(i64), P(u32)]
+        L.orc_hz_scan.restype = ci
+        L.orc_hz_simulate.argtypes = [d, i64, i64, u64, u32, i64, i64, P(d), P(d), P(d),
+                                      P(u32), P(u64), P(i64), ci]
+        L.orc_hz_simulate.restype = ci
     return L
 
 
@@ -279,6 +291,78 @@ def tz_simulate(g: float, K: int, n: int, seed: int, stream: int, rep_lo: int, c
                                nthreads)
     if rc != 0:
         raise ValueError("oracle tz_simulate: invalid cell")
+    return {"D": D, "alpha_hat": A, "S": S, "flags": F, "fp": FP, "xmax": XM}
+
+
+# ---- the law with a lower cutoff xmin (p(k) proportional to k^-alpha, k >= xmin) ----
+
+def hz_cdf_table(alpha: float, xmin: int) -> np.ndarray:
+    T = np.zeros(TABLE_H)
+    lib().orc_hz_cdf_table(alpha, xmin, _ptr(T, C.c_double))
+    return T
+
+
+def hz_sample(alpha: float, xmin: int, n: int, seed: int, stream: int, rep: int):
+    """n draws of one replicate in draw order -> (int64 array, flags)."""
+    T = hz_cdf_table(alpha, xmin)
+    f = C.c_uint32(0)
+    x = np.array([lib().orc_hz_draw(alpha, xmin, _ptr(T, C.c_double), seed, stream, rep, i,
+                                    C.byref(f)) for i in range(n)], dtype=np.int64)
+    return x, f.value
+
+
+def hz_mle(m: float, xmin: int):
+    f = C.c_uint32(0)
+    a = lib().orc_hz_mle(m, xmin, C.byref(f))
+    return a, f.value
+
+
+def hz_fit(x, xmin: int) -> dict:
+    """Fit the values >= xmin: S, alpha_hat, D, flags and their count."""
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    S, a, D = C.c_double(), C.c_double(), C.c_double()
+    m = C.c_int64(0)
+    f = C.c_uint32(0)
+    rc = lib().orc_hz_fit(_ptr(x, C.c_int64), x.size, xmin, C.byref(m), C.byref(S), C.byref(a),
+                          C.byref(D), C.byref(f))
+    if rc == -1:
+        raise ValueError("oracle hz_fit: invalid dataset (n < 1, xmin < 1 or some x < 1)")
+    if rc == -2:
+        raise ValueError("oracle hz_fit: no value >= xmin")
+    return {"S": S.value, "alpha_hat": a.value, "D": D.value, "flags": f.value, "n_tail": m.value}
+
+
+def hz_scan(x, xmins) -> dict:
+    """The KS-minimising xmin among the candidates: per-candidate fits and
+    the index of the smallest D (the first on ties)."""
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    c = np.ascontiguousarray(xmins, dtype=np.int64)
+    A = np.zeros(c.size)
+    D = np.zeros(c.size)
+    M = np.zeros(c.size, dtype=np.int64)
+    F = np.zeros(c.size, dtype=np.uint32)
+    best = lib().orc_hz_scan(_ptr(x, C.c_int64), x.size, _ptr(c, C.c_int64), c.size,
+                             _ptr(A, C.c_double), _ptr(D, C.c_double), _ptr(M, C.c_int64),
+                             _ptr(F, C.c_uint32))
+    if best == -1:
+        raise ValueError("oracle hz_scan: invalid input")
+    return {"best": best, "alpha_hat": A, "D": D, "n_tail": M, "flags": F}
+
+
+def hz_simulate(alpha: float, xmin: int, n: int, seed: int, stream: int, rep_lo: int,
+                count: int, nthreads: int = 0) -> dict:
+    D = np.zeros(count)
+    A = np.zeros(count)
+    S = np.zeros(count)
+    F = np.zeros(count, dtype=np.uint32)
+    FP = np.zeros(count, dtype=np.uint64)
+    XM = np.zeros(count, dtype=np.int64)
+    rc = lib().orc_hz_simulate(alpha, xmin, n, seed, stream, rep_lo, count,
+                               _ptr(D, C.c_double), _ptr(A, C.c_double), _ptr(S, C.c_double),
+                               _ptr(F, C.c_uint32), _ptr(FP, C.c_uint64), _ptr(XM, C.c_int64),
+                               nthreads)
+    if rc != 0:
+        raise ValueError("oracle hz_simulate: invalid cell")
     return {"D": D, "alpha_hat": A, "S": S, "flags": F, "fp": FP, "xmax": XM}
 
 

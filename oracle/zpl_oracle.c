@@ -751,3 +751,283 @@ int orc_tz_simulate(double g, int K, int64_t n, uint64_t seed, uint32_t stream, 
   free(T);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The law with a lower cutoff xmin >= 1 (the practice the paper cites for   */
+/* fitting power laws to data, Sect. 1; the paper itself fixes xmin = 1):    */
+/*   p(k) = k^-alpha / zeta(alpha, xmin),  k >= xmin,                        */
+/*   F(t) = 1 - zeta(alpha, t+1) / zeta(alpha, xmin) for t >= xmin, else 0.  */
+/* MLE (eq. 2 with the Hurwitz zeta): -zeta'(a,xmin)/zeta(a,xmin) = mean     */
+/* ln x over the values >= xmin.  mu(a) = -zeta'(a,xmin)/zeta(a,xmin) is    */
+/* E_a[ln X], which decreases from +inf (a -> 1) to ln xmin (a -> inf), so a  */
+/* root exists exactly when some value exceeds xmin.  If every value equals   */
+/* xmin, one of them is counted as xmin + 1 (the all-ones rule of the pure    */
+/* law, where xmin = 1).  xmin = 1 is the pure law and uses its functions.   */
+/* ------------------------------------------------------------------------ */
+void orc_hz_cdf_table(double alpha, int64_t xmin, double *T) {
+  const double z = hurwitz0(alpha, (double)xmin);
+  for (int j = 1; j <= ORC_TABLE_H; ++j)
+    T[j - 1] = 1.0 - hurwitz0(alpha, (double)(xmin + j)) / z;
+}
+
+/* Tail of the law with cutoff: k >= m = xmin + H, the same floored-Pareto   */
+/* rejection sampler as orc_tail_draw with its start moved to m.             */
+static int64_t hz_tail_draw(double alpha, int64_t xmin, uint64_t seed, uint32_t stream,
+                            uint32_t rep, uint32_t i, uint32_t *flags) {
+  const double beta = alpha - 1.0;
+  const double m = (double)(xmin + ORC_TABLE_H);
+  const double gm = tail_g(beta, m);
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const __float128 two63 = 9223372036854775808.0Q;
+  for (uint32_t attempt = 0; attempt < 0x7fffffffu; ++attempt) {
+    uint32_t ctr[4] = {i, rep, stream, 0x80000000u | attempt};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double V = orc_u53(w[0], w[1]);
+    double W = orc_u53(w[2], w[3]);
+    __float128 Y = (__float128)m * expq(-logq((__float128)V) / (__float128)beta);
+    if (Y >= two63) {
+      *flags |= ORC_FLAG_TAIL_CAPPED;
+      continue;
+    }
+    int64_t X = (int64_t)floorq(Y);
+    if (W * gm <= tail_g(beta, (double)X)) return X;
+  }
+  return xmin + ORC_TABLE_H; /* unreachable in practice */
+}
+
+int64_t orc_hz_draw(double alpha, int64_t xmin, const double *T, uint64_t seed,
+                    uint32_t stream, uint32_t rep, uint32_t i, uint32_t *flags) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {i >> 1, rep, stream, 0u};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  double U = (i & 1u) ? orc_u53(w[2], w[3]) : orc_u53(w[0], w[1]);
+  if (U > T[ORC_TABLE_H - 1]) return hz_tail_draw(alpha, xmin, seed, stream, rep, i, flags);
+  int lo = 1, hi = ORC_TABLE_H;
+  while (lo < hi) {
+    int mid = lo + (hi - lo) / 2;
+    if (T[mid - 1] >= U)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return xmin - 1 + (int64_t)lo;
+}
+
+/* Newton-Raphson on g(a) = mu(a) - m in the bracket [1 + 2^-20, 64], as     */
+/* orc_mle; stops after a step of at most 2^-40 a (with a large cutoff the   */
+/* variance of ln X is small and mu is known to a few ulps only, so a        */
+/* tighter test can lie below the noise).  With a large cutoff a sample      */
+/* close to xmin can have its root above 64 (mu(64) - ln xmin is only about  */
+/* 64/xmin^2 ... 1/xmin): then NOCONV and the bracket end 64.                */
+double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
+  if (xmin == 1) return orc_mle(m, flags);
+  const double q = (double)xmin;
+  double lo = 1.0 + 0x1p-20, hi = 64.0;
+  {
+    double z[3];
+    orc_hurwitz3(hi, q, z);
+    if (!(m > -z[1] / z[0])) { /* m at or below mu(64): the root is above 64 */
+      *flags |= ORC_FLAG_NOCONV;
+      return hi;
+    }
+  }
+  double a = 1.0 + 1.0 / (m - log(q - 0.5)); /* continuous Pareto from xmin - 1/2 */
+  if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    double z[3];
+    orc_hurwitz3(a, q, z);
+    double r1 = z[1] / z[0];
+    double g = -r1 - m;
+    if (g == 0.0) return a;
+    if (g > 0.0)
+      lo = a;
+    else
+      hi = a;
+    double gp = -(z[2] / z[0] - r1 * r1);
+    double an = a - g / gp;
+    if (!(an >= lo && an <= hi)) {
+      an = 0.5 * (lo + hi);
+      *flags |= ORC_FLAG_BISECT;
+    }
+    if (fabs(an - a) <= 0x1p-40 * a) return an;
+    a = an;
+  }
+  *flags |= ORC_FLAG_NOCONV;
+  return a;
+}
+
+/* D over the sorted values (all >= xmin): as ks_sorted with zeta(a, xmin)   */
+/* as the normaliser and F(xmin - 1) = 0.                                    */
+static double hz_ks_sorted(const int64_t *xs, int64_t n, double a, int64_t xmin) {
+  const double z = hurwitz0(a, (double)xmin);
+  const double dn = (double)n;
+  double D = 0.0;
+  int64_t i = 0;
+  while (i < n) {
+    int64_t v = xs[i];
+    int64_t below = i;
+    while (i < n && xs[i] == v) ++i;
+    int64_t upto = i;
+    double Fv = 1.0 - hurwitz0(a, (double)v + 1.0) / z;
+    double Fv1 = (v - 1 < xmin) ? 0.0 : 1.0 - hurwitz0(a, (double)v) / z;
+    double d1 = fabs((double)upto / dn - Fv);
+    double d2 = fabs((double)below / dn - Fv1);
+    if (d1 > D) D = d1;
+    if (d2 > D) D = d2;
+  }
+  return D;
+}
+
+/* xs sorted ascending, every value >= xmin. */
+static void hz_fit_sorted(const int64_t *xs, int64_t n, int64_t xmin, double *S, double *ahat,
+                          double *D, uint32_t *flags) {
+  if (xmin == 1) {
+    fit_sorted(xs, n, S, ahat, D, flags);
+    return;
+  }
+  double s;
+  if (xs[n - 1] == xmin) { /* every value at the cutoff: count one as xmin + 1 */
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    memcpy(tmp, xs, sizeof(int64_t) * (size_t)n);
+    tmp[n - 1] = xmin + 1;
+    s = neumaier_sum_log(tmp, n);
+    free(tmp);
+    *flags |= ORC_FLAG_ALL_ONES;
+  } else {
+    s = neumaier_sum_log(xs, n);
+  }
+  double a = orc_hz_mle(s / (double)n, xmin, flags);
+  *S = s;
+  *ahat = a;
+  *D = hz_ks_sorted(xs, n, a, xmin);
+}
+
+int orc_hz_fit(const int64_t *x, int64_t n, int64_t xmin, int64_t *n_tail, double *S,
+               double *alpha_hat, double *D, uint32_t *flags) {
+  if (n < 1 || xmin < 1) return -1;
+  int64_t *xs = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!xs) return -1;
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (x[i] < 1) {
+      free(xs);
+      return -1;
+    }
+    if (x[i] >= xmin) xs[m++] = x[i];
+  }
+  *n_tail = m;
+  if (m == 0) {
+    free(xs);
+    return -2;
+  }
+  qsort(xs, (size_t)m, sizeof(int64_t), cmp_i64);
+  uint32_t f = 0;
+  hz_fit_sorted(xs, m, xmin, S, alpha_hat, D, &f);
+  *flags = f;
+  free(xs);
+  return 0;
+}
+
+/* The KS-minimising choice of xmin: fit the values >= xmin for every        */
+/* candidate and keep the one with the smallest D (the first on ties).       */
+/* Candidates with no value at or above them get D = +inf.  Returns the     */
+/* index of the chosen candidate, or -1 on invalid input.                    */
+int orc_hz_scan(const int64_t *x, int64_t n, const int64_t *xmins, int n_xmin,
+                double *alpha_hat, double *D, int64_t *n_tail, uint32_t *flags) {
+  int best = -1;
+  for (int c = 0; c < n_xmin; ++c) {
+    double s;
+    int rc = orc_hz_fit(x, n, xmins[c], &n_tail[c], &s, &alpha_hat[c], &D[c], &flags[c]);
+    if (rc == -1) return -1;
+    if (rc == -2) {
+      alpha_hat[c] = 0.0;
+      D[c] = INFINITY;
+      flags[c] = 0;
+      continue;
+    }
+    if (best < 0 || D[c] < D[best]) best = c;
+  }
+  return best;
+}
+
+typedef struct {
+  double alpha;
+  int64_t xmin, n;
+  uint64_t seed;
+  uint32_t stream;
+  int64_t rep_lo;
+  const double *T;
+  double *D, *ahat, *S;
+  uint32_t *flags;
+  uint64_t *fp;
+  int64_t *xmax;
+  int64_t begin, end;
+} hz_job;
+
+static void *hz_worker(void *arg) {
+  hz_job *j = (hz_job *)arg;
+  int64_t *x = (int64_t *)malloc(sizeof(int64_t) * (size_t)j->n);
+  for (int64_t r = j->begin; r < j->end; ++r) {
+    uint32_t rep = (uint32_t)(j->rep_lo + r);
+    uint32_t f = 0;
+    uint64_t h = 0;
+    for (int64_t i = 0; i < j->n; ++i) {
+      x[i] = orc_hz_draw(j->alpha, j->xmin, j->T, j->seed, j->stream, rep, (uint32_t)i, &f);
+      h += mix64((uint64_t)x[i]);
+    }
+    qsort(x, (size_t)j->n, sizeof(int64_t), cmp_i64);
+    double s, a, d;
+    hz_fit_sorted(x, j->n, j->xmin, &s, &a, &d, &f);
+    if (j->D) j->D[r] = d;
+    if (j->ahat) j->ahat[r] = a;
+    if (j->S) j->S[r] = s;
+    if (j->flags) j->flags[r] = f;
+    if (j->fp) j->fp[r] = h;
+    if (j->xmax) j->xmax[r] = x[j->n - 1];
+  }
+  free(x);
+  return NULL;
+}
+
+int orc_hz_simulate(double alpha, int64_t xmin, int64_t n, uint64_t seed, uint32_t stream,
+                    int64_t rep_lo, int64_t count, double *D, double *alpha_hat, double *S,
+                    uint32_t *flags, uint64_t *fp, int64_t *xmax, int nthreads) {
+  if (n < 1 || count < 0 || xmin < 1 || !(alpha > 1.0)) return -1;
+  double *T = (double *)malloc(sizeof(double) * ORC_TABLE_H);
+  if (!T) return -1;
+  orc_hz_cdf_table(alpha, xmin, T);
+  int nt = resolve_threads(nthreads);
+  if (nt > count) nt = count > 0 ? (int)count : 1;
+  hz_job *jobs = (hz_job *)calloc((size_t)nt, sizeof(hz_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)nt, sizeof(pthread_t));
+  for (int t = 0; t < nt; ++t) {
+    hz_job *j = &jobs[t];
+    j->alpha = alpha;
+    j->xmin = xmin;
+    j->n = n;
+    j->seed = seed;
+    j->stream = stream;
+    j->rep_lo = rep_lo;
+    j->T = T;
+    j->D = D;
+    j->ahat = alpha_hat;
+    j->S = S;
+    j->flags = flags;
+    j->fp = fp;
+    j->xmax = xmax;
+    j->begin = count * t / nt;
+    j->end = count * (t + 1) / nt;
+    if (nt == 1)
+      hz_worker(j);
+    else
+      pthread_create(&th[t], NULL, hz_worker, j);
+  }
+  if (nt > 1)
+    for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+  free(th);
+  free(jobs);
+  free(T);
+  return 0;
+}

@@ -117,6 +117,34 @@ int orc_tz_simulate(double g, int K, int64_t n, uint64_t seed, uint32_t stream, 
                     int64_t count, double *D, double *g_hat, double *S, uint32_t *flags,
                     uint64_t *fp, int64_t *xmax, int nthreads);
 
+/* ---- the law with a lower cutoff xmin >= 1: p(k) = k^-alpha / zeta(alpha, xmin), k >= xmin ---- */
+
+/* T[j-1] = F(xmin + j - 1), j = 1..ORC_TABLE_H. */
+void orc_hz_cdf_table(double alpha, int64_t xmin, double *T);
+
+/* Draw i of replicate rep: xmin - 1 + min{j : T[j] >= U}, or the rejection
+ * tail on k >= xmin + ORC_TABLE_H. */
+int64_t orc_hz_draw(double alpha, int64_t xmin, const double *T, uint64_t seed,
+                    uint32_t stream, uint32_t rep, uint32_t i, uint32_t *flags);
+
+/* alpha_hat for mean ln x = m (NOCONV and 64 when m <= ln xmin). */
+double orc_hz_mle(double m, int64_t xmin, uint32_t *flags);
+
+/* Fit the values >= xmin of a dataset.  Returns -1 on invalid input (n < 1,
+ * xmin < 1, some x < 1), -2 if no value is >= xmin. */
+int orc_hz_fit(const int64_t *x, int64_t n, int64_t xmin, int64_t *n_tail, double *S,
+               double *alpha_hat, double *D, uint32_t *flags);
+
+/* Fit for every candidate xmin; returns the index of the smallest D (first
+ * on ties), -1 on invalid input.  D = +inf for a candidate above every value. */
+int orc_hz_scan(const int64_t *x, int64_t n, const int64_t *xmins, int n_xmin,
+                double *alpha_hat, double *D, int64_t *n_tail, uint32_t *flags);
+
+/* orc_simulate for the law with cutoff xmin. */
+int orc_hz_simulate(double alpha, int64_t xmin, int64_t n, uint64_t seed, uint32_t stream,
+                    int64_t rep_lo, int64_t count, double *D, double *alpha_hat, double *S,
+                    uint32_t *flags, uint64_t *fp, int64_t *xmax, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

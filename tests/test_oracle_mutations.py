@@ -41,6 +41,18 @@ MUTANTS = [
      "uint64_t idx = ((uint64_t)R * (uint64_t)num) / (uint64_t)den + 1;"),
     ("MLE equation sign", "double g = -r1 - m;", "double g = r1 - m;"),
     ("bootstrap strict inequality", "if (Db[b] >= d) ++ge;", "if (Db[b] > d) ++ge;"),
+    # the law with a lower cutoff xmin
+    ("xmin draw offset", "return xmin - 1 + (int64_t)lo;", "return xmin + (int64_t)lo;"),
+    ("xmin table normalised by zeta(alpha)", "const double z = hurwitz0(alpha, (double)xmin);",
+     "const double z = hurwitz0(alpha, 1.0);"),
+    ("xmin KS normalised by zeta(a)", "const double z = hurwitz0(a, (double)xmin);",
+     "const double z = hurwitz0(a, 1.0);"),
+    ("xmin MLE with zeta(a)", "orc_hurwitz3(a, q, z);", "orc_hurwitz3(a, 1.0, z);"),
+    ("xmin cutoff rule counts xmin + 2", "tmp[n - 1] = xmin + 1;", "tmp[n - 1] = xmin + 2;"),
+    ("xmin scan keeps the largest D", "if (best < 0 || D[c] < D[best]) best = c;",
+     "if (best < 0 || D[c] > D[best]) best = c;"),
+    ("xmin tail starts at the pure law's", "const double m = (double)(xmin + ORC_TABLE_H);",
+     "const double m = (double)(ORC_TABLE_H + 1);"),
 ]
 
 
@@ -102,6 +114,49 @@ def _checks(orc):
     ones = orc.bootstrap_pvalue(np.ones(10, np.int64), 300, 3, 1)
     if ones["p_value"] < 0.3:
         failed.append("bootstrap ties")
+    failed += _checks_xmin(orc)
+    return failed
+
+
+def _checks_xmin(orc):
+    """Quick pins of the law with a lower cutoff."""
+    failed = []
+    T = orc.hz_cdf_table(2.5, 7)
+    with mp.workdps(30):
+        want = (mp.mpf(7) ** -2.5 + mp.mpf(8) ** -2.5 + mp.mpf(9) ** -2.5) / mp.zeta(2.5, 7)
+    if abs(T[2] - float(want)) > 1e-15:
+        failed.append("xmin table")
+    for a, xmin in ((2.5, 3), (1.6, 500)):
+        T = orc.hz_cdf_table(a, xmin)
+        x, _ = orc.hz_sample(a, xmin, 300, 9, 2, 11)
+        for i in range(300):
+            w = orc.philox([i >> 1, 11, 2, 0], [9, 0])
+            U = orc.u53(w[2], w[3]) if i & 1 else orc.u53(w[0], w[1])
+            body = U <= T[-1]
+            if (body and x[i] != xmin + int(np.searchsorted(T, U, side="left"))) or \
+                    (not body and x[i] < xmin + 4096):
+                failed.append("xmin draws")
+                break
+    xs = np.array([3, 3, 4, 6, 9, 30, 3, 5])
+    r = orc.hz_fit(xs, 3)
+    a = r["alpha_hat"]
+    with mp.workdps(30):
+        z = mp.zeta(a, 3)
+        best, F = mp.mpf(0), mp.mpf(0)
+        for t in range(3, 40):
+            F += mp.mpf(t) ** (-a) / z
+            best = max(best, abs(F - mp.mpf(int(np.sum(xs <= t))) / len(xs)))
+        mu = -mp.zeta(a, 3, 1) / z
+    if abs(r["D"] - float(best)) > 1e-12:
+        failed.append("xmin KS")
+    if abs(float(mu) - r["S"] / len(xs)) > 1e-12:
+        failed.append("xmin MLE equation")
+    r = orc.hz_fit(np.full(10, 2), 2)
+    if abs(r["S"] - (9 * math.log(2) + math.log(3))) > 1e-12:
+        failed.append("xmin cutoff rule")
+    sc = orc.hz_scan(np.array([1, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89]), [1, 2, 3, 5, 8])
+    if sc["best"] != int(np.argmin(sc["D"])):
+        failed.append("xmin scan")
     return failed
 
 
