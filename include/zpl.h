@@ -64,10 +64,10 @@ typedef int32_t zpl_status;
 #define ZPL_ENOTFOUND (-6) /* serving: unknown ticket                          */
 
 /* Per-replicate / per-fit flags. */
-#define ZPL_FLAG_ALL_ONES 1u    /* every value was 1; S replaced by ln 2          */
+#define ZPL_FLAG_ALL_ONES 1u    /* every value was 1 (at xmin); one counted as 2 (xmin + 1) */
 #define ZPL_FLAG_TAIL_CAPPED 2u /* a tail proposal >= 2^63 was redrawn            */
 #define ZPL_FLAG_BISECT 4u      /* the MLE solver took a bisection step (info)    */
-#define ZPL_FLAG_NOCONV 8u      /* the MLE solver hit its iteration cap           */
+#define ZPL_FLAG_NOCONV 8u      /* no MLE root in the bracket, or the iteration cap */
 
 typedef struct zpl_ctx zpl_ctx;
 
@@ -82,7 +82,17 @@ typedef struct zpl_ctx zpl_ctx;
  *             on k = 1..K (Sect. 1 with a finite upper limit); alpha may be
  *             any value in [-64, 64], and alpha_hat is solved on [-64, 64]
  *             (ZPL_FLAG_NOCONV and the bracket end when the sample's mean log
- *             has no root there, e.g. every value equal to K). */
+ *             has no root there, e.g. every value equal to K).
+ *   xmin      lower cutoff of the pure law (0 or 1: none; kmax must be 0
+ *             otherwise; at most 2^40): p(k) = k^-alpha / zeta(alpha, xmin) on
+ *             k >= xmin, the law used when a power law is fitted to the upper
+ *             part of data (the practice the paper cites; its own tables have
+ *             xmin = 1).  alpha_hat solves eq. (2) with the Hurwitz zeta on
+ *             [1 + 2^-20, 64] (ZPL_FLAG_NOCONV and 64 when the root lies
+ *             above); D is eq. (3) with F(t) = 1 - zeta(a, t+1)/zeta(a, xmin).
+ *             If every value equals xmin, one is counted as xmin + 1 (the
+ *             all-ones rule) and ZPL_FLAG_ALL_ONES is set.  Such cells run in
+ *             the heavy form. */
 typedef struct zpl_cell {
   double alpha;
   int64_t n;
@@ -90,6 +100,7 @@ typedef struct zpl_cell {
   uint64_t seed;
   uint32_t stream;
   uint32_t kmax;
+  int64_t xmin;
 } zpl_cell;
 
 /* Launch form of zpl_simulate_cells. */
@@ -290,20 +301,52 @@ zpl_status zpl_serve_poll(zpl_ctx *ctx, uint64_t ticket, int32_t wait_ms,
 /* Finish the queued requests and stop the scheduler. */
 zpl_status zpl_serve_stop(zpl_ctx *ctx);
 
-/* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, kmax, n,
- * seed, stream_id) in draw order, for checking the sampler bit for bit
- * (alpha and kmax as in zpl_cell).
+/* Raw draws of replicates rep_lo .. rep_lo+count-1 of cell (alpha, kmax, xmin,
+ * n, seed, stream_id) in draw order, for checking the sampler bit for bit
+ * (alpha, kmax and xmin as in zpl_cell).
  *   x_out     device [count * n] int64;  flags_out device [count] uint32
  *             (ZPL_FLAG_TAIL_CAPPED per replicate).
  * Asynchronous on `stream`. */
-zpl_status zpl_sample_draws(zpl_ctx *ctx, double alpha, uint32_t kmax, int64_t n, uint64_t seed,
-                            uint32_t stream_id, int64_t rep_lo, int64_t count,
+zpl_status zpl_sample_draws(zpl_ctx *ctx, double alpha, uint32_t kmax, int64_t xmin, int64_t n,
+                            uint64_t seed, uint32_t stream_id, int64_t rep_lo, int64_t count,
                             int64_t *x_out, uint32_t *flags_out, void *stream);
 
-/* The FP64 CDF table F(k; alpha), k = 1..4096, the sampler searches (the
- * truncated law's for kmax > 0, with F(k) = 1 for k >= kmax).
+/* The FP64 CDF table the sampler searches: T[j-1] = F(xmin - 1 + j; alpha),
+ * j = 1..4096 (the truncated law's for kmax > 0, with F(k) = 1 for k >= kmax;
+ * xmin as in zpl_cell).
  *   T_out  device [4096].  Asynchronous on `stream`. */
-zpl_status zpl_cdf_table(zpl_ctx *ctx, double alpha, uint32_t kmax, double *T_out, void *stream);
+zpl_status zpl_cdf_table(zpl_ctx *ctx, double alpha, uint32_t kmax, int64_t xmin, double *T_out,
+                         void *stream);
+
+/* --------------------------------------------------------------------------
+ * Fitting the upper part of data (the practice the paper cites for power-law
+ * fits; the paper's own method has xmin = 1): the law with lower cutoff xmin
+ * is fitted to the values >= xmin only (eq. 2 and eq. 3 with the Hurwitz
+ * zeta, as for a zpl_cell with that xmin), and xmin itself is chosen as the
+ * candidate whose fit has the smallest D.
+ * ------------------------------------------------------------------------ */
+
+/* Fit for each candidate cutoff, one wavefront per candidate, in one launch.
+ *   x[n]            host (x_on_device = 0) or device int64, every x >= 1
+ *                   (values below a candidate are ignored for that candidate).
+ *   xmins[n_xmin]   host; each in [1, 2^40]; 1 <= n_xmin <= 65536.
+ *   alpha_hat, D, n_tail, flags   host [n_xmin]: the fit of the values >=
+ *                   xmins[c] and their count; a candidate above every value
+ *                   has n_tail = 0, D = +inf, alpha_hat = 0.
+ *   best            host: index of the smallest D (the first on ties), or -1
+ *                   when no candidate has a value at or above it.
+ * ZPL_EINVAL for n < 1, n > 2^31, any x < 1 or a candidate out of range.
+ * A candidate whose MLE root lies above 64 keeps ZPL_FLAG_NOCONV in its flags
+ * (the call still succeeds).  Synchronises the stream. */
+zpl_status zpl_fit_scan(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
+                        const int64_t *xmins, int32_t n_xmin, double *alpha_hat, double *D,
+                        int64_t *n_tail, uint32_t *flags, int32_t *best, void *stream);
+
+/* zpl_fit_scan with the one candidate xmin.  ZPL_EINVAL also when no value is
+ * >= xmin; ZPL_ENOCONV (outputs still set) when the MLE root lies above 64. */
+zpl_status zpl_fit_xmin(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
+                        int64_t xmin, double *alpha_hat, double *D, int64_t *n_tail,
+                        uint32_t *flags, void *stream);
 
 #ifdef __cplusplus
 }

@@ -72,6 +72,7 @@ const HostLn& host_ln() {
 // the capped rejection sampler take many attempts per draw.  (Fitted
 // exponents are never below about 1.023: mean ln x < ln 2^63.)
 constexpr double kMinAlpha = 1.01;
+constexpr int64_t kMaxXmin = (int64_t)1 << 40;
 
 // P(X > h) under exponent a: the pure law (K = 0) or the truncated law on
 // 1..K (finite sums).
@@ -112,7 +113,8 @@ struct zpl_ctx {
   double* ln = nullptr;
   // scratch, grow-only
   DevBuf cells, tables, guides, units, hunits, queues, esc, esc_cnt, err, list_v, list_c,
-      wslots, heavy, dbuf, gather, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d;
+      wslots, heavy, dbuf, gather, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d,
+      scan;
   // pinned host staging
   void* pin = nullptr;
   size_t pin_bytes = 0;
@@ -335,6 +337,12 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
       if (!(z.alpha >= -64.0) || !(z.alpha <= 64.0))
         return fail(ZPL_EINVAL, "cell %d: alpha must be in [-64, 64], got %g", i, z.alpha);
     }
+    const int64_t xmin = z.xmin == 0 ? 1 : z.xmin;
+    if (xmin < 1 || xmin > kMaxXmin)
+      return fail(ZPL_EINVAL, "cell %d: xmin must be 0, 1 or in [2, 2^40], got %lld", i,
+                  (long long)z.xmin);
+    if (xmin > 1 && z.kmax != 0)
+      return fail(ZPL_EINVAL, "cell %d: xmin > 1 needs kmax = 0 (the pure law)", i);
     if (z.n < 1 || z.n > ((int64_t)1 << 31))
       return fail(ZPL_EINVAL, "cell %d: n must be in [1, 2^31], got %lld", i, (long long)z.n);
     if (z.replicates < 1 || z.replicates > ((int64_t)1 << 32))
@@ -350,6 +358,7 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
     d.k1 = (uint32_t)(z.seed >> 32);
     d.stream = z.stream;
     d.K = z.kmax;
+    d.xmin = xmin;
     uint32_t m;
     switch (form) {
       case ZPL_FORM_LANE:
@@ -359,6 +368,13 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
       case ZPL_FORM_WAVE: m = kModeWave; break;
       case ZPL_FORM_HEAVY: m = kModeHeavy; break;
       default: m = choose_form(z.alpha, z.n, tune, z.kmax);
+    }
+    // the lane and wave forms histogram values from 1; a cutoff law runs in
+    // the heavy form, whose histogram and overflow list take any values
+    if (xmin > 1) {
+      if (form == ZPL_FORM_LANE || form == ZPL_FORM_WAVE)
+        return fail(ZPL_EINVAL, "cell %d: a cell with xmin > 1 runs in the heavy form only", i);
+      m = kModeHeavy;
     }
     d.mode = m;
     P.total_R += z.replicates;
@@ -1005,7 +1021,7 @@ void zpl_destroy(zpl_ctx* c) {
   DevBuf* bufs[] = {&c->cells, &c->tables, &c->guides, &c->units, &c->hunits, &c->queues,
                     &c->esc, &c->esc_cnt, &c->err, &c->list_v, &c->list_c, &c->wslots, &c->heavy, &c->gather,
                     &c->dbuf, &c->qnum, &c->qden, &c->qout, &c->fit_x, &c->fit_ptrs,
-                    &c->fit_ns, &c->fit_out, &c->fit_st, &c->count, &c->boot_d};
+                    &c->fit_ns, &c->fit_out, &c->fit_st, &c->count, &c->boot_d, &c->scan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->ln) (void)hipFree(c->ln);
@@ -1166,6 +1182,75 @@ zpl_status zpl_fit(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
   return ZPL_OK;
 }
 
+zpl_status zpl_fit_scan(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                        const int64_t* xmins, int32_t n_xmin, double* alpha_hat, double* D,
+                        int64_t* n_tail, uint32_t* flags, int32_t* best, void* stream) {
+  g_err.clear();
+  if (!c || !x || !xmins || !alpha_hat || !D || !n_tail || !flags || !best)
+    return fail(ZPL_EINVAL, "NULL argument");
+  if (n < 1 || n > ((int64_t)1 << 31)) return fail(ZPL_EINVAL, "n must be in [1, 2^31]");
+  if (n_xmin < 1 || n_xmin > 65536) return fail(ZPL_EINVAL, "n_xmin must be in [1, 65536]");
+  for (int i = 0; i < n_xmin; ++i)
+    if (xmins[i] < 1 || xmins[i] > kMaxXmin)
+      return fail(ZPL_EINVAL, "candidate %d: xmin must be in [1, 2^40], got %lld", i,
+                  (long long)xmins[i]);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t* xd;
+  ZPL_TRY(stage_x(c, x, n, x_on_device, s, &xd));
+  // one wave per candidate; each wave keeps its overflow and list areas in
+  // the heavy scratch, so the grid is what a quarter of the budget holds
+  const int64_t stride = heavy_stride(n);
+  int grid = std::min(n_xmin, 4 * c->n_cu);
+  while (grid > 1 && (uint64_t)grid * stride * 8 > c->budget / 4) grid /= 2;
+  const size_t nc = (size_t)n_xmin;
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)stride * grid));
+  ZPL_TRY(ensure(c, c->scan, nc * (sizeof(int64_t) + 2 * sizeof(double) + sizeof(int64_t) +
+                                   2 * sizeof(uint32_t))));
+  const size_t host_bytes = nc * (2 * sizeof(double) + sizeof(int64_t) + 2 * sizeof(uint32_t));
+  ZPL_TRY(ensure_pinned(c, std::max(host_bytes, nc * sizeof(int64_t))));
+  HIP_TRY(hipStreamSynchronize(s));  // the staging area may still be in use
+  std::memcpy(c->pin, xmins, nc * sizeof(int64_t));
+  char* dp = (char*)c->scan.p;
+  int64_t* d_xmins = (int64_t*)dp;
+  double* d_a = (double*)(dp + nc * 8);
+  double* d_D = d_a + nc;
+  int64_t* d_nt = (int64_t*)(d_D + nc);
+  uint32_t* d_fl = (uint32_t*)(d_nt + nc);
+  uint32_t* d_st = d_fl + nc;
+  HIP_TRY(hipMemcpyAsync(d_xmins, c->pin, nc * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_fit_scan(grid, xd, n, d_xmins, n_xmin, c->ln, (int64_t*)c->heavy.p, stride,
+                          d_a, d_D, d_nt, d_fl, d_st, s));
+  // results: alpha_hat, D, n_tail, flags, status are contiguous on the device
+  HIP_TRY(hipMemcpyAsync(c->pin, d_a, host_bytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const char* hp = (const char*)c->pin;
+  std::memcpy(alpha_hat, hp, nc * 8);
+  std::memcpy(D, hp + nc * 8, nc * 8);
+  std::memcpy(n_tail, hp + nc * 16, nc * 8);
+  std::memcpy(flags, hp + nc * 24, nc * 4);
+  const uint32_t* st = (const uint32_t*)(hp + nc * 28);
+  int b = -1;
+  for (int i = 0; i < n_xmin; ++i) {
+    if (st[i] & kErrBadValue) return fail(ZPL_EINVAL, "every x must be >= 1");
+    if (st[i] & kErrNoTail) continue;
+    if (b < 0 || D[i] < D[b]) b = i;
+  }
+  *best = b;
+  return ZPL_OK;
+}
+
+zpl_status zpl_fit_xmin(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                        int64_t xmin, double* alpha_hat, double* D, int64_t* n_tail,
+                        uint32_t* flags, void* stream) {
+  int32_t best = -1;
+  ZPL_TRY(zpl_fit_scan(c, x, n, x_on_device, &xmin, 1, alpha_hat, D, n_tail, flags, &best,
+                       stream));
+  if (best < 0) return fail(ZPL_EINVAL, "no value is >= xmin = %lld", (long long)xmin);
+  if (*flags & ZPL_FLAG_NOCONV) return fail(ZPL_ENOCONV, "the MLE root lies above 64");
+  return ZPL_OK;
+}
+
 zpl_status zpl_fit_truncated(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
                              uint32_t kmax, double* alpha_hat, double* D, uint32_t* flags,
                              void* stream) {
@@ -1320,8 +1405,8 @@ zpl_status zpl_serve_stop(zpl_ctx* c) {
   return ZPL_OK;
 }
 
-zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t n, uint64_t seed,
-                            uint32_t stream_id, int64_t rep_lo, int64_t count,
+zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmin, int64_t n,
+                            uint64_t seed, uint32_t stream_id, int64_t rep_lo, int64_t count,
                             int64_t* x_out, uint32_t* flags_out, void* stream) {
   g_err.clear();
   if (!c || !x_out || !flags_out) return fail(ZPL_EINVAL, "NULL argument");
@@ -1330,9 +1415,9 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t n, 
     return fail(ZPL_EINVAL, "bad n / replicate range");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  zpl_cell z = {alpha, n, count, seed, stream_id, kmax};
+  zpl_cell z = {alpha, n, count, seed, stream_id, kmax, xmin};
   Plan P;
-  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha and kmax
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha, kmax and xmin
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
@@ -1350,14 +1435,15 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t n, 
   return ZPL_OK;
 }
 
-zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, uint32_t kmax, double* T_out, void* stream) {
+zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmin, double* T_out,
+                         void* stream) {
   g_err.clear();
   if (!c || !T_out) return fail(ZPL_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  zpl_cell z = {alpha, 1, 1, 0, 0, kmax};
+  zpl_cell z = {alpha, 1, 1, 0, 0, kmax, xmin};
   Plan P;
-  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha and kmax
+  ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha, kmax and xmin
   ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));

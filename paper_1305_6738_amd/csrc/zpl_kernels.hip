@@ -177,6 +177,25 @@ __device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k
   return tail_draw(beta, gm, k0, k1, i, rep, stream, flags);
 }
 
+__device__ __noinline__ int64_t tail_draw_from_dev(double m0, double beta, double gm,
+                                                   uint32_t k0, uint32_t k1, uint32_t i,
+                                                   uint32_t rep, uint32_t stream,
+                                                   uint32_t* flags) {
+  return tail_draw_from(m0, beta, gm, k0, k1, i, rep, stream, flags);
+}
+
+// Resolves a deferred draw of a cell with a lower cutoff (xmin = 1 for the
+// pure law): the table index j is the value xmin - 1 + j, the tail starts at
+// xmin + kH.
+__device__ __forceinline__ int64_t resolve_x(const QEntry& e, uint32_t rep, const DevCell& c,
+                                             const uint64_t* __restrict__ T,
+                                             const uint32_t* __restrict__ guide, uint32_t& fl) {
+  if (e.i & kTailBit)
+    return tail_draw_from_dev((double)(c.xmin + kH), c.beta, c.gm, c.k0, c.k1, e.i & ~kTailBit,
+                              rep, c.stream, &fl);
+  return (c.xmin - 1) + (int64_t)slow_search(e.m, T, guide);
+}
+
 // Resolves a deferred draw.
 __device__ __forceinline__ int64_t resolve(const QEntry& e, uint32_t rep, const DevCell& c,
                                            const uint64_t* __restrict__ T,
@@ -417,10 +436,12 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return v;
 }
 
+// iz = 1/zeta(a, xmin): F(t) = 1 - zeta(a, t+1) iz for t >= xmin - 1 (the
+// first distinct value's lower term is then zero).
 __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_t* __restrict__ lc,
                                    int len, const EmCoef& E, const double (&suf)[17], int64_t n,
-                                   const double* __restrict__ ln, int lane) {
-  const double iz = 1.0 / suf[0], idn = 1.0 / (double)n;
+                                   const double* __restrict__ ln, int lane, double iz) {
+  const double idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0;
   int p = 0;
@@ -471,10 +492,32 @@ __device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const u
                                                       const U128& S, int64_t n, uint32_t fl,
                                                       const double* __restrict__ ln, int lane,
                                                       uint32_t K, double& ahat, double& D,
-                                                      uint32_t& flags) {
+                                                      uint32_t& flags, int64_t xmin = 1) {
   if (K) {  // O(K) per replicate either way: every lane runs the same sequence
     ListSrc src(lv, lc, len);
     finish_replicate(src, S, n, fl, ln, K, ahat, D, flags);
+    return;
+  }
+  if (xmin > 1) {  // the law with a lower cutoff (every value >= xmin)
+    U128 Sx = S;
+    if (len == 1 && lv[0] == xmin) {  // every value at the cutoff: one counts as xmin + 1
+      Sx = U128{0, 0};
+      u128_add_mul(Sx, (uint64_t)(n - 1), ln_fixed(xmin, ln));
+      u128_add(Sx, ln_fixed(xmin + 1, ln), 0);
+      fl |= kFlagAllOnes;
+    }
+    const double a = mle_alpha_hz(u128_to_S(Sx) / (double)n, xmin, ln, &fl);
+    const EmCoef E = em_coef(a);
+    double suf[17];
+    survival_head(E, ln, suf);
+    double zx = 0.0;  // zeta(a, xmin) = suf[xmin - 1] (static indices: no scratch)
+#pragma unroll
+    for (int t = 1; t <= 16; ++t)
+      if (xmin - 1 == t) zx = suf[t];
+    if (xmin > 17) zx = hurwitz_tail(E, (double)xmin, ln_value(xmin, ln));
+    D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / zx);
+    ahat = a;
+    flags = fl;
     return;
   }
   double Sd;
@@ -488,7 +531,7 @@ __device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const u
   const EmCoef E = em_coef(a);
   double suf[17];
   survival_head(E, ln, suf);
-  D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane);
+  D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / suf[0]);
   ahat = a;
   flags = fl;
 }
@@ -1192,7 +1235,7 @@ template <class Fill>
 __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
                            uint32_t* lc, const double* __restrict__ ln, uint32_t K, bool want_fp,
                            double& a, double& D, uint32_t& flags, uint64_t& fp, int64_t& xmax,
-                           bool& ok) {
+                           bool& ok, int64_t xmin = 1) {
   const int lane = lane_id();
   for (int k = lane; k < kHeavyHist; k += 64) W->hist[k] = 0u;
   if (lane == 0) {
@@ -1236,7 +1279,7 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
   }
   const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, want_fp);
   wave_sync_global();
-  finish_replicate_wave(lv, lc, s.len, s.S, n, fl, ln, lane, K, a, D, flags);
+  finish_replicate_wave(lv, lc, s.len, s.S, n, fl, ln, lane, K, a, D, flags, xmin);
   fp = s.fp;
   xmax = s.xmax;
 }
@@ -1249,6 +1292,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
   const int64_t n = c.n;
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   const uint64_t timax = table_int(c.tmax);
+  const int64_t off = c.xmin - 1;  // table index j is the value off + j
   auto fill = [&](auto sink, uint32_t& fl) {
     for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
       const uint32_t j = j0 + (uint32_t)lane;
@@ -1261,7 +1305,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
           const uint64_t m = half ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
           const int x = fast_draw(m, timax, T, guide);
           if (x) {
-            sink(x);
+            sink(off + (int64_t)x);
           } else {
             const uint32_t slot = atomicAdd(&W->qn, 1u);
             W->q[slot] = QEntry{m, m > timax ? (i | kTailBit) : i, 0u};
@@ -1271,7 +1315,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
       wave_sync();
       while (W->qn >= 64u) {
         const QEntry e = W->q[lane];
-        sink(resolve(e, rep, c, T, guide, fl));
+        sink(resolve_x(e, rep, c, T, guide, fl));
         wave_sync();
         queue_compact(W, 64, lane);
       }
@@ -1279,7 +1323,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
     for (int m = (int)W->qn; m > 0; m = (int)W->qn) {
       if (lane < m) {
         const QEntry e = W->q[lane];
-        sink(resolve(e, rep, c, T, guide, fl));
+        sink(resolve_x(e, rep, c, T, guide, fl));
       }
       wave_sync();
       queue_compact(W, m, lane);
@@ -1291,7 +1335,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
   int64_t xmax;
   bool ok;
   heavy_core(W, n, fill, gov, lv, lc, ln, c.K, out.fp != nullptr || out.xmax != nullptr, a, D,
-             flags, fp, xmax, ok);
+             flags, fp, xmax, ok, c.xmin);
   if (lane == 0) write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
   wave_sync_global();
 }
@@ -1359,6 +1403,67 @@ __global__ __launch_bounds__(64 * kHeavyWaves) void k_heavy(
 // dataset).  Same histogram/list/finish arithmetic as the simulated
 // replicates, so identical multisets give bit-identical results.
 // ---------------------------------------------------------------------------
+// The KS-minimising choice of a lower cutoff (the practice the paper cites
+// for fitting data): for each candidate xmin one wave fits the values >= xmin
+// of the same dataset (the law with cutoff xmin, eq. 2 and eq. 3 with the
+// Hurwitz zeta).  A candidate above every value gets D = +inf and status
+// kErrNoTail; any value below 1 sets kErrBadValue.
+__global__ __launch_bounds__(64) void k_fit_scan(const int64_t* __restrict__ x, int64_t n,
+                                                const int64_t* __restrict__ xmins, int n_cand,
+                                                const double* __restrict__ ln, int64_t* scratch,
+                                                int64_t scratch_stride, double* ahat_out,
+                                                double* D_out, int64_t* ntail_out,
+                                                uint32_t* flags_out, uint32_t* status_out) {
+  __shared__ HeavyWave W;
+  int64_t* gov = scratch + (int64_t)blockIdx.x * scratch_stride;
+  const int64_t half = scratch_stride / 2;
+  int64_t* lv = gov + half;
+  uint32_t* lc = reinterpret_cast<uint32_t*>(lv + half / 2);
+  const int lane = lane_id();
+  for (int cand = (int)blockIdx.x; cand < n_cand; cand += (int)gridDim.x) {
+    const int64_t xmin = xmins[cand];
+    uint32_t cnt = 0, bad = 0;
+    for (int64_t i = lane; i < n; i += 64) {
+      const int64_t v = x[i];
+      bad |= v < 1 ? 1u : 0u;
+      cnt += v >= xmin ? 1u : 0u;
+    }
+    cnt = wave_sum_u32(cnt);
+    bad = wave_or_u32(bad);
+    if (bad != 0u || cnt == 0u) {
+      if (lane == 0) {
+        ahat_out[cand] = 0.0;
+        D_out[cand] = __builtin_inf();
+        ntail_out[cand] = (int64_t)cnt;
+        flags_out[cand] = 0u;
+        status_out[cand] = bad != 0u ? kErrBadValue : kErrNoTail;
+      }
+      continue;
+    }
+    auto fill = [&](auto sink, uint32_t&) {
+      for (int64_t i = lane; i < n; i += 64) {
+        const int64_t v = x[i];
+        if (v >= xmin) sink(v);
+      }
+    };
+    double a = 0.0, D = 0.0;
+    uint32_t flags = 0;
+    uint64_t fp;
+    int64_t xmax;
+    bool ok;
+    heavy_core(&W, (int64_t)cnt, fill, gov, lv, lc, ln, 0u, false, a, D, flags, fp, xmax, ok,
+               xmin);
+    if (lane == 0) {
+      ahat_out[cand] = a;
+      D_out[cand] = D;
+      ntail_out[cand] = (int64_t)cnt;
+      flags_out[cand] = flags;
+      status_out[cand] = ok ? 0u : kErrBadValue;
+    }
+    wave_sync_global();
+  }
+}
+
 __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ xs,
                                            const int64_t* __restrict__ ns, int n_sets,
                                            const double* __restrict__ ln, int64_t* scratch,
@@ -1406,6 +1511,19 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
   const double a = cells[cell].alpha;
   double suf[17];
   survival_head(a, ln, suf);
+  const int64_t xmin = cells[cell].xmin;
+  if (xmin > 1) {  // T[k-1] = F(xmin + k - 1) = 1 - zeta(a, xmin + k)/zeta(a, xmin)
+    const EmCoef E = em_coef(a);
+    auto zq = [&](int64_t q) {  // zeta(a, q), q >= 2 (static indices into suf: no scratch)
+      double z = 0.0;
+#pragma unroll
+      for (int t = 1; t <= 16; ++t)
+        if (q - 1 == t) z = suf[t];
+      return q <= 17 ? z : survival_next(E, q - 1, ln);
+    };
+    tables[(size_t)cell * kH + (k - 1)] = 1.0 - zq(xmin + k) / zq(xmin);
+    return;
+  }
   double zk = suf[16];
 #pragma unroll
   for (int t = 1; t < 16; ++t)
@@ -1488,7 +1606,7 @@ __global__ __launch_bounds__(256) void k_guide(DevCell* __restrict__ cells,
     DevCell& c = cells[cell];
     c.tmax = T[kH - 1];
     c.beta = c.alpha - 1.0;
-    c.gm = tail_g(c.beta, kTailM);
+    c.gm = tail_g(c.beta, (double)(c.xmin + kH));
   }
 }
 
@@ -1761,7 +1879,10 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
     const uint64_t timax = table_int(c.tmax);
     uint32_t fl = 0;
     int64_t v = fast_draw(m, timax, T, guide);
-    if (v == 0) v = resolve(QEntry{m, m > timax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
+    if (v != 0)
+      v += c.xmin - 1;
+    else
+      v = resolve_x(QEntry{m, m > timax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
     x[t] = v;
     if (fl) atomicOr(&flags[rr], fl);
   }
@@ -1828,6 +1949,16 @@ hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int
                       double* D, uint32_t* flags, uint32_t* status, uint32_t K, hipStream_t s) {
   if (n_sets <= 0) return hipSuccess;
   k_fit<<<grid, 64, 0, s>>>(xs, ns, n_sets, ln, scratch, stride, ahat, D, flags, status, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_scan(int grid, const int64_t* x, int64_t n, const int64_t* xmins,
+                           int n_cand, const double* ln, int64_t* scratch, int64_t stride,
+                           double* ahat, double* D, int64_t* ntail, uint32_t* flags,
+                           uint32_t* status, hipStream_t s) {
+  if (n_cand <= 0 || grid <= 0) return hipSuccess;
+  k_fit_scan<<<grid, 64, 0, s>>>(x, n, xmins, n_cand, ln, scratch, stride, ahat, D, ntail,
+                                 flags, status);
   return hipGetLastError();
 }
 

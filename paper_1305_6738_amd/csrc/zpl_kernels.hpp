@@ -62,6 +62,7 @@ struct DevCell {
   uint32_t mode;    // Mode
   uint32_t K;       // 0: the pure law; else the truncated law on 1..K
   uint32_t pad;
+  int64_t xmin;     // lower cutoff of the pure law (1: none); values >= xmin
 };
 
 struct Unit {
@@ -81,5 +82,6 @@ struct Outputs {
 // Error bits written by kernels into the context's error word.
 constexpr uint32_t kErrEscOverflow = 1u;
 constexpr uint32_t kErrBadValue = 2u;
+constexpr uint32_t kErrNoTail = 4u;  // no value at or above the cutoff (xmin scan)
 
 }  // namespace zpl

@@ -144,8 +144,12 @@ ZPL_HD double hurwitz_tail(const EmCoef& E, double q, double lnq) {
   return qs * (fma(q, E.ism1, 0.5) + acc * iq);
 }
 
-// Reciprocal for the small Euler-Maclaurin correction terms (they change
-// zeta by less than 1e-17 relative, so the hardware reciprocal suffices).
+// Reciprocal for the s-derivative factors of the Euler-Maclaurin corrections
+// at q = 17.  The hardware reciprocal is accurate to about 2^-24 (measured on
+// gfx950); at q = 17 that moves alpha_hat by at most about 3e-13 relative
+// (the error injected into a host build), so it suffices there.  The law with
+// a lower cutoff uses recip instead: with a large xmin the variance of ln X
+// is small and eq. (2) amplifies errors in zeta'/zeta.
 ZPL_HD double rcp_corr(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   return __builtin_amdgcn_rcp(x);
@@ -275,6 +279,103 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
   return a;
 }
 
+// ln of an integer value: from the table for v <= kH + 1, else computed.
+ZPL_HD double ln_value(int64_t v, const double* __restrict__ ln) {
+  return v <= (int64_t)(kH + 1) ? ln[v] : log((double)v);
+}
+
+// ---------------------------------------------------------------------------
+// The law with a lower cutoff xmin (p(k) = k^-a / zeta(a, xmin), k >= xmin;
+// the practice the paper cites for fitting, xmin = 1 being its own case).
+// zeta(s, xmin) and its first two s-derivatives: direct terms k = xmin..16
+// (none when xmin >= 17), largest k first, after the Euler-Maclaurin tail at
+// q = max(xmin, 17) and its derivatives, as zeta3 does for xmin = 1.
+// ---------------------------------------------------------------------------
+ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
+  const double q = xmin < 17 ? 17.0 : (double)xmin;
+  const double L = xmin < 17 ? ln[17] : ln_value(xmin, ln);
+  const double iq = 1.0 / q, iq2 = iq * iq;
+  const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
+                       1.0 / 30240.0,      -1.0 / 1209600.0,
+                       1.0 / 47900160.0,   -691.0 / 1307674368000.0,
+                       1.0 / 74724249600.0, -3617.0 / 10670622842880000.0};
+  // full-precision reciprocals: with a large cutoff the variance of ln X is
+  // small and eq. (2) amplifies any error in zeta'/zeta
+  const double is = recip(s);
+  double P = s, sg1 = is, sg2 = is * is, E = iq;
+  double Q0 = 0.0, Q1 = 0.0, Q2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double ce = c[i] * E;
+    Q0 = fma(ce, P, Q0);
+    Q1 = fma(ce, P * sg1, Q1);
+    Q2 = fma(ce, P * fma(sg1, sg1, -sg2), Q2);
+    const double u = s + (double)(2 * i + 1), v = s + (double)(2 * i + 2);
+    const double iu = recip(u), iv = recip(v);
+    P *= u * v;
+    sg1 += iu + iv;
+    sg2 += iu * iu + iv * iv;
+    E *= iq2;
+  }
+  const double sm1 = s - 1.0, ism1 = 1.0 / sm1;
+  Q0 += 0.5;
+  Q0 += q * ism1;
+  Q1 += -q * ism1 * ism1;
+  Q2 += 2.0 * q * ism1 * ism1 * ism1;
+  const double qs = pow_neg(s, L);
+  double z0 = qs * Q0;
+  double z1 = qs * fma(-L, Q0, Q1);
+  double z2 = qs * fma(L * L, Q0, fma(-2.0 * L, Q1, Q2));
+  for (int64_t k = 16; k >= xmin; --k) {
+    const double lk = ln[k];
+    const double t = pow_neg(s, lk);
+    z0 += t;
+    z1 = fma(-lk, t, z1);
+    z2 = fma(lk * lk, t, z2);
+  }
+  return Z3{z0, z1, z2};
+}
+
+// MLE of eq. (2) with the Hurwitz zeta: mu(a) = -zeta'(a,xmin)/zeta(a,xmin)
+// = E_a[ln X] decreases from +inf (a -> 1) to ln xmin (a -> inf).  Newton on
+// mu(a) - m in the bracket [1 + 2^-20, 64] with a bisection safeguard, from
+// the continuous-Pareto guess a = 1 + 1/(m - ln(xmin - 1/2)); stops after a
+// step of at most 2^-40 a.  A root above 64 (m <= mu(64), a sample close to
+// a large cutoff) gives 64 with kFlagNoConv.  xmin >= 2.
+ZPL_HD double mle_alpha_hz(double m, int64_t xmin, const double* __restrict__ ln,
+                           uint32_t* flags) {
+  double lo = 1.0 + 0x1p-20, hi = 64.0;
+  {
+    const Z3 z = hurwitz3(hi, xmin, ln);
+    if (!(m > -z.z1 / z.z0)) {
+      *flags |= kFlagNoConv;
+      return hi;
+    }
+  }
+  double a = 1.0 + 1.0 / (m - log((double)xmin - 0.5));
+  if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const Z3 z = hurwitz3(a, xmin, ln);
+    const double r1 = z.z1 / z.z0;
+    const double g = -r1 - m;
+    if (g == 0.0) return a;
+    if (g > 0.0)
+      lo = a;
+    else
+      hi = a;
+    const double gp = -fma(-r1, r1, z.z2 / z.z0);
+    double an = a - g / gp;
+    if (!(an >= lo && an <= hi)) {
+      an = 0.5 * (lo + hi);
+      *flags |= kFlagBisect;
+    }
+    if (fabs(an - a) <= 0x1p-40 * a) return an;
+    a = an;
+  }
+  *flags |= kFlagNoConv;
+  return a;
+}
+
 // ---------------------------------------------------------------------------
 // Truncated law on 1..K (Sect. 1 with a finite upper limit): Z_K(s) =
 // sum_{k<=K} k^-s and its first two s-derivatives by direct summation, index
@@ -356,11 +457,6 @@ ZPL_HD void survival_head(const EmCoef& E, const double* __restrict__ ln, double
 
 ZPL_HD void survival_head(double a, const double* __restrict__ ln, double suf[17]) {
   survival_head(em_coef(a), ln, suf);
-}
-
-// ln of an integer value: from the table for v <= kH + 1, else computed.
-ZPL_HD double ln_value(int64_t v, const double* __restrict__ ln) {
-  return v <= (int64_t)(kH + 1) ? ln[v] : log((double)v);
 }
 
 // zeta(a, v+1) for an integer 16 <= v < 2^63 (v + 1 may not fit in int64).
@@ -521,15 +617,17 @@ ZPL_HD int64_t dd_floor(DD y) {
 
 // Returns the accepted draw; ORs kFlagTailCapped into *flags if a proposal at
 // or above 2^63 was rejected.
-ZPL_HD int64_t tail_draw(double beta, double gm, uint32_t k0, uint32_t k1,
-                         uint32_t i, uint32_t rep, uint32_t stream, uint32_t* flags) {
+// Rejection tail on k >= m0 (m0 an integer below 2^53): kTailM for the pure
+// law, xmin + kH for the law with a lower cutoff; gm = tail_g(beta, m0).
+ZPL_HD int64_t tail_draw_from(double m0, double beta, double gm, uint32_t k0, uint32_t k1,
+                              uint32_t i, uint32_t rep, uint32_t stream, uint32_t* flags) {
   const double two63 = 0x1p63;
   for (uint32_t attempt = 0; attempt < 0x7fffffffu; ++attempt) {
     const Words4 w = philox4x32_10(i, rep, stream, kTailDomain | attempt, k0, k1);
     const double V = u53(w.w0, w.w1);
     const double W = u53(w.w2, w.w3);
     const double z = -log(V) / beta;
-    const double y = kTailM * exp(z);
+    const double y = m0 * exp(z);
     int64_t X;
     if (y >= two63 * (1.0 + 0x1p-40)) {
       *flags |= kFlagTailCapped;
@@ -542,7 +640,7 @@ ZPL_HD int64_t tail_draw(double beta, double gm, uint32_t k0, uint32_t k1,
       X = (int64_t)fy;
     } else {
       const DD zd = dd_div_d(dd_log(V), -beta);
-      const DD Y = dd_mul_d(dd_exp(zd), kTailM);
+      const DD Y = dd_mul_d(dd_exp(zd), m0);
       if (Y.hi > two63 || (Y.hi == two63 && Y.lo >= 0.0)) {
         *flags |= kFlagTailCapped;
         continue;
@@ -551,7 +649,12 @@ ZPL_HD int64_t tail_draw(double beta, double gm, uint32_t k0, uint32_t k1,
     }
     if (W * gm <= tail_g(beta, (double)X)) return X;
   }
-  return (int64_t)kTailM;
+  return (int64_t)m0;
+}
+
+ZPL_HD int64_t tail_draw(double beta, double gm, uint32_t k0, uint32_t k1,
+                         uint32_t i, uint32_t rep, uint32_t stream, uint32_t* flags) {
+  return tail_draw_from(kTailM, beta, gm, k0, k1, i, rep, stream, flags);
 }
 
 }  // namespace zpl

@@ -34,7 +34,8 @@ class ZplError(RuntimeError):
 
 class Cell(C.Structure):
     _fields_ = [("alpha", C.c_double), ("n", C.c_int64), ("replicates", C.c_int64),
-                ("seed", C.c_uint64), ("stream", C.c_uint32), ("kmax", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("kmax", C.c_uint32),
+                ("xmin", C.c_int64)]
 
 
 class ServeOpts(C.Structure):
@@ -98,9 +99,9 @@ def lib() -> C.CDLL:
         L.zpl_serve_poll.restype = i32
         L.zpl_serve_stop.argtypes = [vp]
         L.zpl_serve_stop.restype = i32
-        L.zpl_sample_draws.argtypes = [vp, d, u32, i64, u64, u32, i64, i64, vp, vp, vp]
+        L.zpl_sample_draws.argtypes = [vp, d, u32, i64, i64, u64, u32, i64, i64, vp, vp, vp]
         L.zpl_sample_draws.restype = i32
-        L.zpl_cdf_table.argtypes = [vp, d, u32, vp, vp]
+        L.zpl_cdf_table.argtypes = [vp, d, u32, i64, vp, vp]
         L.zpl_cdf_table.restype = i32
         L.zpl_autotune.argtypes = [vp, P(d), i32, P(i64), i32, P(TuneEntry), vp]
         L.zpl_autotune.restype = i32
@@ -111,6 +112,11 @@ def lib() -> C.CDLL:
         L.zpl_critical_table.argtypes = [vp, P(d), i32, P(i64), i32, u32, i32, u64, i64, P(u32),
                                          P(u32), i32, P(d), P(d), vp]
         L.zpl_critical_table.restype = i32
+        L.zpl_fit_scan.argtypes = [vp, vp, i64, i32, P(i64), i32, P(d), P(d), P(i64), P(u32),
+                                   P(i32), vp]
+        L.zpl_fit_scan.restype = i32
+        L.zpl_fit_xmin.argtypes = [vp, vp, i64, i32, i64, P(d), P(d), P(i64), P(u32), vp]
+        L.zpl_fit_xmin.restype = i32
         _lib = L
     return _lib
 
@@ -120,7 +126,8 @@ def exported_symbols() -> list:
             "zpl_set_timing", "zpl_get_timing", "zpl_fit", "zpl_bootstrap_pvalue",
             "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
             "zpl_sample_draws", "zpl_cdf_table", "zpl_autotune", "zpl_set_tuning",
-            "zpl_plan_forms", "zpl_fit_truncated", "zpl_critical_table"]
+            "zpl_plan_forms", "zpl_fit_truncated", "zpl_critical_table", "zpl_fit_scan",
+            "zpl_fit_xmin"]
 
 
 FORM_NAMES = {FORM_LANE: "lane", FORM_WAVE: "wave", FORM_HEAVY: "heavy"}
@@ -197,6 +204,7 @@ class CellSpec:
     seed: int = 0
     stream: int = 0
     kmax: int = 0  # 0: pure law; K in 2..4096: truncated law on 1..K
+    xmin: int = 0  # 0 or 1: none; else the pure law on k >= xmin
 
 
 def _cells(cells: Sequence) -> C.Array:
@@ -207,7 +215,7 @@ def _cells(cells: Sequence) -> C.Array:
         elif not isinstance(c, CellSpec):
             c = CellSpec(*c)
         arr[i] = Cell(float(c.alpha), int(c.n), int(c.replicates), int(c.seed), int(c.stream),
-                      int(c.kmax))
+                      int(c.kmax), int(c.xmin))
     return arr
 
 
@@ -303,10 +311,22 @@ class Context:
         return {"tables": ms[0], "simulate": ms[1], "heavy": ms[2], "select": ms[3]}
 
     # -- zpl_fit ------------------------------------------------------------
-    def fit(self, x, kmax: int = 0, stream=None) -> dict:
-        """zpl_fit (kmax = 0) or zpl_fit_truncated (kmax = K)."""
+    def fit(self, x, kmax: int = 0, xmin: int = 1, stream=None) -> dict:
+        """zpl_fit (kmax = 0), zpl_fit_truncated (kmax = K) or zpl_fit_xmin
+        (xmin > 1: the values >= xmin under the law with that cutoff)."""
         ptr, n, on_dev, keep = _xarg(x)
         a, D, f = C.c_double(), C.c_double(), C.c_uint32()
+        if xmin > 1:
+            if kmax:
+                raise ValueError("xmin > 1 needs the pure law (kmax = 0)")
+            m = C.c_int64()
+            st = lib().zpl_fit_xmin(self._h, ptr, n, on_dev, int(xmin), C.byref(a), C.byref(D),
+                                    C.byref(m), C.byref(f), _stream(stream))
+            del keep
+            if st not in (OK, ENOCONV):
+                _check(st)
+            return {"alpha_hat": a.value, "D": D.value, "flags": f.value, "status": st,
+                    "n_tail": m.value}
         if kmax:
             st = lib().zpl_fit_truncated(self._h, ptr, n, on_dev, int(kmax), C.byref(a),
                                          C.byref(D), C.byref(f), _stream(stream))
@@ -355,14 +375,34 @@ class Context:
 
     # -- zpl_sample_draws / zpl_cdf_table -----------------------------------
     def sample_draws(self, alpha: float, n: int, seed: int, stream_id: int, rep_lo: int,
-                     count: int, x_out, flags_out, kmax: int = 0, stream=None):
-        _check(lib().zpl_sample_draws(self._h, float(alpha), int(kmax), int(n), int(seed),
-                                      int(stream_id), int(rep_lo), int(count), _dptr(x_out),
-                                      _dptr(flags_out), _stream(stream)))
+                     count: int, x_out, flags_out, kmax: int = 0, xmin: int = 1, stream=None):
+        _check(lib().zpl_sample_draws(self._h, float(alpha), int(kmax), int(xmin), int(n),
+                                      int(seed), int(stream_id), int(rep_lo), int(count),
+                                      _dptr(x_out), _dptr(flags_out), _stream(stream)))
 
-    def cdf_table(self, alpha: float, T_out, kmax: int = 0, stream=None):
-        _check(lib().zpl_cdf_table(self._h, float(alpha), int(kmax), _dptr(T_out),
+    def cdf_table(self, alpha: float, T_out, kmax: int = 0, xmin: int = 1, stream=None):
+        _check(lib().zpl_cdf_table(self._h, float(alpha), int(kmax), int(xmin), _dptr(T_out),
                                    _stream(stream)))
+
+    # -- zpl_fit_scan ---------------------------------------------------------
+    def fit_scan(self, x, xmins: Sequence[int], stream=None) -> dict:
+        """The KS-minimising lower cutoff among the candidates (zpl_fit_scan):
+        per-candidate alpha_hat, D, n_tail, flags and the index `best`."""
+        ptr, n, on_dev, keep = _xarg(x)
+        c = np.ascontiguousarray(np.asarray(xmins), dtype=np.int64)
+        k = int(c.size)
+        A, D = np.zeros(k), np.zeros(k)
+        M = np.zeros(k, dtype=np.int64)
+        F = np.zeros(k, dtype=np.uint32)
+        best = C.c_int32()
+        P = C.POINTER
+        _check(lib().zpl_fit_scan(
+            self._h, ptr, n, on_dev, c.ctypes.data_as(P(C.c_int64)), k,
+            A.ctypes.data_as(P(C.c_double)), D.ctypes.data_as(P(C.c_double)),
+            M.ctypes.data_as(P(C.c_int64)), F.ctypes.data_as(P(C.c_uint32)), C.byref(best),
+            _stream(stream)))
+        del keep
+        return {"best": best.value, "alpha_hat": A, "D": D, "n_tail": M, "flags": F}
 
 
 def _xarg(x):

@@ -50,6 +50,19 @@ double hm_S(const int64_t* x, int64_t n) {
   for (int64_t i = 0; i < n; ++i) u128_add(S, ln_fixed(x[i], g_ln.data()), 0);
   return u128_to_S(S);
 }
+void hm_hurwitz3(double s, int64_t xmin, double* out) {
+  Z3 z = hurwitz3(s, xmin, g_ln.data());
+  out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;
+}
+double hm_mle_hz(double m, int64_t xmin, uint32_t* flags) {
+  return mle_alpha_hz(m, xmin, g_ln.data(), flags);
+}
+int64_t hm_tail_from(double alpha, int64_t xmin, uint64_t seed, uint32_t stream, uint32_t rep,
+                     uint32_t i, uint32_t* flags) {
+  const double beta = alpha - 1.0, m0 = (double)(xmin + kH);
+  return tail_draw_from(m0, beta, tail_g(beta, m0), (uint32_t)seed, (uint32_t)(seed >> 32), i,
+                        rep, stream, flags);
+}
 void hm_dd_exp_log(double v, double* out) {
   DD l = dd_log(v);
   DD e = dd_exp(DD{v, 0.0});

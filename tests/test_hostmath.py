@@ -40,6 +40,12 @@ def hm(tmp_path_factory):
     L.hm_S.argtypes = [P(C.c_int64), C.c_int64]
     L.hm_S.restype = C.c_double
     L.hm_dd_exp_log.argtypes = [C.c_double, P(C.c_double)]
+    L.hm_hurwitz3.argtypes = [C.c_double, C.c_int64, P(C.c_double)]
+    L.hm_mle_hz.argtypes = [C.c_double, C.c_int64, P(C.c_uint32)]
+    L.hm_mle_hz.restype = C.c_double
+    L.hm_tail_from.argtypes = [C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_uint32,
+                               C.c_uint32, P(C.c_uint32)]
+    L.hm_tail_from.restype = C.c_int64
     return L
 
 
@@ -141,3 +147,55 @@ def test_exact_S_order_independent(hm):
     assert s1 == s2
     want = math.fsum(np.log(x.astype(np.float64)))
     assert abs(s1 - want) <= 4e-16 * want
+
+
+@pytest.mark.parametrize("s,q", [(1.3, 2), (2.5, 7), (3.0, 17), (2.2, 18), (4.0, 300),
+                                 (50.0, 300), (1.7, 123456)])
+def test_hurwitz3_at_a_cutoff(hm, s, q):
+    """zeta(s, q) and its s-derivatives for the law with a lower cutoff,
+    against partial sums at 40 digits (mpmath's own Hurwitz zeta is not
+    accurate enough at s = 50, q = 300) or mpmath where the sum is long."""
+    out = np.zeros(3)
+    hm.hm_hurwitz3(s, q, _p(out, C.c_double))
+    with mp.workdps(40):
+        if s >= 10.0:  # the sum converges within a few thousand terms
+            K = q + 5000
+            terms = [(mp.mpf(k) ** -s, mp.log(k)) for k in range(q, K)]
+            want = [mp.fsum(t for t, _ in terms), -mp.fsum(t * l for t, l in terms),
+                    mp.fsum(t * l * l for t, l in terms)]
+        else:
+            want = [mp.zeta(s, q), mp.zeta(s, q, 1), mp.zeta(s, q, 2)]
+    # q^-s = exp(-s ln q) inherits s times the rounding of ln q (about
+    # s ln(q) 1.1e-16 relative); that factor is common to all three and
+    # cancels in zeta'/zeta
+    tol = 3e-15 + 1.2e-16 * s * math.log(q)
+    for i in range(3):
+        assert abs(out[i] - float(want[i])) <= tol * abs(float(want[i])), (s, q, i)
+
+
+@pytest.mark.parametrize("xmin", [2, 9, 17, 60, 300, 5000])
+def test_mle_at_a_cutoff_matches_oracle(hm, orc, xmin):
+    rng = np.random.default_rng(xmin)
+    for _ in range(6):
+        x, _ = orc.hz_sample(float(rng.uniform(1.5, 4.0)), xmin, int(rng.integers(5, 400)), 3,
+                             1, int(rng.integers(0, 1000)))
+        r = orc.hz_fit(x, xmin)
+        if r["flags"] & orc.FLAG_NOCONV:
+            continue
+        f = C.c_uint32(0)
+        a = hm.hm_mle_hz(r["S"] / r["n_tail"], xmin, C.byref(f))
+        assert abs(a - r["alpha_hat"]) <= 1e-12 * r["alpha_hat"], (xmin, x)
+
+
+def test_tail_from_a_cutoff_matches_oracle(hm, orc):
+    for a, xmin in [(1.6, 500), (2.5, 3), (1.2, 10 ** 6)]:
+        T = orc.hz_cdf_table(a, xmin)
+        for i in range(400):
+            w = orc.philox([i >> 1, 0, 7, 0], [11, 0])
+            U = orc.u53(w[2], w[3]) if i & 1 else orc.u53(w[0], w[1])
+            if U <= T[-1]:
+                continue
+            f = C.c_uint32(0)
+            got = hm.hm_tail_from(a, xmin, 11, 7, 0, i, C.byref(f))
+            x, _ = orc.hz_sample(a, xmin, i + 1, 11, 7, 0)
+            assert got == x[i], (a, xmin, i)
