@@ -226,6 +226,47 @@ def paper_tables(ctx, torch):
     return out
 
 
+def cutoff_runs(ctx, torch):
+    """The law with a lower cutoff xmin: one timed batched call over six
+    cells (alpha in {2, 2.5, 3} x xmin in {10, 100}, n = 1000, R = 100,000;
+    heavy form), and one timed KS-minimising scan of 1,000 candidate cutoffs
+    over a device dataset of 100,000 values (30,000 uniform on 1..59 below
+    70,000 draws of the law with cutoff 60 and alpha = 2.5, drawn by the
+    library's own sampler)."""
+    import numpy as np
+    out = {}
+    cells = [(a, 1000, 100000, 42, i, 0, xm)
+             for i, (a, xm) in enumerate([(a, xm) for a in (2.0, 2.5, 3.0) for xm in (10, 100)])]
+    R = sum(c[2] for c in cells)
+    ctx.simulate_cells(cells[:1], quantiles=QS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.simulate_cells(cells, quantiles=QS)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out["cells"] = {"what": "alpha in {2, 2.5, 3} x xmin in {10, 100}, n = 1000, R = 100,000",
+                    "replicates": R, "ms": ms, "replicates_per_s": R / (ms / 1e3)}
+    progress("cutoff cells: %.1f ms" % ms)
+    rng = np.random.default_rng(7)
+    body = torch.from_numpy(rng.integers(1, 60, size=30000).astype(np.int64)).cuda()
+    tail = torch.zeros(70000, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.sample_draws(2.5, 70000, 7, 0, 0, 1, tail, fl, xmin=60)
+    x = torch.cat([body, tail])
+    cand = np.arange(1, 1001, dtype=np.int64)
+    ctx.fit_scan(x, cand[:8])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.fit_scan(x, cand)
+    ms = (time.perf_counter() - t0) * 1e3
+    out["scan"] = {"what": "1,000 candidate cutoffs over 100,000 values (device input)",
+                   "ms": ms, "candidates_per_s": cand.size / (ms / 1e3),
+                   "chosen_xmin": int(cand[r["best"]]),
+                   "alpha_hat": float(r["alpha_hat"][r["best"]])}
+    progress("xmin scan: %.1f ms, chose %d" % (ms, cand[r["best"]]))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +406,7 @@ def main(argv=None):
         out["configs"] = config_runs(ctx, stream, torch)
         if not args.no_paper_tables:
             out["paper_tables"] = paper_tables(ctx, torch)
+        out["cutoff"] = cutoff_runs(ctx, torch)
         out["fit_latency"] = fit_latency(ctx)
         progress("fit latency done")
         if args.serve_seconds > 0:
