@@ -73,6 +73,10 @@ const HostLn& host_ln() {
 // exponents are never below about 1.023: mean ln x < ln 2^63.)
 constexpr double kMinAlpha = 1.01;
 constexpr int64_t kMaxXmin = (int64_t)1 << 40;
+// Datasets at least this long are fitted by a whole workgroup.
+constexpr int64_t kFitBlockMin = 2048;
+// Host datasets up to this many bytes go through pinned staging.
+constexpr size_t kPinStageMax = (size_t)64 << 20;
 
 // P(X > h) under exponent a: the pure law (K = 0) or the truncated law on
 // 1..K (finite sums).
@@ -118,6 +122,8 @@ struct zpl_ctx {
   // pinned host staging
   void* pin = nullptr;
   size_t pin_bytes = 0;
+  void* pin_x = nullptr;  // host datasets on their way to fit_x
+  size_t pin_x_bytes = 0;
   // graph cache (one entry)
   bool graph_valid = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -719,9 +725,15 @@ zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, d
   HIP_TRY(hipMemcpyAsync(c->fit_ns.p, &pin[1], sizeof(int64_t), hipMemcpyHostToDevice, s));
   double* o = (double*)c->fit_out.p;
   uint32_t* of = (uint32_t*)(o + 2);
-  HIP_TRY(launch_fit(1, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, 1,
-                     c->ln, (int64_t*)c->heavy.p, stride, o, o + 1, of,
-                     (uint32_t*)c->fit_st.p, K, s));
+  // a large dataset is read, histogrammed and sorted by a whole workgroup
+  // (the same list and finish, so the same bits as the one-wave kernel)
+  if (n >= kFitBlockMin)
+    HIP_TRY(launch_fit_block(xd, n, c->ln, (int64_t*)c->heavy.p, stride, o, o + 1, of,
+                             (uint32_t*)c->fit_st.p, K, s));
+  else
+    HIP_TRY(launch_fit(1, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, 1,
+                       c->ln, (int64_t*)c->heavy.p, stride, o, o + 1, of,
+                       (uint32_t*)c->fit_st.p, K, s));
   char* hp = (char*)c->pin + 16;
   HIP_TRY(hipMemcpyAsync(hp, o, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(hp + 16, of, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -740,8 +752,25 @@ zpl_status stage_x(zpl_ctx* c, const int64_t* x, int64_t n, int32_t on_dev, hipS
     *xd = x;
     return ZPL_OK;
   }
-  ZPL_TRY(ensure(c, c->fit_x, sizeof(int64_t) * (size_t)n));
-  HIP_TRY(hipMemcpyAsync(c->fit_x.p, x, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, s));
+  const size_t bytes = sizeof(int64_t) * (size_t)n;
+  ZPL_TRY(ensure(c, c->fit_x, bytes));
+  if (bytes <= kPinStageMax) {
+    // a pageable source is copied by the runtime in small staged pieces;
+    // one host copy into pinned memory and one DMA are several times faster
+    if (c->pin_x_bytes < bytes) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (c->pin_x) HIP_TRY(hipHostFree(c->pin_x));
+      c->pin_x = nullptr;
+      c->pin_x_bytes = 0;
+      HIP_TRY(hipHostMalloc(&c->pin_x, bytes, hipHostMallocDefault));
+      c->pin_x_bytes = bytes;
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // the previous staged copy has finished
+    std::memcpy(c->pin_x, x, bytes);
+    HIP_TRY(hipMemcpyAsync(c->fit_x.p, c->pin_x, bytes, hipMemcpyHostToDevice, s));
+  } else {
+    HIP_TRY(hipMemcpyAsync(c->fit_x.p, x, bytes, hipMemcpyHostToDevice, s));
+  }
   *xd = (const int64_t*)c->fit_x.p;
   return ZPL_OK;
 }
@@ -1029,6 +1058,7 @@ void zpl_destroy(zpl_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->pin) (void)hipHostFree(c->pin);
+  if (c->pin_x) (void)hipHostFree(c->pin_x);
   delete c;
 }
 

@@ -1403,6 +1403,104 @@ __global__ __launch_bounds__(64 * kHeavyWaves) void k_heavy(
 // dataset).  Same histogram/list/finish arithmetic as the simulated
 // replicates, so identical multisets give bit-identical results.
 // ---------------------------------------------------------------------------
+// Bitonic sort of buf[0..P) (P a power of two) by the nthreads threads of
+// one workgroup; buf is LDS or global memory (a workgroup shares its CU's
+// caches, so the barrier orders the passes either way).
+__device__ __forceinline__ void block_bitonic(int64_t* buf, int P, int tid, int nthreads) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += nthreads) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int64_t a = buf[i], b = buf[ixj];
+          const bool asc = (i & k) == 0;
+          if ((a > b) == asc) {
+            buf[i] = b;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Fit of one large dataset (eq. 2 and eq. 3) by a whole workgroup: all
+// kFitWaves waves fill the LDS histogram (values 1..kHeavyHist) and the
+// global overflow list and sort the overflow (in LDS when it fits); wave 0
+// then builds the (value, count) list and finishes as k_fit does, so the
+// result has k_fit's bits.
+constexpr int kFitWaves = 8;
+constexpr int kFitSortLds = 4096;
+__global__ __launch_bounds__(64 * kFitWaves) void k_fit_block(
+    const int64_t* __restrict__ x, int64_t n, const double* __restrict__ ln, int64_t* scratch,
+    int64_t scratch_stride, double* ahat_out, double* D_out, uint32_t* flags_out,
+    uint32_t* status_out, uint32_t K) {
+  __shared__ HeavyWave W;
+  __shared__ int64_t sbuf[kFitSortLds];
+  __shared__ uint32_t sbad;
+  const int tid = (int)threadIdx.x;
+  const int nt = (int)blockDim.x;
+  const int lane = tid & 63;
+  int64_t* gov = scratch;
+  const int64_t half = scratch_stride / 2;
+  int64_t* lv = gov + half;
+  uint32_t* lc = reinterpret_cast<uint32_t*>(lv + half / 2);
+  for (int k = tid; k < kHeavyHist; k += nt) W.hist[k] = 0u;
+  if (tid == 0) {
+    W.ovc = 0u;
+    sbad = 0u;
+  }
+  __syncthreads();
+  const int64_t xhi = K ? (int64_t)K : INT64_MAX;
+  uint32_t bad = 0u;
+  for (int64_t i = tid; i < n; i += nt) {
+    const int64_t v = x[i];
+    if (v < 1 || v > xhi) {
+      bad = 1u;
+    } else if (v <= kHeavyHist) {
+      atomicAdd(&W.hist[v - 1], 1u);
+    } else {
+      const uint32_t idx = atomicAdd(&W.ovc, 1u);
+      gov[idx] = v;
+    }
+  }
+  if (bad) atomicOr(&sbad, 1u);
+  __syncthreads();
+  const bool ok = sbad == 0u;
+  const int oc = (int)W.ovc;
+  if (ok && oc > 1) {
+    const int P = next_pow2(oc);
+    if (P <= kFitSortLds) {
+      for (int k = tid; k < P; k += nt) sbuf[k] = k < oc ? gov[k] : INT64_MAX;
+      __syncthreads();
+      block_bitonic(sbuf, P, tid, nt);
+      for (int k = tid; k < oc; k += nt) gov[k] = sbuf[k];
+    } else {
+      for (int k = oc + tid; k < P; k += nt) gov[k] = INT64_MAX;
+      __syncthreads();
+      block_bitonic(gov, P, tid, nt);
+    }
+    __syncthreads();
+  }
+  if (tid >= 64) return;
+  if (!ok) {
+    if (lane == 0) status_out[0] = kErrBadValue;
+    return;
+  }
+  const Summary sm = build_list(W.hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, false);
+  wave_sync_global();
+  double a = 0.0, D = 0.0;
+  uint32_t flags = 0;
+  finish_replicate_wave(lv, lc, sm.len, sm.S, n, 0u, ln, lane, K, a, D, flags);
+  if (lane == 0) {
+    ahat_out[0] = a;
+    D_out[0] = D;
+    flags_out[0] = flags;
+    status_out[0] = 0u;
+  }
+}
+
 // The KS-minimising choice of a lower cutoff (the practice the paper cites
 // for fitting data): for each candidate xmin one wave fits the values >= xmin
 // of the same dataset (the law with cutoff xmin, eq. 2 and eq. 3 with the
@@ -1949,6 +2047,13 @@ hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int
                       double* D, uint32_t* flags, uint32_t* status, uint32_t K, hipStream_t s) {
   if (n_sets <= 0) return hipSuccess;
   k_fit<<<grid, 64, 0, s>>>(xs, ns, n_sets, ln, scratch, stride, ahat, D, flags, status, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_block(const int64_t* x, int64_t n, const double* ln, int64_t* scratch,
+                            int64_t stride, double* ahat, double* D, uint32_t* flags,
+                            uint32_t* status, uint32_t K, hipStream_t s) {
+  k_fit_block<<<1, 64 * kFitWaves, 0, s>>>(x, n, ln, scratch, stride, ahat, D, flags, status, K);
   return hipGetLastError();
 }
 

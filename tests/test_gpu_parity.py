@@ -216,6 +216,20 @@ def test_fit_equals_simulated_replicate_bits(ctx, orc):
         assert f["alpha_hat"] == g["alpha_hat"][r] and f["D"] == g["D"][r]
 
 
+def test_large_fit_equals_simulated_replicate_bits(ctx, orc):
+    """Datasets of 2,048 values and more are fitted by a whole workgroup
+    (overflow sorted in LDS up to 4,096 values, in global memory above);
+    the result still has the simulation's bits."""
+    for cell in [(1.5, 20000, 3, 9, 7), (1.3, 100000, 2, 9, 8), (2.5, 2048, 2, 9, 9)]:
+        say("large fit", cell)
+        g = run_cells(ctx, [cell])
+        for r in range(cell[2]):
+            x, _ = orc.sample(cell[0], cell[1], cell[3], cell[4], r)
+            for xin in (x, torch.from_numpy(x).cuda()):
+                f = ctx.fit(xin)
+                assert f["alpha_hat"] == g["alpha_hat"][r] and f["D"] == g["D"][r], (cell, r)
+
+
 def test_bootstrap_matches_oracle(ctx, orc):
     rng = np.random.default_rng(9)
     for x in [rng.zipf(2.5, 300).astype(np.int64), np.ones(12, np.int64),
