@@ -168,6 +168,17 @@ zpl_status ensure(zpl_ctx* c, DevBuf& b, size_t bytes) {
   return ZPL_OK;
 }
 
+// Size for a buffer on a latency path (dataset staging, fit scratch): the
+// next power of two, at least 1 MiB, so that datasets of growing size do not
+// reallocate (a reallocation synchronises the device) on most calls; sizes
+// above 64 MiB are taken as they are.
+size_t grow_size(size_t bytes) {
+  if (bytes > ((size_t)64 << 20)) return bytes;
+  size_t v = (size_t)1 << 20;
+  while (v < bytes) v <<= 1;
+  return v;
+}
+
 zpl_status ensure_pinned(zpl_ctx* c, size_t bytes) {
   if (c->pin_bytes >= bytes) return ZPL_OK;
   HIP_TRY(hipDeviceSynchronize());  // async copies may still read the old area
@@ -715,7 +726,7 @@ zpl_status fit_device(zpl_ctx* c, const int64_t* xd, int64_t n, hipStream_t s, d
   ZPL_TRY(ensure(c, c->fit_ns, sizeof(int64_t)));
   ZPL_TRY(ensure(c, c->fit_out, sizeof(double) * 2 + sizeof(uint32_t) * 2));
   ZPL_TRY(ensure(c, c->fit_st, sizeof(uint32_t) * 2));
-  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)stride));
+  ZPL_TRY(ensure(c, c->heavy, grow_size(sizeof(int64_t) * (size_t)stride)));
   ZPL_TRY(ensure_pinned(c, 64));
   HIP_TRY(hipStreamSynchronize(s));
   int64_t* pin = (int64_t*)c->pin;
@@ -753,17 +764,18 @@ zpl_status stage_x(zpl_ctx* c, const int64_t* x, int64_t n, int32_t on_dev, hipS
     return ZPL_OK;
   }
   const size_t bytes = sizeof(int64_t) * (size_t)n;
-  ZPL_TRY(ensure(c, c->fit_x, bytes));
+  ZPL_TRY(ensure(c, c->fit_x, bytes <= kPinStageMax ? grow_size(bytes) : bytes));
   if (bytes <= kPinStageMax) {
     // a pageable source is copied by the runtime in small staged pieces;
     // one host copy into pinned memory and one DMA are several times faster
     if (c->pin_x_bytes < bytes) {
+      const size_t want = grow_size(bytes);
       HIP_TRY(hipStreamSynchronize(s));
       if (c->pin_x) HIP_TRY(hipHostFree(c->pin_x));
       c->pin_x = nullptr;
       c->pin_x_bytes = 0;
-      HIP_TRY(hipHostMalloc(&c->pin_x, bytes, hipHostMallocDefault));
-      c->pin_x_bytes = bytes;
+      HIP_TRY(hipHostMalloc(&c->pin_x, want, hipHostMallocDefault));
+      c->pin_x_bytes = want;
     }
     HIP_TRY(hipStreamSynchronize(s));  // the previous staged copy has finished
     std::memcpy(c->pin_x, x, bytes);
