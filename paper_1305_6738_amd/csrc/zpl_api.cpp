@@ -318,31 +318,75 @@ bool form_eligible(uint32_t m, double alpha, int64_t n, uint32_t K = 0) {
   return true;
 }
 
-uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0) {
+// Time for one cell alone under form f (tuned cost v ns per replicate with
+// the device busy): its work units (kBlock replicates per workgroup for the
+// lane and wave forms, 8 for the heavy form, which fits two workgroups per
+// compute unit) run in rounds of as many units as the device holds at once,
+// and a unit takes v x (replicates the device holds at once).
+double cell_makespan(int f, double v, int64_t R, int n_cu) {
+  const double per = f == (int)kModeHeavy ? 8.0 : (double)kBlock;
+  const double conc = f == (int)kModeHeavy ? 2.0 * n_cu : (double)n_cu;
+  return std::ceil(std::ceil((double)R / per) / conc) * v * conc * per;
+}
+
+// With a tuning table: the eligible form of least cost per replicate, or,
+// when `horizon` (ns) is given and that form alone would take longer than
+// the horizon (a few thousand long replicates, as in a bootstrap, fill only
+// a few workgroups), the form that finishes the cell soonest.
+uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0, int64_t R = 0,
+                     int n_cu = 256, double horizon = -1.0, double* cost = nullptr) {
   if (t && !t->empty()) {
-    int best = -1;
-    double bc = 0.0;
+    int best = -1, fast = -1;
+    double bc = 0.0, bm = 0.0;
     for (int f = 0; f < 3; ++f) {
       if (!form_eligible((uint32_t)f, alpha, n, K)) continue;
       const double v = tuned_cost(*t, f, alpha, n);
-      if (v >= 0.0 && (best < 0 || v < bc)) {
+      if (!(v >= 0.0)) continue;
+      if (best < 0 || v < bc) {
         best = f;
         bc = v;
       }
+      const double m = cell_makespan(f, v, R, n_cu);
+      if (fast < 0 || m < bm) {
+        fast = f;
+        bm = m;
+      }
     }
-    if (best >= 0) return (uint32_t)best;
+    if (best >= 0) {
+      if (cost) *cost = bc * (double)R;
+      if (horizon >= 0.0 && R > 0 && cell_makespan(best, bc, R, n_cu) > horizon) return (uint32_t)fast;
+      return (uint32_t)best;
+    }
   }
+  if (cost) *cost = 0.0;
   if (n <= 65535 && (double)n * tail_prob(alpha, kHLB, K) <= 2.0) return kModeLane;
   if (form_eligible(kModeWave, alpha, n, K)) return kModeWave;
   return kModeHeavy;
 }
 
 zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
-                     const Tuning* tune = nullptr) {
+                     const Tuning* tune = nullptr, int n_cu = 256) {
   P = Plan();
   P.cells.resize(n_cells);
   P.cell_unit_begin.assign(n_cells, 0);
   P.cell_unit_end.assign(n_cells, 0);
+  // the batch's work with every cell in its cheapest form: a cell that alone
+  // would outlast it is given the form that finishes it soonest instead
+  double horizon = -1.0;
+  if (form == ZPL_FORM_AUTO && tune && !tune->empty()) {
+    horizon = 0.0;
+    for (int i = 0; i < n_cells; ++i) {
+      const zpl_cell& z = cells[i];
+      double c = 0.0;
+      const bool valid = z.kmax == 0 ? (z.alpha >= kMinAlpha && z.alpha <= 64.0)
+                                     : (z.kmax >= 2 && z.kmax <= (uint32_t)kH &&
+                                        z.alpha >= -64.0 && z.alpha <= 64.0);
+      // (invalid cells are rejected below; cutoff cells run in the heavy form)
+      if (valid && z.n >= 1 && z.replicates >= 1 && (z.xmin == 0 || z.xmin == 1))
+        (void)choose_form(z.alpha, z.n, tune, z.kmax, z.replicates, n_cu, -1.0, &c);
+      horizon += c;
+    }
+  }
   for (int i = 0; i < n_cells; ++i) {
     const zpl_cell& z = cells[i];
     if (z.kmax == 0) {
@@ -384,7 +428,7 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
         break;
       case ZPL_FORM_WAVE: m = kModeWave; break;
       case ZPL_FORM_HEAVY: m = kModeHeavy; break;
-      default: m = choose_form(z.alpha, z.n, tune, z.kmax);
+      default: m = choose_form(z.alpha, z.n, tune, z.kmax, z.replicates, n_cu, horizon);
     }
     // the lane and wave forms histogram values from 1; a cutoff law runs in
     // the heavy form, whose histogram and overflow list take any values
@@ -576,7 +620,7 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
     if (q_den[i] == 0 || q_num[i] >= q_den[i])
       return fail(ZPL_EINVAL, "quantile %d: need num < den (got %u/%u)", i, q_num[i], q_den[i]);
   Plan P;
-  ZPL_TRY(make_plan(cells, n_cells, o.form, P, &c->tune));
+  ZPL_TRY(make_plan(cells, n_cells, o.form, P, &c->tune, c->n_cu));
   if (o.launch == ZPL_LAUNCH_PLAIN) plain_unit_order(P);
   const bool need_sel = quantiles && n_q > 0;
   const bool need_dbuf = need_sel && out.D == nullptr;

@@ -13,6 +13,11 @@ from paper_1305_6738_amd import ZplError, load_tuning, plan_forms, save_tuning
 from inputs import table_slice
 
 
+# Tuned choices below are per-replicate comparisons: cells of many replicates,
+# for which the soonest-finishing form is the cheapest one per replicate.
+R = 10 ** 6
+
+
 def grid(alphas, ns, cost):
     return [{"alpha": a, "n": n, "ns_per_replicate": list(cost(a, n))} for a in alphas for n in ns]
 
@@ -33,7 +38,7 @@ def test_builtin_rule_heavy_for_large_overflow():
 
 
 def test_table_picks_cheapest_form():
-    cells = [(2.5, 100, 10, 1, 0), (3.0, 1000, 10, 1, 1)]
+    cells = [(2.5, 100, R, 1, 0), (3.0, 1000, R, 1, 1)]
     heavy = grid([2.0, 3.5], [10, 10000], lambda a, n: (9.0, 9.0, 1.0))
     wave = grid([2.0, 3.5], [10, 10000], lambda a, n: (9.0, 1.0, 5.0))
     lane = grid([2.0, 3.5], [10, 10000], lambda a, n: (1.0, 2.0, 5.0))
@@ -47,9 +52,9 @@ def test_table_respects_eligibility():
     # about 1,100 values above 48 (lane ineligible) and about 240 above 1024
     # (wave still eligible)
     t = grid([1.5, 3.5], [10, 100000], lambda a, n: (1.0, 2.0, 3.0))
-    assert plan_forms([(1.5, 10000, 10, 1, 0)], t) == ["wave"]
-    assert plan_forms([(1.2, 10000, 10, 1, 0)], t) == ["heavy"]
-    assert plan_forms([(3.0, 70000, 10, 1, 0)], t) == ["wave"]  # n > 65535
+    assert plan_forms([(1.5, 10000, R, 1, 0)], t) == ["wave"]
+    assert plan_forms([(1.2, 10000, R, 1, 0)], t) == ["heavy"]
+    assert plan_forms([(3.0, 70000, R, 1, 0)], t) == ["wave"]  # n > 65535
 
 
 def test_bilinear_interpolation_in_log_n():
@@ -60,23 +65,23 @@ def test_bilinear_interpolation_in_log_n():
     w = 39.0 / 99.0
     n_cross = math.exp(math.log(100) + w * (math.log(10000) - math.log(100)))
     below, above = int(n_cross * 0.95), int(n_cross * 1.05)
-    assert plan_forms([(3.2, below, 10, 1, 0)], t) == ["lane"]
-    assert plan_forms([(3.2, above, 10, 1, 0)], t) == ["wave"]
+    assert plan_forms([(3.2, below, R, 1, 0)], t) == ["lane"]
+    assert plan_forms([(3.2, above, R, 1, 0)], t) == ["wave"]
 
 
 def test_bilinear_interpolation_in_alpha():
     # wave cost 10 at alpha 2.5, 30 at 3.5; lane cost 20 throughout:
     # crossover at alpha = 3.0
     t = grid([2.5, 3.5], [10, 1000], lambda a, n: (20.0, 10.0 if a == 2.5 else 30.0, 1000.0))
-    assert plan_forms([(2.9, 500, 10, 1, 0)], t) == ["wave"]
-    assert plan_forms([(3.1, 500, 10, 1, 0)], t) == ["lane"]
+    assert plan_forms([(2.9, 500, R, 1, 0)], t) == ["wave"]
+    assert plan_forms([(3.1, 500, R, 1, 0)], t) == ["lane"]
 
 
 def test_clamped_outside_grid():
     t = grid([2.5, 3.0], [100, 1000], lambda a, n: (1.0, 2.0, 3.0) if a == 3.0 else (2.0, 1.0, 3.0))
     # alpha above the grid takes the last row (lane cheapest), below the first (wave)
-    assert plan_forms([(3.4, 300, 10, 1, 0)], t) == ["lane"]
-    assert plan_forms([(2.0, 300, 10, 1, 0)], t) == ["wave"]
+    assert plan_forms([(3.4, 300, R, 1, 0)], t) == ["lane"]
+    assert plan_forms([(2.0, 300, R, 1, 0)], t) == ["wave"]
 
 
 def test_unmeasured_corner_excludes_form():
@@ -84,8 +89,8 @@ def test_unmeasured_corner_excludes_form():
     def cost(a, n):
         return (-1.0 if (a == 3.5 and n == 1000) else 1.0, 2.0, 3.0)
     t = grid([2.5, 3.5], [100, 1000], cost)
-    assert plan_forms([(3.0, 300, 10, 1, 0)], t) == ["wave"]
-    assert plan_forms([(2.5, 100, 10, 1, 0)], t) == ["lane"]
+    assert plan_forms([(3.0, 300, R, 1, 0)], t) == ["wave"]
+    assert plan_forms([(2.5, 100, R, 1, 0)], t) == ["lane"]
 
 
 def test_all_unmeasured_falls_back_to_builtin():
@@ -108,7 +113,7 @@ def test_invalid_tables_rejected(bad):
     elif bad == "alpha_range":
         t = grid([0.5, 3.5], [100, 1000], lambda a, n: (1.0, 2.0, 3.0))
     with pytest.raises(ZplError) as e:
-        plan_forms([(3.0, 300, 10, 1, 0)], t)
+        plan_forms([(3.0, 300, R, 1, 0)], t)
     assert e.value.status == -1
 
 
@@ -133,3 +138,13 @@ def test_truncated_cells_plan_and_validate():
         with pytest.raises(ZplError) as e:
             plan_forms([bad])
         assert e.value.status == -1, bad
+
+
+def test_few_long_replicates_spread_over_the_device():
+    """A bootstrap-sized cell (2,500 replicates of 98,000 draws): the wave
+    form is cheaper per replicate (208 against 545 ns with the device busy)
+    but puts 2,500 replicates in 5 workgroups, one round of about 27 ms; the
+    heavy form's 313 units of 8 fit in one round of about 2.2 ms."""
+    t = grid([2.5, 3.0], [10000, 100000], lambda a, n: (-1.0, 208.0, 545.0))
+    assert plan_forms([(2.65, 98000, 2500, 1, 0)], t) == ["heavy"]
+    assert plan_forms([(2.65, 98000, 10 ** 6, 1, 0)], t) == ["wave"]
