@@ -60,10 +60,11 @@ def test_autotune_table_shape_and_eligibility(ctx):
     # the lane form is eligible at small n with light tails, not at (1.5, 1e4)
     by = {(e["alpha"], e["n"]): e["ns_per_replicate"] for e in t}
     assert by[(3.5, 10)][0] > 0 and by[(1.5, 10000)][0] == -1.0
-    # the planner picks the cheapest measured form at a grid point
+    # for a cell of many replicates the planner picks the cheapest measured
+    # form at a grid point
     for (a, n), c in by.items():
         best = min((v, f) for f, v in enumerate(c) if v > 0)[1]
-        assert plan_forms([(a, n, 10, 1, 0)], t) == [["lane", "wave", "heavy"][best]]
+        assert plan_forms([(a, n, 10 ** 6, 1, 0)], t) == [["lane", "wave", "heavy"][best]]
     ctx.set_tuning(None)
 
 
