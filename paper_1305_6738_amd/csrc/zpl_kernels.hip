@@ -705,6 +705,55 @@ __device__ __forceinline__ int next_pow2(int v) {
   return p;
 }
 
+// Passes j = jtop..1 of bitonic stage k on one 64-element chunk held one
+// element per lane (element i = chunk base + lane), exchanged by shuffles:
+// the lower index of each pair keeps the smaller value when the block of
+// size k holding it sorts ascending, the larger otherwise.
+__device__ __forceinline__ int64_t chunk_passes_reg(int64_t v, int i, int k, int jtop, int lane) {
+  const bool up = (i & k) == 0;
+  for (int j = jtop; j > 0; j >>= 1) {
+    const int64_t o = (int64_t)shfl_xor_u64((uint64_t)v, j);
+    const bool lower = (lane & j) == 0;
+    const int64_t lo = o < v ? o : v, hi = o < v ? v : o;
+    v = (lower == up) ? lo : hi;
+  }
+  return v;
+}
+
+// Bitonic sort of the global array g[0..P) (P a power of two, at least 128)
+// by one wave: wave_bitonic's passes in its order, but every pass with
+// j < 64 runs on 64-element chunks in registers, so only the passes with
+// j >= 64 go through memory (21 instead of 78 for 4,096 values).
+__device__ void wave_sort_global(int64_t* g, int P, int lane) {
+  for (int base = 0; base < P; base += 64) {
+    int64_t v = g[base + lane];
+    for (int k = 2; k <= 64; k <<= 1) v = chunk_passes_reg(v, base + lane, k, k >> 1, lane);
+    g[base + lane] = v;
+  }
+  wave_sync_global();
+  for (int k = 128; k <= P; k <<= 1) {
+    for (int j = k >> 1; j >= 64; j >>= 1) {
+      for (int i = lane; i < P; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int64_t x = g[i], y = g[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            g[i] = y;
+            g[ixj] = x;
+          }
+        }
+      }
+      wave_sync_global();
+    }
+    for (int base = 0; base < P; base += 64) {
+      const int64_t v = chunk_passes_reg(g[base + lane], base + lane, k, 32, lane);
+      g[base + lane] = v;
+    }
+    wave_sync_global();
+  }
+}
+
 __device__ __forceinline__ int64_t resolve_entry(uint64_t e, uint32_t rep, const DevCell& c,
                                                  const uint64_t* __restrict__ T,
                                                  const uint32_t* __restrict__ guide,
@@ -1275,7 +1324,7 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
     const int P = next_pow2(oc);
     for (int k = oc + lane; k < P; k += 64) gov[k] = INT64_MAX;
     wave_sync_global();
-    wave_bitonic(gov, P, lane, GlobalSync{});
+    wave_sort_global(gov, P, lane);
   }
   const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, want_fp);
   wave_sync_global();
