@@ -25,7 +25,7 @@ sys.path.insert(0, str(ROOT))
 METRIC = "MC replicates/sec (sample+MLE+KS) batched vs plain at n=1000; p99 fit latency"
 QS = [(9, 10), (95, 100), (99, 100), (999, 1000)]
 
-# Algorithmic VALU work model (ops per draw and per replicate), see the design doc:
+# Algorithmic VALU work model (ops per draw and per replicate):
 # Philox4x32-10 = 10 rounds x (2 32x32->64 multiplies as 2 ops each + 2
 # three-way xors as 2 ops each) = 80 ops per block of 2 draws; the 53-bit
 # uniform 3 ops; guide lookup + table compare 4 ops; histogram update 2 ops.

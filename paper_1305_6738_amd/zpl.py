@@ -66,8 +66,8 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not LIB_PATH.exists():
             raise RuntimeError(
-                "libzpl.so is not built (run __graft_entry__.build() or "
-                "python -m paper_1305_6738_amd._build); there is no CPU fallback")
+                "libzpl.so is not built (run python -m paper_1305_6738_amd._build); "
+                "there is no CPU fallback")
         L = C.CDLL(str(LIB_PATH))
         vp, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
         P = C.POINTER
