@@ -162,6 +162,10 @@ def test_fit_xmin_matches_oracle(ctx, orc, xmin):
     # device input gives the same result
     rd = ctx.fit(torch.from_numpy(x).cuda(), xmin=xmin)
     assert (rd["alpha_hat"], rd["D"]) == (r["alpha_hat"], r["D"])
+    # the scan's candidate runs the same arithmetic as the single fit (at
+    # xmin = 1 the pure law's: the workgroup fit of zpl_fit, bit for bit)
+    s = ctx.fit_scan(x, [xmin])
+    assert (s["alpha_hat"][0], s["D"][0]) == (r["alpha_hat"], r["D"])
 
 
 def test_fit_xmin_edge_cases(ctx, orc):
