@@ -318,6 +318,12 @@ bool form_eligible(uint32_t m, double alpha, int64_t n, uint32_t K = 0) {
   return true;
 }
 
+// Estimated cost (ns per replicate, device busy) of a replicate of the
+// truncated law on 1..K with n draws, in the lane or wave form: about 2.2 ps
+// per draw and 19 ps per support value (sums of the MLE and the KS distance),
+// measured on MI355X over the paper's sample sizes at K = 20 and K = 1000.
+double trunc_cost(int64_t n, uint32_t K) { return 2.2e-3 * ((double)n + 8.6 * (double)K); }
+
 // Time for one cell alone under form f (tuned cost v ns per replicate with
 // the device busy): its work units (kBlock replicates per workgroup for the
 // lane and wave forms, 8 for the heavy form, which fits two workgroups per
@@ -329,13 +335,22 @@ double cell_makespan(int f, double v, int64_t R, int n_cu) {
   return std::ceil(std::ceil((double)R / per) / conc) * v * conc * per;
 }
 
-// With a tuning table: the eligible form of least cost per replicate, or,
+// Pure law with a tuning table: the eligible form of least cost per replicate, or,
 // when `horizon` (ns) is given and that form alone would take longer than
 // the horizon (a few thousand long replicates, as in a bootstrap, fill only
-// a few workgroups), the form that finishes the cell soonest.
+// a few workgroups), the form that finishes the cell soonest.  Otherwise
+// (no table, or the truncated law): the lane form when a replicate's values
+// above its column are few, else the wave form when its overflow area holds
+// them, else the heavy form.
 uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0, int64_t R = 0,
                      int n_cu = 256, double horizon = -1.0, double* cost = nullptr) {
-  if (t && !t->empty()) {
+  if (cost) *cost = 0.0;
+  if (K > 0) {
+    // the table measures the pure law; the truncated law's cost is mostly
+    // its finite sums (K terms per MLE step), which the heavy form runs one
+    // replicate per wave: the built-in rule below, with an estimated cost
+    if (cost && t && !t->empty()) *cost = trunc_cost(n, K) * (double)R;
+  } else if (t && !t->empty()) {
     int best = -1, fast = -1;
     double bc = 0.0, bm = 0.0;
     for (int f = 0; f < 3; ++f) {
@@ -358,7 +373,6 @@ uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0, i
       return (uint32_t)best;
     }
   }
-  if (cost) *cost = 0.0;
   if (n <= 65535 && (double)n * tail_prob(alpha, kHLB, K) <= 2.0) return kModeLane;
   if (form_eligible(kModeWave, alpha, n, K)) return kModeWave;
   return kModeHeavy;
@@ -444,14 +458,15 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
   }
   // units: kBlock replicates (one per lane, or 64 per wave) for lane/wave
   // cells, 8 replicates (2 per wave) for heavy cells; weights for the
-  // longest-first order come from the tuning table when there is one
+  // longest-first order come from the tuning table when there is one (the
+  // truncated law: draws plus its K-term sums, see trunc_cost)
   std::vector<std::pair<double, Unit>> tmp;
   for (int i = 0; i < n_cells; ++i) {
     const DevCell& d = P.cells[i];
     const int per = d.mode == kModeHeavy ? 8 : kBlock;
-    double w = (double)d.n;
+    double w = d.K ? (double)d.n + 8.6 * (double)d.K : (double)d.n;
     if (tune && !tune->empty()) {
-      const double v = tuned_cost(*tune, (int)d.mode, d.alpha, d.n);
+      const double v = d.K ? trunc_cost(d.n, d.K) : tuned_cost(*tune, (int)d.mode, d.alpha, d.n);
       if (v > 0.0) w = v;
     }
     for (int64_t r = 0; r < d.R; r += per) {

@@ -140,6 +140,18 @@ def test_truncated_cells_plan_and_validate():
         assert e.value.status == -1, bad
 
 
+def test_truncated_cells_ignore_the_pure_law_table():
+    """A table measures the pure law only: under one that makes the heavy
+    form cheapest everywhere, truncated cells keep the built-in rule (the
+    heavy form runs their K-term sums one replicate per wave), and pure cells
+    beside them follow the table."""
+    heavy = grid([1.5, 3.5], [10, 100000], lambda a, n: (9.0, 9.0, 1.0))
+    cells = [(0.25, 50000, R, 1, 0, 1000), (4.0, 20000, R, 1, 1, 20), (1.0, 10, R, 1, 2, 1000),
+             (2.5, 1000, R, 1, 3)]
+    assert plan_forms(cells, heavy) == plan_forms(cells[:3]) + ["heavy"]
+    assert plan_forms(cells[:3], heavy) == ["wave", "lane", "wave"]
+
+
 def test_few_long_replicates_spread_over_the_device():
     """A bootstrap-sized cell (2,500 replicates of 98,000 draws): the wave
     form is cheaper per replicate (208 against 545 ns with the device busy)
