@@ -116,6 +116,29 @@ def test_table_entry_is_a_simulate_cells_run(ctx):
     assert np.array_equal(q.reshape(2, 3, 2, 4), runs)
 
 
+def test_table_split_by_the_memory_budget_is_bit_identical(ctx):
+    """Runs are simulated in groups whose D arrays and selection scratch fit
+    a quarter of the context's budget.  Under a 2 GiB budget, 1,000 runs of
+    50,000 replicates need two groups; the table and every run's quantiles
+    equal those of one group (the default 64 GiB context)."""
+    from paper_1305_6738_amd import Context
+    R, budget = 50000, 2 << 30
+    per_run = R * 8 + 4 * min(32768, R * 3 // 20 + 1024) * 8 + 4096 * 8 + 3585 * 2
+    gammas, ns, seeds = [1.75, 3.0], [10, 20], 250
+    assert len(gammas) * len(ns) * seeds > (budget // 4) // per_run  # at least two groups
+    say("table split by budget")
+    small = Context(0, mem_budget_bytes=budget)
+    try:
+        tab, runs = small.critical_table(gammas, ns, kmax=0, seeds=seeds, seed0=3,
+                                         replicates=R, quantiles=Q4, per_run=True)
+    finally:
+        small.close()
+    tab1, runs1 = ctx.critical_table(gammas, ns, kmax=0, seeds=seeds, seed0=3, replicates=R,
+                                     quantiles=Q4, per_run=True)
+    assert np.array_equal(runs, runs1)
+    assert np.array_equal(tab, tab1)
+
+
 def test_invalid_tables_rejected(ctx):
     from paper_1305_6738_amd import ZplError
     for kw in [dict(seeds=0), dict(seeds=1025), dict(replicates=0), dict(kmax=1),
