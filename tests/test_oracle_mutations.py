@@ -53,6 +53,23 @@ MUTANTS = [
      "if (best < 0 || D[c] > D[best]) best = c;"),
     ("xmin tail starts at the pure law's", "const double m = (double)(xmin + ORC_TABLE_H);",
      "const double m = (double)(ORC_TABLE_H + 1);"),
+    # the truncated law on 1..K
+    ("trunc suffix sum one index up", "suf[t] = suf[t + 1] + pow((double)(t + 1), -g);",
+     "suf[t] = suf[t + 1] + pow((double)(t + 2), -g);"),
+    ("trunc Z' sign", "    z1 -= l * t;", "    z1 += l * t;"),
+    ("trunc Z'' without the square", "    z2 += l * l * t;", "    z2 += l * t;"),
+    ("trunc table normalised by the wrong sum", "T[k - 1] = 1.0 - suf[k] / suf[0];",
+     "T[k - 1] = 1.0 - suf[k] / suf[1];"),
+    ("trunc draw never returns 1", "  int lo = 1, hi = K;\n  while (lo < hi) {\n    int mid = lo + (hi - lo) / 2;",
+     "  int lo = 2, hi = K;\n  while (lo < hi) {\n    int mid = lo + (hi - lo) / 2;"),
+    ("trunc MLE equation sign", "double gval = -r1 - m;", "double gval = r1 - m;"),
+    ("trunc KS below each value at the value", "double Fv1 = 1.0 - suf[v - 1] / z;",
+     "double Fv1 = 1.0 - suf[v] / z;"),
+    ("trunc KS upper term uses the count below", "double d1 = fabs((double)upto / dn - Fv);",
+     "double d1 = fabs((double)below / dn - Fv);"),
+    ("trunc all-ones rule missing",
+     "    s = log(2.0);\n    *flags |= ORC_FLAG_ALL_ONES;\n  }\n  double a = orc_tz_mle(",
+     "    s = 0.0;\n    *flags |= ORC_FLAG_ALL_ONES;\n  }\n  double a = orc_tz_mle("),
 ]
 
 
@@ -115,6 +132,59 @@ def _checks(orc):
     if ones["p_value"] < 0.3:
         failed.append("bootstrap ties")
     failed += _checks_xmin(orc)
+    failed += _checks_trunc(orc)
+    return failed
+
+
+def _checks_trunc(orc):
+    """Quick pins of the truncated law on 1..K against mpmath sums."""
+    failed = []
+    K = 20
+    with mp.workdps(30):
+        for g in (0.0, 1.0, 2.5):
+            want = [mp.fsum(mp.mpf(k) ** -g * mp.log(k) ** d for k in range(1, K + 1))
+                    for d in range(3)]
+            z = orc.tz_norm3(g, K)
+            if abs(z[0] - float(want[0])) > 1e-13 * float(want[0]) or \
+                    abs(z[1] + float(want[1])) > 1e-13 * float(want[1]) or \
+                    abs(z[2] - float(want[2])) > 1e-13 * float(want[2]):
+                failed.append("trunc normaliser")
+                break
+        g = 0.75
+        T = orc.tz_cdf_table(g, K)
+        Z = mp.fsum(mp.mpf(k) ** -g for k in range(1, K + 1))
+        F = [float(mp.fsum(mp.mpf(k) ** -g for k in range(1, t + 1)) / Z) for t in range(1, K + 1)]
+    if np.max(np.abs(T - np.array(F))) > 1e-15:
+        failed.append("trunc table")
+    x = orc.tz_sample(g, K, 200, 5, 3, 11)
+    for i in range(200):
+        w = orc.philox([i >> 1, 11, 3, 0], [5, 0])
+        U = orc.u53(w[2], w[3]) if i & 1 else orc.u53(w[0], w[1])
+        if x[i] != 1 + int(np.searchsorted(np.array(F), U, side="left")):
+            failed.append("trunc draws")
+            break
+    xs = np.array([1, 1, 2, 3, 3, 7, 12, 20, 5])
+    r = orc.tz_fit(xs, K)
+    a = r["alpha_hat"]
+    with mp.workdps(30):
+        Z = mp.fsum(mp.mpf(k) ** -a for k in range(1, K + 1))
+        mu = mp.fsum(mp.log(k) * mp.mpf(k) ** -a for k in range(1, K + 1)) / Z
+        best, Fa = mp.mpf(0), mp.mpf(0)
+        for t in range(1, K + 1):
+            Fa += mp.mpf(t) ** -a / Z
+            best = max(best, abs(Fa - mp.mpf(int(np.sum(xs <= t))) / len(xs)))
+    if abs(float(mu) - r["S"] / len(xs)) > 1e-12:
+        failed.append("trunc MLE equation")
+    if abs(r["D"] - float(best)) > 1e-12:
+        failed.append("trunc KS")
+    # all ones: S := ln 2, and D is the mass above 1 under the fit
+    r = orc.tz_fit(np.ones(10, np.int64), K)
+    with mp.workdps(30):
+        a = mp.findroot(lambda s: mp.fsum(mp.log(k) * mp.mpf(k) ** -s for k in range(1, K + 1))
+                        / mp.fsum(mp.mpf(k) ** -s for k in range(1, K + 1)) - mp.log(2) / 10, 4)
+        want = 1 - 1 / mp.fsum(mp.mpf(k) ** -a for k in range(1, K + 1))
+    if abs(r["D"] - float(want)) > 1e-12:
+        failed.append("trunc all-ones atom")
     return failed
 
 
