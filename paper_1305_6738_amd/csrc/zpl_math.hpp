@@ -429,7 +429,12 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
     if (done) break;
   }
   if (it == 200) *flags |= kFlagNoConv;
-  if (fabs(a) > 63.0) {  // near an edge: is the root inside the bracket?
+  // Near an edge, is the root inside the bracket?  mu tends to ln K as s
+  // falls, and for small K it reaches ln K to FP64 rounding well inside the
+  // bracket (K = 2: from s of about -53 on), where an iterate can stop with
+  // mu == m although m (every value equal to K) has no root: check the lower
+  // edge then too.
+  if (fabs(a) > 63.0 || (a < 0.0 && m >= ln[K] * (1.0 - 0x1p-50))) {
     const double e = a > 0.0 ? 64.0 : -64.0;
     const Z3 z = zeta3_trunc(e, K, ln);
     const double mue = -z.z1 / z.z0;

@@ -63,6 +63,13 @@ int64_t hm_tail_from(double alpha, int64_t xmin, uint64_t seed, uint32_t stream,
   return tail_draw_from(m0, beta, tail_g(beta, m0), (uint32_t)seed, (uint32_t)(seed >> 32), i,
                         rep, stream, flags);
 }
+void hm_zeta3_trunc(double s, uint32_t K, double* out) {
+  Z3 z = zeta3_trunc(s, K, g_ln.data());
+  out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;
+}
+double hm_mle_trunc(double m, uint32_t K, uint32_t* flags) {
+  return mle_alpha_trunc(m, K, g_ln.data(), flags);
+}
 void hm_dd_exp_log(double v, double* out) {
   DD l = dd_log(v);
   DD e = dd_exp(DD{v, 0.0});

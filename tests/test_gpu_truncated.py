@@ -106,6 +106,25 @@ def test_simulate_all_forms(ctx, orc, form):
         lo += cell[2]
 
 
+@pytest.mark.parametrize("form", ["auto", "wave", "heavy"])
+def test_no_root_at_small_K(ctx, orc, form):
+    """K = 2 and 3 with small samples: a replicate whose values all equal K
+    has no root (mu < ln K everywhere, and for K = 2 mu reaches ln K to FP64
+    rounding near s = -53).  Like the oracle, the GPU returns the bracket end
+    -64 with NOCONV for every such replicate, in every form."""
+    cells = [(0.25, 5, 3000, 3, 0, 2), (-1.0, 5, 2000, 3, 1, 2), (-2.0, 4, 2000, 3, 2, 3)]
+    say("no root at small K", form)
+    g = run_cells(ctx, cells, form=form)
+    lo = 0
+    for cell in cells:
+        compare(orc, g, lo, cell)
+        lo += cell[2]
+    edge = g["alpha_hat"] == -64.0
+    assert edge.sum() > 100 and np.all(g["flags"][edge] & 8)
+    r = ctx.fit(np.full(7, 2, dtype=np.int64), kmax=2)
+    assert r["status"] == -4 and r["alpha_hat"] == -64.0
+
+
 def test_mixed_with_pure_cells_bit_identical(ctx):
     pure = [(2.5, 100, 400, 1, 0, 0), (1.75, 50, 300, 1, 1, 0)]
     trunc = [(1.0, 100, 400, 1, 2, 20), (0.5, 200, 300, 1, 3, 1000)]

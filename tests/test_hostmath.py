@@ -46,6 +46,9 @@ def hm(tmp_path_factory):
     L.hm_tail_from.argtypes = [C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_uint32,
                                C.c_uint32, P(C.c_uint32)]
     L.hm_tail_from.restype = C.c_int64
+    L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
+    L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
+    L.hm_mle_trunc.restype = C.c_double
     return L
 
 
@@ -199,3 +202,38 @@ def test_tail_from_a_cutoff_matches_oracle(hm, orc):
             got = hm.hm_tail_from(a, xmin, 11, 7, 0, i, C.byref(f))
             x, _ = orc.hz_sample(a, xmin, i + 1, 11, 7, 0)
             assert got == x[i], (a, xmin, i)
+
+
+@pytest.mark.parametrize("K", [2, 20, 1000, 4096])
+def test_truncated_sums_vs_oracle(hm, orc, K):
+    """Z_K and its s-derivatives (the library sums from K down with exp of
+    s ln k from a rounded ln k; the oracle with pow): within the
+    recursive-summation bound K eps plus the exponent's rounding, |s| ln K
+    eps relative per term (the terms of each sum share one sign)."""
+    for s in (-3.0, 0.0, 0.25, 1.0, 2.5, 40.0):
+        out = (C.c_double * 3)()
+        hm.hm_zeta3_trunc(s, K, out)
+        ref = orc.tz_norm3(s, K)
+        tol = 4e-16 * K + 2.3e-16 * abs(s) * math.log(K)
+        for i in range(3):
+            assert abs(out[i] - ref[i]) <= tol * abs(ref[i]) + 1e-300, (K, s, i)
+
+
+@pytest.mark.parametrize("K", [2, 20, 1000, 4096])
+def test_truncated_mle_vs_oracle(hm, orc, K):
+    """mle_alpha_trunc on the mean log of simulated samples (and of samples
+    with no root in [-64, 64]) against the oracle's truncated MLE."""
+    rng = np.random.default_rng(K)
+    for _ in range(8):
+        g = float(rng.uniform(-0.5, 4.0))
+        x = orc.tz_sample(g, K, int(rng.integers(3, 300)), 5, 2, int(rng.integers(0, 1000)))
+        r = orc.tz_fit(x, K)
+        f = C.c_uint32(0)
+        a = hm.hm_mle_trunc(r["S"] / x.size, K, C.byref(f))
+        assert abs(a - r["alpha_hat"]) <= 1e-11 * max(abs(r["alpha_hat"]), 1.0), (K, g, x)
+        assert (f.value & 8) == (r["flags"] & 8)
+    for m in (0.0 + 1e-300, math.log(K)):  # every value 1 (without the rule) / every value K
+        f = C.c_uint32(0)
+        a = hm.hm_mle_trunc(m, K, C.byref(f))
+        ao, fo = orc.tz_mle(m, K)
+        assert a == ao and (f.value & 8) and (fo & 8), (K, m, a, ao)
