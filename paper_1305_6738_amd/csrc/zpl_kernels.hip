@@ -437,10 +437,13 @@ __device__ __forceinline__ double wave_max_f64(double v) {
 }
 
 // iz = 1/zeta(a, xmin): F(t) = 1 - zeta(a, t+1) iz for t >= xmin - 1 (the
-// first distinct value's lower term is then zero).
+// first distinct value's lower term is then zero).  cut: the law with a lower
+// cutoff, whose survival values above 16 come from survival_next_cut (there
+// they are the normaliser's own scale, not a tail of zeta(a)).
 __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_t* __restrict__ lc,
                                    int len, const EmCoef& E, const double (&suf)[17], int64_t n,
-                                   const double* __restrict__ ln, int lane, double iz) {
+                                   const double* __restrict__ ln, int lane, double iz,
+                                   bool cut = false) {
   const double idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0;
@@ -468,10 +471,10 @@ __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_
     bool have = q0 == p16;  // zprev is zeta(a, vprev + 1)
     for (int q = q0; q < q1; ++q) {
       const int64_t v = lv[q];
-      const double zv = survival_next(E, v, ln);
+      const double zv = cut ? survival_next_cut(E, v, ln) : survival_next(E, v, ln);
       double zv1;
       if (v - 1 == vprev)
-        zv1 = have ? zprev : survival_next(E, vprev, ln);
+        zv1 = have ? zprev : (cut ? survival_next_cut(E, vprev, ln) : survival_next(E, vprev, ln));
       else
         zv1 = zv + pow_neg(E.s, ln_value(v, ln));
       const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
@@ -509,13 +512,13 @@ __device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const u
     const double a = mle_alpha_hz(u128_to_S(Sx) / (double)n, xmin, ln, &fl);
     const EmCoef E = em_coef(a);
     double suf[17];
-    survival_head(E, ln, suf);
+    survival_head_cut(E, ln, suf);
     double zx = 0.0;  // zeta(a, xmin) = suf[xmin - 1] (static indices: no scratch)
 #pragma unroll
     for (int t = 1; t <= 16; ++t)
       if (xmin - 1 == t) zx = suf[t];
-    if (xmin > 17) zx = hurwitz_tail(E, (double)xmin, ln_value(xmin, ln));
-    D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / zx);
+    if (xmin > 17) zx = survival_next_cut(E, xmin - 1, ln);
+    D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / zx, true);
     ahat = a;
     flags = fl;
     return;
@@ -1661,20 +1664,21 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
   if (k > kH || cells[cell].K != 0u) return;
   const double a = cells[cell].alpha;
   double suf[17];
-  survival_head(a, ln, suf);
   const int64_t xmin = cells[cell].xmin;
   if (xmin > 1) {  // T[k-1] = F(xmin + k - 1) = 1 - zeta(a, xmin + k)/zeta(a, xmin)
     const EmCoef E = em_coef(a);
+    survival_head_cut(E, ln, suf);
     auto zq = [&](int64_t q) {  // zeta(a, q), q >= 2 (static indices into suf: no scratch)
       double z = 0.0;
 #pragma unroll
       for (int t = 1; t <= 16; ++t)
         if (q - 1 == t) z = suf[t];
-      return q <= 17 ? z : survival_next(E, q - 1, ln);
+      return q <= 17 ? z : survival_next_cut(E, q - 1, ln);
     };
     tables[(size_t)cell * kH + (k - 1)] = 1.0 - zq(xmin + k) / zq(xmin);
     return;
   }
+  survival_head(a, ln, suf);
   double zk = suf[16];
 #pragma unroll
   for (int t = 1; t < 16; ++t)

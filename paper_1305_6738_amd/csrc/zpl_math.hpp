@@ -285,15 +285,44 @@ ZPL_HD double ln_value(int64_t v, const double* __restrict__ ln) {
 }
 
 // ---------------------------------------------------------------------------
+// zeta(s, q) for the law with a lower cutoff, where it is the whole
+// normaliser rather than a small tail of zeta(s).  The Euler-Maclaurin terms
+// shrink like ((s + 2i) / (2 pi q))^2: with eight Bernoulli terms the
+// remainder is below 1e-16 relative from q = 1.5 s + 10 on (s <= 64, checked
+// against partial sums at 40 digits), while at q = 17 it reaches 4e-15 at
+// s = 10 and 2e-4 at s = 64.  So the tail starts at q0 = em_start(s) =
+// ceil(1.6 s + 10) (a margin over 1.5 s + 10; 17 for s <= 4.375, where
+// nothing changes) and the terms below it are summed directly.
+// ---------------------------------------------------------------------------
+ZPL_HD int64_t em_start(double s) {
+  const double q = ceil(fma(1.6, s, 10.0));
+  return q > 17.0 ? (int64_t)q : 17;
+}
+
+// Where zeta(s, q) itself (q >= 2) starts its Euler-Maclaurin tail:
+// em_start(s), or 2q if that is smaller (the tail from 2q on weighs about
+// 2^(1-s) of zeta(s, q) when em_start(s) > 2q, which outweighs its larger
+// Euler-Maclaurin error: the product stays below 1e-18), and at least 17.
+ZPL_HD int64_t em_point(double s, int64_t q) {
+  const int64_t e = em_start(s);
+  const int64_t t = q < (e + 1) / 2 ? 2 * q : e;  // no 2q overflow for large q
+  return t > 17 ? t : 17;
+}
+
+// ---------------------------------------------------------------------------
 // The law with a lower cutoff xmin (p(k) = k^-a / zeta(a, xmin), k >= xmin;
 // the practice the paper cites for fitting, xmin = 1 being its own case).
-// zeta(s, xmin) and its first two s-derivatives: direct terms k = xmin..16
-// (none when xmin >= 17), largest k first, after the Euler-Maclaurin tail at
-// q = max(xmin, 17) and its derivatives, as zeta3 does for xmin = 1.
+// zeta(s, xmin) and its first two s-derivatives: direct terms k = xmin..q-1
+// (none when xmin >= q), largest k first, after the Euler-Maclaurin tail at
+// q = max(xmin, em_point(s, xmin)) and its derivatives (em_point keeps that
+// tail accurate at large s; it is 17 for s <= 4.375, as zeta3 uses for
+// xmin = 1).
 // ---------------------------------------------------------------------------
 ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
-  const double q = xmin < 17 ? 17.0 : (double)xmin;
-  const double L = xmin < 17 ? ln[17] : ln_value(xmin, ln);
+  const int64_t q0 = em_point(s, xmin);
+  const int64_t qi = xmin < q0 ? q0 : xmin;
+  const double q = (double)qi;
+  const double L = ln_value(qi, ln);
   const double iq = 1.0 / q, iq2 = iq * iq;
   const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
                        1.0 / 30240.0,      -1.0 / 1209600.0,
@@ -326,7 +355,7 @@ ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
   double z0 = qs * Q0;
   double z1 = qs * fma(-L, Q0, Q1);
   double z2 = qs * fma(L * L, Q0, fma(-2.0 * L, Q1, Q2));
-  for (int64_t k = 16; k >= xmin; --k) {
+  for (int64_t k = qi - 1; k >= xmin; --k) {
     const double lk = ln[k];
     const double t = pow_neg(s, lk);
     z0 += t;
@@ -473,6 +502,37 @@ ZPL_HD double survival_next(const EmCoef& E, int64_t v, const double* __restrict
 
 ZPL_HD double survival_next(double a, int64_t v, const double* __restrict__ ln) {
   return survival_next(em_coef(a), v, ln);
+}
+
+// The direct part of survival_next_cut: zeta(s, v+1) as the tail at q0 plus
+// the terms v+1..q0-1, largest first (k < q0 <= 113: from the ln table).
+// Out of line: only large exponents take it, and inlined it would crowd the
+// registers of the KS loops that call it.
+static __host__ __device__ __noinline__ double survival_cut_direct(double s, int64_t v, int64_t q0,
+                                                                   const double* __restrict__ ln) {
+  double z = hurwitz_tail(em_coef(s), (double)q0, ln[q0]);
+  for (int64_t k = q0 - 1; k > v; --k) z += pow_neg(s, ln[k]);
+  return z;
+}
+
+// zeta(a, v+1) for an integer 16 <= v < 2^63, accurate at any a <= 64: the
+// Euler-Maclaurin tail at max(v + 1, em_point(a, v + 1)), then the direct
+// terms below it.
+ZPL_HD double survival_next_cut(const EmCoef& E, int64_t v, const double* __restrict__ ln) {
+  if (v >= em_start(E.s) - 1) return survival_next(E, v, ln);  // (v + 1 may not fit)
+  const int64_t q0 = em_point(E.s, v + 1);
+  if (v >= q0 - 1) return survival_next(E, v, ln);
+  return survival_cut_direct(E.s, v, q0, ln);
+}
+
+// survival_head with an accurate suf[16] = zeta(a, 17) (see em_start).
+ZPL_HD void survival_head_cut(const EmCoef& E, const double* __restrict__ ln, double suf[17]) {
+  double pw[17];
+  small_powers(E.s, ln, pw);
+  suf[16] = survival_next_cut(E, 16, ln);
+#pragma unroll
+  for (int t = 15; t >= 1; --t) suf[t] = suf[t + 1] + pw[t + 1];
+  suf[0] = suf[1] + 1.0;
 }
 
 // ---------------------------------------------------------------------------

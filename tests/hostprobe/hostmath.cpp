@@ -54,6 +54,12 @@ void hm_hurwitz3(double s, int64_t xmin, double* out) {
   Z3 z = hurwitz3(s, xmin, g_ln.data());
   out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;
 }
+double hm_survival_cut(double a, int64_t v) {  // zeta(a, v+1), law with a cutoff
+  const EmCoef E = em_coef(a);
+  double suf[17];
+  survival_head_cut(E, g_ln.data(), suf);
+  return v <= 16 ? suf[v] : survival_next_cut(E, v, g_ln.data());
+}
 double hm_mle_hz(double m, int64_t xmin, uint32_t* flags) {
   return mle_alpha_hz(m, xmin, g_ln.data(), flags);
 }

@@ -65,7 +65,8 @@ def compare(orc, g, lo, cell, reps=None):
     assert np.all(np.abs(g["D"][gi] - ref["D"]) <= 1e-12), cell
 
 
-@pytest.mark.parametrize("a,xmin", [(2.5, 2), (1.6, 17), (3.3, 18), (2.0, 500), (1.8, 123456)])
+@pytest.mark.parametrize("a,xmin", [(2.5, 2), (1.6, 17), (3.3, 18), (2.0, 500), (1.8, 123456),
+                                    (30.0, 17), (50.0, 20), (12.0, 16)])
 def test_cdf_table_matches_oracle(ctx, orc, a, xmin):
     T = torch.zeros(4096, dtype=torch.float64, device="cuda")
     ctx.cdf_table(a, T, xmin=xmin)
@@ -114,6 +115,31 @@ def test_simulate_cells_match_oracle(ctx, orc):
     # the all-at-cutoff rule and the bracket end are exercised
     assert np.any(g["flags"][700 + 200:700 + 200 + 513] & 1)
     assert np.any(g["flags"][700 + 200 + 513 + 130:700 + 200 + 513 + 130 + 300] & 8)
+
+
+def test_large_exponents_at_small_cutoffs(ctx, orc):
+    """Exponents far above 2 with cutoffs near 17: zeta(a, q) is then the
+    whole normaliser, and its Euler-Maclaurin tail must start at 1.6 a + 10
+    (at q = 17 it is off by 4e-15 at a = 10 and 2e-4 at a = 64).  Every
+    replicate against the oracle, and fits of data piled at the cutoff."""
+    cells = [(25.0, 50, 400, 5, 10, 0, 17), (12.0, 200, 300, 5, 11, 0, 3),
+             (40.0, 30, 300, 5, 12, 0, 20), (9.0, 100, 300, 5, 13, 0, 16),
+             (60.0, 40, 200, 5, 14, 0, 30)]
+    say("large exponents at small cutoffs")
+    g = run_cells(ctx, cells)
+    lo = 0
+    for cell in cells:
+        compare(orc, g, lo, cell)
+        lo += cell[2]
+    for xmin in (2, 16, 17, 20):
+        for extra in ([1, 1, 1], [1, 1, 2], [1] * 6 + [3]):
+            x = np.array([xmin] * 60 + [xmin + e for e in extra])
+            r = ctx.fit(x, xmin=xmin)
+            ref = orc.hz_fit(x, xmin)
+            assert abs(r["alpha_hat"] - ref["alpha_hat"]) <= 1e-10 * ref["alpha_hat"], (xmin, extra)
+            assert abs(r["D"] - ref["D"]) <= 1e-12, (xmin, extra)
+            s = ctx.fit_scan(x, [xmin])
+            assert (s["alpha_hat"][0], s["D"][0]) == (r["alpha_hat"], r["D"])
 
 
 def test_cutoff_cells_beside_pure_cells_bit_identical(ctx):

@@ -46,6 +46,8 @@ def hm(tmp_path_factory):
     L.hm_tail_from.argtypes = [C.c_double, C.c_int64, C.c_uint64, C.c_uint32, C.c_uint32,
                                C.c_uint32, P(C.c_uint32)]
     L.hm_tail_from.restype = C.c_int64
+    L.hm_survival_cut.argtypes = [C.c_double, C.c_int64]
+    L.hm_survival_cut.restype = C.c_double
     L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
     L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
     L.hm_mle_trunc.restype = C.c_double
@@ -153,7 +155,10 @@ def test_exact_S_order_independent(hm):
 
 
 @pytest.mark.parametrize("s,q", [(1.3, 2), (2.5, 7), (3.0, 17), (2.2, 18), (4.0, 300),
-                                 (50.0, 300), (1.7, 123456)])
+                                 (50.0, 300), (1.7, 123456),
+                                 # large s at small q: the tail starts at 1.6 s + 10
+                                 (10.0, 17), (20.0, 17), (40.0, 17), (64.0, 17), (54.0, 16),
+                                 (30.0, 2), (25.0, 30), (50.0, 60), (64.0, 106), (64.0, 107)])
 def test_hurwitz3_at_a_cutoff(hm, s, q):
     """zeta(s, q) and its s-derivatives for the law with a lower cutoff,
     against partial sums at 40 digits (mpmath's own Hurwitz zeta is not
@@ -237,3 +242,70 @@ def test_truncated_mle_vs_oracle(hm, orc, K):
         a = hm.hm_mle_trunc(m, K, C.byref(f))
         ao, fo = orc.tz_mle(m, K)
         assert a == ao and (f.value & 8) and (fo & 8), (K, m, a, ao)
+
+
+@pytest.mark.parametrize("a", [3.0, 10.0, 25.0, 40.0, 64.0])
+def test_survival_at_a_cutoff_large_exponent(hm, a):
+    """zeta(a, v+1) as the law with a cutoff uses it (CDF table and KS),
+    against partial sums at 40 digits, for v below, at and above 1.6 a + 10."""
+    for v in (1, 2, 5, 15, 16, 17, 18, 30, 60, 100, 111, 112, 200, 5000):
+        got = hm.hm_survival_cut(a, v)
+        with mp.workdps(40):
+            # 6,000 terms, then the remainder (relatively tiny: mpmath's own
+            # Hurwitz value is accurate enough for it)
+            want = mp.fsum(mp.mpf(k) ** -a for k in range(v + 1, v + 1 + 6000)) + \
+                mp.zeta(a, v + 1 + 6000)
+            if a < 10.0:
+                want = mp.zeta(a, v + 1)
+        tol = 3e-15 + 1.2e-16 * a * math.log(v + 1)
+        assert abs(got - float(want)) <= tol * float(want), (a, v, got, float(want))
+
+
+def _var_trunc(a, K):
+    with mp.workdps(40):
+        w = [mp.mpf(k) ** -mp.mpf(a) for k in range(1, K + 1)]
+        Z = mp.fsum(w)
+        mu = mp.fsum(mp.log(k) * w[k - 1] for k in range(1, K + 1)) / Z
+        return float(mp.fsum((mp.log(k) - mu) ** 2 * w[k - 1] for k in range(1, K + 1)) / Z)
+
+
+def _var_cut(a, q):
+    with mp.workdps(40):
+        N = q + 6000  # partial sums: mpmath's own Hurwitz zeta is not accurate at large a
+        w = [(mp.mpf(k) ** -mp.mpf(a), mp.log(k)) for k in range(q, N)]
+        Z = mp.fsum(t for t, _ in w)
+        mu = mp.fsum(t * l for t, l in w) / Z
+        return float(mp.fsum(t * (l - mu) ** 2 for t, l in w) / Z)
+
+
+def test_mle_edges_agree_within_the_conditioning_of_eq2(hm, orc):
+    """Across each law's whole range of mean logs m, up to its edges (every
+    value at K, or at the cutoff), the library's root agrees with the
+    oracle's to 1e-10, or -- where eq. (2) is ill-conditioned -- within
+    4 eps m / Var(ln X) at the root: an FP64 mu is only that precise, and
+    both sides sit at that noise.  (This found the Euler-Maclaurin start
+    that the law with a cutoff needs at large exponents.)"""
+    eps = 2.0 ** -53
+    rng = np.random.default_rng(23)
+    for K in (2, 3, 20, 1000):
+        lnK = math.log(K)
+        ms = list(rng.uniform(0, lnK, 25)) + [lnK * (1 - 10.0 ** -e) for e in (2, 5, 8, 11, 14)]
+        for m in ms:
+            f = C.c_uint32(0)
+            a = hm.hm_mle_trunc(m, K, C.byref(f))
+            ao, fo = orc.tz_mle(m, K)
+            if abs(a - ao) <= 1e-10 * max(abs(ao), 1.0):
+                continue
+            assert abs(ao) < 64.0, (K, m, a, ao)
+            assert abs(a - ao) <= 4 * eps * m / _var_trunc(ao, K), (K, m, a, ao)
+    for xmin in (2, 3, 16, 17, 18, 30, 100):
+        lx = math.log(xmin)
+        for d in list(10 ** rng.uniform(-12, 1.2, 25)):
+            m = lx + d
+            f = C.c_uint32(0)
+            a = hm.hm_mle_hz(m, xmin, C.byref(f))
+            ao, fo = orc.hz_mle(m, xmin)
+            if abs(a - ao) <= 1e-10 * ao:
+                continue
+            assert ao < 64.0, (xmin, m, a, ao)
+            assert abs(a - ao) <= 4 * eps * m / _var_cut(ao, xmin), (xmin, m, a, ao)

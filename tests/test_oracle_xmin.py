@@ -25,14 +25,41 @@ def _F_direct(a, xmin, t):
         return s / _Z(a, xmin)
 
 
-@pytest.mark.parametrize("a,xmin", [(1.5, 2), (2.5, 7), (3.3, 100), (1.8, 4000)])
+def _Zsum(a, q):
+    """zeta(a, q) by partial sums for a >= 10 (mpmath's own Hurwitz zeta is
+    not accurate at large a); the remainder after 6,000 terms is negligible."""
+    with mp.workdps(40):
+        return mp.fsum(mp.mpf(k) ** -mp.mpf(a) for k in range(q, q + 6000)) + \
+            mp.zeta(a, q + 6000)
+
+
+@pytest.mark.parametrize("a,xmin", [(1.5, 2), (2.5, 7), (3.3, 100), (1.8, 4000),
+                                    (40.0, 17), (25.0, 30), (12.0, 16)])
 def test_cdf_table_is_the_partial_sum_of_the_pmf(orc, a, xmin):
     T = orc.hz_cdf_table(a, xmin)
+    Z = _Zsum if a >= 10.0 else _Z
     for j in (1, 2, 3, 17, 200, 4096):
         want = float(_F_direct(a, xmin, xmin + j - 1)) if j <= 200 else \
-            float(1 - _Z(a, xmin + j) / _Z(a, xmin))
+            float(1 - Z(a, xmin + j) / Z(a, xmin))
         assert abs(T[j - 1] - want) < 2e-15, (a, xmin, j)
     assert np.all(np.diff(T) >= 0)
+
+
+@pytest.mark.parametrize("xmin", [2, 16, 17, 20])
+def test_mle_large_root_at_a_small_cutoff(orc, xmin):
+    """Samples piled at the cutoff have roots far above 2 (here 6 to 60):
+    the fitted exponent solves eq. (2) with partial sums at 40 digits, to
+    the FP64 rounding of mu."""
+    for extra in ([1, 1, 1], [1, 1, 2], [1] * 6 + [3]):
+        x = np.array([xmin] * 60 + [xmin + e for e in extra])
+        r = orc.hz_fit(x, xmin)
+        a = r["alpha_hat"]
+        assert not (r["flags"] & orc.FLAG_NOCONV) and a > 5.0, (xmin, extra, a)
+        with mp.workdps(40):
+            w = [(mp.mpf(k) ** -mp.mpf(a), mp.log(k)) for k in range(xmin, xmin + 6000)]
+            mu = mp.fsum(t * l for t, l in w) / mp.fsum(t for t, _ in w)
+        m = r["S"] / x.size
+        assert abs(float(mu) - m) <= 8 * 2.0 ** -53 * m, (xmin, extra, float(mu), m)
 
 
 def test_xmin_one_is_the_pure_law(orc):
