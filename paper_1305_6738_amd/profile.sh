@@ -5,10 +5,10 @@
 #      of its own, with a 256 MiB device-to-device copy first whose counters
 #      scale the readings to bytes.
 # The shipped tuning table is loaded so that no autotuning probe launches mix
-# into the statistics.  Output goes to $1 (default gpurun_out/profile).
+# into the statistics.  Output goes to $1 (default profile_out/ at the root).
 set -o pipefail
 ROOT="$(cd "$(dirname "$0")/.." && pwd)"
-OUT="${1:-$ROOT/gpurun_out/profile}"
+OUT="${1:-$ROOT/profile_out}"
 mkdir -p "$OUT"
 cd /tmp && export TMPDIR=/tmp
 ARGS="--steps 5 --warmup 2 --no-extras --no-cpu-baseline --tune $ROOT/paper_1305_6738_amd/tuning/mi355x.json --copy-probe-mib 256"
