@@ -115,6 +115,24 @@ def test_simulate_small_cells_all_forms(ctx, orc, form):
         lo += cell[2]
 
 
+@pytest.mark.parametrize("form", ["auto", "heavy"])
+def test_extreme_exponents(ctx, orc, form):
+    """The ends of the simulated range, every replicate against the oracle:
+    alpha = 1.01 and 1.05 (every replicate meets the 2^63 cap; values up to
+    9e18 in the overflow sort), and alpha = 8, 20, 64 (almost every replicate
+    all ones: the S := ln 2 rule), plus a long heavy-tailed replicate."""
+    cells = [(1.01, 20, 300, 3, 50), (1.05, 60, 300, 3, 51), (8.0, 10, 400, 3, 52),
+             (20.0, 100, 300, 3, 53), (64.0, 30, 200, 3, 54), (1.3, 5000, 40, 3, 55)]
+    say("extreme exponents", form)
+    g = run_cells(ctx, cells, form=form)
+    lo = 0
+    for cell in cells:
+        compare_cell(orc, g, lo, cell)
+        lo += cell[2]
+    assert np.all(g["flags"][:600] & 2)       # the cap at alpha = 1.01 and 1.05
+    assert np.sum(g["flags"][600:1300] & 1) > 600  # all-ones replicates at alpha = 8, 20
+
+
 def test_forms_and_launches_bit_identical(ctx):
     """Same replicate, same bits: lane / wave / heavy forms, plain vs batched
     launches and hipGraph replay all give identical outputs."""
