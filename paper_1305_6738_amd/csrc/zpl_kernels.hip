@@ -1793,6 +1793,7 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // the radix selection runs over all of D instead.  Both give the same element.
 // ---------------------------------------------------------------------------
 constexpr int kSelSample = 2048;
+constexpr int kSelUnroll = 8;
 static_assert(kHW % 256 == 0 && kHeavyHist % 256 == 0, "build_list reads 256 bins per step");
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
@@ -1827,13 +1828,15 @@ __device__ void block_bitonic_u64(uint64_t* a, int P) {
 struct SelLds {
   union {
     uint64_t sample[kSelSample];
-    uint32_t hist[2048];
+    uint32_t hist[kSelQ][2048];  // one per quantile group; the block-wide select uses [0]
   } u;
   uint64_t lo[kSelQ], hi[kSelQ];
   unsigned long long below[kSelQ];
   uint32_t nb[kSelQ];
   uint64_t prefix, mask;
   int64_t krem;
+  uint64_t gprefix[kSelQ], gmask[kSelQ];
+  int64_t gkrem[kSelQ];
 };
 
 // Exact radix selection (11-bit digits) of rank k of bits[0..R), block-wide.
@@ -1853,17 +1856,27 @@ __device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, i
     const int width = hi_bit + 1 < 11 ? hi_bit + 1 : 11;
     const int sh = hi_bit + 1 - width;
     const uint32_t dm = (1u << width) - 1u;
-    for (int b = tid; b < 2048; b += (int)blockDim.x) L.u.hist[b] = 0u;
+    for (int b = tid; b < 2048; b += (int)blockDim.x) L.u.hist[0][b] = 0u;
     __syncthreads();
     const uint64_t pre = L.prefix, msk = L.mask;
-    for (int64_t i = tid; i < R; i += blockDim.x) {
-      const uint64_t b = bits[i];
-      if ((b & msk) == pre) atomicAdd(&L.u.hist[(b >> sh) & dm], 1u);
+    const int64_t nt = (int64_t)blockDim.x;
+    for (int64_t i0 = 0; i0 < R; i0 += nt * kSelUnroll) {
+      uint64_t bv[kSelUnroll];
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const int64_t i = i0 + u * nt + tid;
+        bv[u] = i < R ? bits[i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const int64_t i = i0 + u * nt + tid;
+        if (i < R && (bv[u] & msk) == pre) atomicAdd(&L.u.hist[0][(bv[u] >> sh) & dm], 1u);
+      }
     }
     __syncthreads();
     if (wave == 0) {
       uint32_t sum = 0;
-      for (int t = 0; t < 32; ++t) sum += L.u.hist[lane * 32 + t];
+      for (int t = 0; t < 32; ++t) sum += L.u.hist[0][lane * 32 + t];
       const uint32_t incl = wave_incl_scan_u32(sum, lane);
       const int64_t kk0 = L.krem;
       const uint64_t hit = __ballot((int64_t)incl > kk0);
@@ -1871,8 +1884,8 @@ __device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, i
       if (lane == owner) {
         int64_t kk = kk0 - (int64_t)(incl - sum);
         int d = lane * 32;
-        while ((int64_t)L.u.hist[d] <= kk) {
-          kk -= L.u.hist[d];
+        while ((int64_t)L.u.hist[0][d] <= kk) {
+          kk -= L.u.hist[0][d];
           ++d;
         }
         L.krem = kk;
@@ -1883,6 +1896,86 @@ __device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, i
     __syncthreads();
   }
   return L.prefix;
+}
+
+// radix_select for up to kSelQ quantiles at once: group g (threads
+// 256g..256g+255 of the 1024-thread block) selects rank k[g] of its own
+// array a[g][0..n[g]), whose values share the bits above top[g] with
+// common[g]; groups with act[g] false idle.  Same digits, same result as
+// radix_select, with the quantiles' passes running side by side.  Every
+// barrier is reached by the whole block: the loop runs over the longest
+// digit sequence and finished groups idle through the rest.
+__device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ],
+                                    const int64_t (&n)[kSelQ], const int64_t (&k)[kSelQ],
+                                    const int (&top)[kSelQ], const uint64_t (&common)[kSelQ],
+                                    const bool (&act)[kSelQ], uint64_t (&res)[kSelQ]) {
+  static_assert(kSelQ * 256 == 1024, "one 256-thread group per quantile");
+  const int tid = (int)threadIdx.x, g = tid >> 8, gt = tid & 255, lane = tid & 63;
+  const bool scanner = ((tid >> 6) & 3) == 0;  // the group's first wave
+  if (gt == 0) {
+    const uint64_t m = top[g] >= 63 ? 0ull : (~0ull << (top[g] + 1));
+    L.gprefix[g] = common[g] & m;
+    L.gmask[g] = m;
+    L.gkrem[g] = k[g];
+  }
+  int maxtop = -1;
+#pragma unroll
+  for (int q = 0; q < kSelQ; ++q)
+    if (act[q] && top[q] > maxtop) maxtop = top[q];
+  __syncthreads();
+  uint32_t* hist = L.u.hist[g];
+  for (int p = 0; maxtop - 11 * p >= 0; ++p) {
+    const int hb = top[g] - 11 * p;
+    const bool on = act[g] && hb >= 0;
+    const int width = hb + 1 < 11 ? hb + 1 : 11;
+    const int sh = hb + 1 - width;
+    const uint32_t dm = on ? (1u << width) - 1u : 0u;
+    if (on)
+      for (int b = gt; b < 2048; b += 256) hist[b] = 0u;
+    __syncthreads();
+    if (on) {
+      const uint64_t pre = L.gprefix[g], msk = L.gmask[g];
+      const uint64_t* __restrict__ src = a[g];
+      const int64_t cnt = n[g];
+      for (int64_t i0 = 0; i0 < cnt; i0 += 256 * kSelUnroll) {
+        uint64_t bv[kSelUnroll];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t i = i0 + u * 256 + gt;
+          bv[u] = i < cnt ? src[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          const int64_t i = i0 + u * 256 + gt;
+          if (i < cnt && (bv[u] & msk) == pre) atomicAdd(&hist[(bv[u] >> sh) & dm], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    if (on && scanner) {
+      uint32_t sum = 0;
+      for (int t = 0; t < 32; ++t) sum += hist[lane * 32 + t];
+      const uint32_t incl = wave_incl_scan_u32(sum, lane);
+      const int64_t kk0 = L.gkrem[g];
+      const uint64_t hit = __ballot((int64_t)incl > kk0);
+      const int owner = __ffsll((long long)hit) - 1;
+      if (lane == owner) {
+        int64_t kk = kk0 - (int64_t)(incl - sum);
+        int d = lane * 32;
+        while ((int64_t)hist[d] <= kk) {
+          kk -= hist[d];
+          ++d;
+        }
+        L.gkrem[g] = kk;
+        L.gprefix[g] = L.gprefix[g] | ((uint64_t)d << sh);
+        L.gmask[g] = L.gmask[g] | ((uint64_t)dm << sh);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kSelQ; ++q) res[q] = L.gprefix[q];
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ D,
@@ -1928,24 +2021,34 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ D,
       below[qq] = 0u;
     }
     const int lane = tid & 63;
-    for (int64_t i0 = 0; i0 < R; i0 += 1024) {
-      const int64_t i = i0 + tid;
-      const bool valid = i < R;
-      const uint64_t b = valid ? bits[i] : 0ull;
+    // kSelUnroll independent loads per thread in flight per step: the pass
+    // is bound by memory latency, not bandwidth (one workgroup per cell)
+    for (int64_t i0 = 0; i0 < R; i0 += 1024 * kSelUnroll) {
+      uint64_t bv[kSelUnroll];
 #pragma unroll
-      for (int qq = 0; qq < kSelQ; ++qq) {
-        if (qq < nq) {
-          const bool bl = valid && b < lo[qq];
-          const bool in = valid && !bl && b <= hi[qq];
-          below[qq] += bl ? 1u : 0u;
-          const uint64_t m = __ballot(in);
-          if (m) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&L.nb[qq], (uint32_t)__popcll(m));
-            base = (uint32_t)__shfl((int)base, 0, 64);
-            if (in) {
-              const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
-              if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const int64_t i = i0 + u * 1024 + tid;
+        bv[u] = i < R ? bits[i] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const bool valid = i0 + u * 1024 + tid < R;
+        const uint64_t b = bv[u];
+#pragma unroll
+        for (int qq = 0; qq < kSelQ; ++qq) {
+          if (qq < nq) {
+            const bool bl = valid && b < lo[qq];
+            const bool in = valid && !bl && b <= hi[qq];
+            below[qq] += bl ? 1u : 0u;
+            const uint64_t m = __ballot(in);
+            if (m) {
+              uint32_t base = 0;
+              if (lane == 0) base = atomicAdd(&L.nb[qq], (uint32_t)__popcll(m));
+              base = (uint32_t)__shfl((int)base, 0, 64);
+              if (in) {
+                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
+                if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
+              }
             }
           }
         }
@@ -1960,24 +2063,53 @@ __global__ __launch_bounds__(1024) void k_select(const double* __restrict__ D,
     }
     __threadfence_block();
     __syncthreads();
-    // 4. per quantile: select within the gathered bracket, or over all of D
-    for (int qq = 0; qq < nq; ++qq) {
-      const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + qq]) / qden[q0 + qq]);
-      const int64_t lo_rank = (int64_t)L.below[qq];
-      const int64_t nin = (int64_t)L.nb[qq];
-      uint64_t res;
-      if (k >= lo_rank && k < lo_rank + nin && L.lo[qq] == L.hi[qq])
-        res = L.lo[qq];  // every value in the bracket equals lo (an atom of D)
-      else if (k >= lo_rank && k < lo_rank + nin && nin <= gcap) {
-        const uint64_t x = L.lo[qq] ^ L.hi[qq];
-        const int top = x ? 63 - __clzll((long long)x) : 0;
-        res = radix_select(L, G + qq * gcap, nin, k - lo_rank, top, L.lo[qq]);
-      } else {
-        res = radix_select(L, bits, R, k, 63, 0ull);
+    // 4. per quantile: select within the gathered bracket (the quantiles side
+    //    by side), or over all of D when the bracket missed
+    const uint64_t* arr[kSelQ];
+    int64_t cnt[kSelQ], rk[kSelQ];
+    int tops[kSelQ];
+    uint64_t com[kSelQ], res[kSelQ];
+    bool grp[kSelQ], full[kSelQ];
+#pragma unroll
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      arr[qq] = G + qq * gcap;
+      cnt[qq] = 0;
+      rk[qq] = 0;
+      tops[qq] = 0;
+      com[qq] = 0ull;
+      res[qq] = 0ull;
+      grp[qq] = false;
+      full[qq] = false;
+      if (qq < nq) {
+        const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + qq]) / qden[q0 + qq]);
+        const int64_t lo_rank = (int64_t)L.below[qq];
+        const int64_t nin = (int64_t)L.nb[qq];
+        rk[qq] = k;
+        if (k >= lo_rank && k < lo_rank + nin && L.lo[qq] == L.hi[qq]) {
+          res[qq] = L.lo[qq];  // every value in the bracket equals lo (an atom of D)
+        } else if (k >= lo_rank && k < lo_rank + nin && nin <= gcap) {
+          const uint64_t x = L.lo[qq] ^ L.hi[qq];
+          tops[qq] = x ? 63 - __clzll((long long)x) : 0;
+          com[qq] = L.lo[qq];
+          cnt[qq] = nin;
+          rk[qq] = k - lo_rank;
+          grp[qq] = true;
+        } else {
+          full[qq] = true;
+        }
       }
-      if (tid == 0) qout[cell * n_q + q0 + qq] = __longlong_as_double((long long)res);
-      __syncthreads();
     }
+    uint64_t gres[kSelQ];
+    radix_select_groups(L, arr, cnt, rk, tops, com, grp, gres);
+#pragma unroll
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      if (grp[qq]) res[qq] = gres[qq];
+      if (full[qq]) res[qq] = radix_select(L, bits, R, rk[qq], 63, 0ull);
+    }
+    if (tid == 0)
+      for (int qq = 0; qq < nq; ++qq)
+        qout[cell * n_q + q0 + qq] = __longlong_as_double((long long)res[qq]);
+    __syncthreads();
   }
 }
 
