@@ -514,6 +514,7 @@ struct Launch {
   int heavy_grid = 0;
   int64_t hstride = 0;
   int64_t gcap = 0;
+  int64_t maxR = 1;
 };
 
 // Grows every scratch buffer the plan needs.
@@ -554,7 +555,11 @@ zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L
   int64_t maxR = 1;
   for (const DevCell& d : P.cells) maxR = std::max(maxR, d.R);
   L.gcap = std::min<int64_t>(kSelGather, maxR * 3 / 20 + 1024);
-  if (n_q > 0) ZPL_TRY(ensure(c, c->gather, sizeof(uint64_t) * (size_t)nc * kSelQ * L.gcap));
+  L.maxR = maxR;
+  // gather areas, then 32 bytes of selection state per (cell, quantile)
+  if (n_q > 0)
+    ZPL_TRY(ensure(c, c->gather, sizeof(uint64_t) * (size_t)nc * kSelQ * L.gcap +
+                                     (size_t)32 * nc * kSelQ));
   return ZPL_OK;
 }
 
@@ -603,7 +608,7 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
   if (n_q > 0 && Dsel)
     HIP_TRY(launch_select(Dsel, dcells, nc, n_q, (const uint32_t*)c->qnum.p,
                           (const uint32_t*)c->qden.p, (double*)c->qout.p,
-                          (uint64_t*)c->gather.p, L.gcap, s));
+                          (uint64_t*)c->gather.p, L.gcap, L.maxR, c->n_cu, s));
   HIP_TRY(mark(4));
   return ZPL_OK;
 }
@@ -1181,7 +1186,7 @@ zpl_status zpl_critical_table(zpl_ctx* c, const double* gammas, int32_t n_gamma,
   // groups of whole runs whose D values, selection scratch and tables fit in
   // a quarter of the budget (at least one run per group)
   const int64_t per_run = replicates * 8 +
-                          (int64_t)kSelQ * std::min<int64_t>(kSelGather, replicates * 3 / 20 + 1024) * 8 +
+                          (int64_t)kSelQ * (std::min<int64_t>(kSelGather, replicates * 3 / 20 + 1024) * 8 + 32) +
                           (int64_t)kH * 8 + (int64_t)(kGuide + 1) * 2;
   const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((int64_t)(c->budget / 4) / per_run, 4096));
   std::vector<double> q((size_t)n_runs * n_q);

@@ -1780,15 +1780,18 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Order statistics per cell: the element of rank k = floor(R num/den) in the
 // ascending D values (the annex's index rule).  D >= 0, so comparing the FP64
-// bit patterns as unsigned integers orders the values.  One workgroup of
-// 1024 threads per cell, up to kSelQ quantiles at a time:
-//   1. a sample of kSelSample values at fixed positions is sorted in LDS;
-//   2. each quantile takes the sample values 5 standard deviations of the
-//      sample rank around its expected position as a bracket [lo, hi];
-//   3. one pass over D counts the values below each bracket and gathers the
-//      values inside it into global scratch;
-//   4. the rank k - below is selected exactly among the gathered values by
-//      radix selection (11-bit digits).
+// bit patterns as unsigned integers orders the values.  Up to kSelQ quantiles
+// at a time, in three launches:
+//   1. k_sel_bracket (a workgroup per cell): a sample of kSelSample values at
+//      fixed positions is sorted in LDS, and each quantile takes the sample
+//      values 5 standard deviations of the sample rank around its expected
+//      position as a bracket [lo, hi];
+//   2. k_sel_gather (many workgroups per cell, each a slice of D): counts the
+//      values below each bracket and gathers the values inside it into global
+//      scratch, through per-(cell, quantile) counters;
+//   3. k_sel_finish (a workgroup per cell): the rank k - below is selected
+//      exactly among the gathered values by radix selection (11-bit digits),
+//      the quantiles side by side.
 // If rank k falls outside its bracket, or the bracket overflows its scratch,
 // the radix selection runs over all of D instead.  Both give the same element.
 // ---------------------------------------------------------------------------
@@ -1826,13 +1829,9 @@ __device__ void block_bitonic_u64(uint64_t* a, int P) {
 }
 
 struct SelLds {
-  union {
-    uint64_t sample[kSelSample];
+  struct {
     uint32_t hist[kSelQ][2048];  // one per quantile group; the block-wide select uses [0]
   } u;
-  uint64_t lo[kSelQ], hi[kSelQ];
-  unsigned long long below[kSelQ];
-  uint32_t nb[kSelQ];
   uint64_t prefix, mask;
   int64_t krem;
   uint64_t gprefix[kSelQ], gmask[kSelQ];
@@ -1912,21 +1911,36 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
   static_assert(kSelQ * 256 == 1024, "one 256-thread group per quantile");
   const int tid = (int)threadIdx.x, g = tid >> 8, gt = tid & 255, lane = tid & 63;
   const bool scanner = ((tid >> 6) & 3) == 0;  // the group's first wave
-  if (gt == 0) {
-    const uint64_t m = top[g] >= 63 ? 0ull : (~0ull << (top[g] + 1));
-    L.gprefix[g] = common[g] & m;
-    L.gmask[g] = m;
-    L.gkrem[g] = k[g];
-  }
+  // this group's parameters (static indices: the arrays stay in registers)
+  const uint64_t* src = nullptr;
+  int64_t cnt = 0, kg = 0;
+  int topg = 0;
+  uint64_t comg = 0ull;
+  bool actg = false;
   int maxtop = -1;
 #pragma unroll
-  for (int q = 0; q < kSelQ; ++q)
+  for (int q = 0; q < kSelQ; ++q) {
+    if (q == g) {
+      src = a[q];
+      cnt = n[q];
+      kg = k[q];
+      topg = top[q];
+      comg = common[q];
+      actg = act[q];
+    }
     if (act[q] && top[q] > maxtop) maxtop = top[q];
+  }
+  if (gt == 0) {
+    const uint64_t m = topg >= 63 ? 0ull : (~0ull << (topg + 1));
+    L.gprefix[g] = comg & m;
+    L.gmask[g] = m;
+    L.gkrem[g] = kg;
+  }
   __syncthreads();
   uint32_t* hist = L.u.hist[g];
   for (int p = 0; maxtop - 11 * p >= 0; ++p) {
-    const int hb = top[g] - 11 * p;
-    const bool on = act[g] && hb >= 0;
+    const int hb = topg - 11 * p;
+    const bool on = actg && hb >= 0;
     const int width = hb + 1 < 11 ? hb + 1 : 11;
     const int sh = hb + 1 - width;
     const uint32_t dm = on ? (1u << width) - 1u : 0u;
@@ -1935,8 +1949,6 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
     __syncthreads();
     if (on) {
       const uint64_t pre = L.gprefix[g], msk = L.gmask[g];
-      const uint64_t* __restrict__ src = a[g];
-      const int64_t cnt = n[g];
       for (int64_t i0 = 0; i0 < cnt; i0 += 256 * kSelUnroll) {
         uint64_t bv[kSelUnroll];
 #pragma unroll
@@ -1978,138 +1990,174 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
   __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ D,
-                                                const DevCell* __restrict__ cells, int n_q,
-                                                const uint32_t* __restrict__ qnum,
-                                                const uint32_t* __restrict__ qden,
-                                                double* __restrict__ qout,
-                                                uint64_t* __restrict__ gather, int64_t gcap) {
-  __shared__ SelLds L;
+// Per (cell, quantile) state between the three launches.
+struct SelMeta {
+  uint64_t lo, hi;           // bracket (FP64 bit patterns)
+  unsigned long long below;  // values below lo
+  uint32_t nb;               // values gathered in [lo, hi]
+  uint32_t pad;
+};
+
+__global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__ D,
+                                                     const DevCell* __restrict__ cells, int q0,
+                                                     int nq, const uint32_t* __restrict__ qnum,
+                                                     const uint32_t* __restrict__ qden,
+                                                     SelMeta* __restrict__ meta) {
+  __shared__ uint64_t sample[kSelSample];
   const int cell = (int)blockIdx.x;
   const int tid = (int)threadIdx.x;
   const DevCell c = cells[cell];
   const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
-  uint64_t* G = gather + (int64_t)cell * kSelQ * gcap;
   const int64_t R = c.R;
-  for (int q0 = 0; q0 < n_q; q0 += kSelQ) {
-    const int nq = (n_q - q0) < kSelQ ? (n_q - q0) : kSelQ;
-    // 1. sorted sample
-    for (int t = tid; t < kSelSample; t += 1024)
-      L.u.sample[t] = bits[(int64_t)(((uint64_t)t * (uint64_t)R) / kSelSample)];
-    __syncthreads();
-    block_bitonic_u64(L.u.sample, kSelSample);
-    // 2. brackets: +-(5 sd + 8) sample positions around the expected one
-    if (tid < nq) {
-      const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
-      const double qf = (double)k / (double)R;
-      const int64_t p = (int64_t)(qf * kSelSample);
-      const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
-      const int64_t a = p - dl, b = p + dl;
-      L.lo[tid] = a <= 0 ? 0ull : L.u.sample[a];
-      L.hi[tid] = b >= kSelSample - 1 ? ~0ull : L.u.sample[b];
-      L.below[tid] = 0ull;
-      L.nb[tid] = 0u;
+  for (int t = tid; t < kSelSample; t += 1024)
+    sample[t] = bits[(int64_t)(((uint64_t)t * (uint64_t)R) / kSelSample)];
+  __syncthreads();
+  block_bitonic_u64(sample, kSelSample);
+  if (tid < nq) {
+    const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
+    const double qf = (double)k / (double)R;
+    const int64_t p = (int64_t)(qf * kSelSample);
+    const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
+    const int64_t a = p - dl, b = p + dl;
+    SelMeta m;
+    m.lo = a <= 0 ? 0ull : sample[a];
+    m.hi = b >= kSelSample - 1 ? ~0ull : sample[b];
+    m.below = 0ull;
+    m.nb = 0u;
+    m.pad = 0u;
+    meta[(size_t)cell * kSelQ + tid] = m;
+  }
+}
+
+// Slice `slice` of cell `cell` (blocks laid out cell-major, `slices` per
+// cell): values below each bracket are counted, values inside are appended
+// to the quantile's gather area at slots from its global counter.
+__global__ __launch_bounds__(256) void k_sel_gather(const double* __restrict__ D,
+                                                   const DevCell* __restrict__ cells, int nq,
+                                                   int slices, int64_t chunk,
+                                                   SelMeta* __restrict__ meta,
+                                                   uint64_t* __restrict__ gather, int64_t gcap) {
+  const int cell = (int)(blockIdx.x / (unsigned)slices);
+  const int slice = (int)(blockIdx.x % (unsigned)slices);
+  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const DevCell c = cells[cell];
+  const int64_t R = c.R;
+  const int64_t ib = (int64_t)slice * chunk;
+  if (ib >= R) return;  // the whole block
+  const int64_t ie = ib + chunk < R ? ib + chunk : R;
+  const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
+  SelMeta* M = meta + (size_t)cell * kSelQ;
+  uint64_t* G = gather + (size_t)cell * kSelQ * gcap;
+  uint64_t lo[kSelQ], hi[kSelQ];
+  uint32_t below[kSelQ];
+#pragma unroll
+  for (int qq = 0; qq < kSelQ; ++qq) {
+    lo[qq] = qq < nq ? M[qq].lo : 0ull;
+    hi[qq] = qq < nq ? M[qq].hi : 0ull;
+    below[qq] = 0u;
+  }
+  for (int64_t i0 = ib; i0 < ie; i0 += 256 * kSelUnroll) {
+    uint64_t bv[kSelUnroll];
+#pragma unroll
+    for (int u = 0; u < kSelUnroll; ++u) {
+      const int64_t i = i0 + u * 256 + tid;
+      bv[u] = i < ie ? bits[i] : 0ull;
     }
-    __syncthreads();
-    // 3. count below, gather inside
-    uint64_t lo[kSelQ], hi[kSelQ];
-    uint32_t below[kSelQ];
 #pragma unroll
-    for (int qq = 0; qq < kSelQ; ++qq) {
-      lo[qq] = L.lo[qq];
-      hi[qq] = L.hi[qq];
-      below[qq] = 0u;
-    }
-    const int lane = tid & 63;
-    // kSelUnroll independent loads per thread in flight per step: the pass
-    // is bound by memory latency, not bandwidth (one workgroup per cell)
-    for (int64_t i0 = 0; i0 < R; i0 += 1024 * kSelUnroll) {
-      uint64_t bv[kSelUnroll];
+    for (int u = 0; u < kSelUnroll; ++u) {
+      const bool valid = i0 + u * 256 + tid < ie;
+      const uint64_t b = bv[u];
 #pragma unroll
-      for (int u = 0; u < kSelUnroll; ++u) {
-        const int64_t i = i0 + u * 1024 + tid;
-        bv[u] = i < R ? bits[i] : 0ull;
-      }
-#pragma unroll
-      for (int u = 0; u < kSelUnroll; ++u) {
-        const bool valid = i0 + u * 1024 + tid < R;
-        const uint64_t b = bv[u];
-#pragma unroll
-        for (int qq = 0; qq < kSelQ; ++qq) {
-          if (qq < nq) {
-            const bool bl = valid && b < lo[qq];
-            const bool in = valid && !bl && b <= hi[qq];
-            below[qq] += bl ? 1u : 0u;
-            const uint64_t m = __ballot(in);
-            if (m) {
-              uint32_t base = 0;
-              if (lane == 0) base = atomicAdd(&L.nb[qq], (uint32_t)__popcll(m));
-              base = (uint32_t)__shfl((int)base, 0, 64);
-              if (in) {
-                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
-                if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
-              }
+      for (int qq = 0; qq < kSelQ; ++qq) {
+        if (qq < nq) {
+          const bool bl = valid && b < lo[qq];
+          const bool in = valid && !bl && b <= hi[qq];
+          below[qq] += bl ? 1u : 0u;
+          const uint64_t m = __ballot(in);
+          if (m) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&M[qq].nb, (uint32_t)__popcll(m));
+            base = (uint32_t)__shfl((int)base, 0, 64);
+            if (in) {
+              const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
+              if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
             }
           }
         }
       }
     }
+  }
 #pragma unroll
-    for (int qq = 0; qq < kSelQ; ++qq) {
-      if (qq < nq) {
-        const uint32_t w = wave_sum_u32(below[qq]);
-        if ((tid & 63) == 0 && w) atomicAdd(&L.below[qq], (unsigned long long)w);
+  for (int qq = 0; qq < kSelQ; ++qq) {
+    if (qq < nq) {
+      const uint32_t w = wave_sum_u32(below[qq]);
+      if (lane == 0 && w) atomicAdd(&M[qq].below, (unsigned long long)w);
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_sel_finish(const double* __restrict__ D,
+                                                    const DevCell* __restrict__ cells, int q0,
+                                                    int nq, int n_q,
+                                                    const uint32_t* __restrict__ qnum,
+                                                    const uint32_t* __restrict__ qden,
+                                                    const SelMeta* __restrict__ meta,
+                                                    double* __restrict__ qout,
+                                                    uint64_t* __restrict__ gather, int64_t gcap) {
+  __shared__ SelLds L;
+  const int cell = (int)blockIdx.x;
+  const int tid = (int)threadIdx.x;
+  const DevCell c = cells[cell];
+  const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
+  const uint64_t* G = gather + (size_t)cell * kSelQ * gcap;
+  const SelMeta* M = meta + (size_t)cell * kSelQ;
+  const int64_t R = c.R;
+  const uint64_t* arr[kSelQ];
+  int64_t cnt[kSelQ], rk[kSelQ];
+  int tops[kSelQ];
+  uint64_t com[kSelQ], res[kSelQ];
+  bool grp[kSelQ], full[kSelQ];
+#pragma unroll
+  for (int qq = 0; qq < kSelQ; ++qq) {
+    arr[qq] = G + qq * gcap;
+    cnt[qq] = 0;
+    rk[qq] = 0;
+    tops[qq] = 0;
+    com[qq] = 0ull;
+    res[qq] = 0ull;
+    grp[qq] = false;
+    full[qq] = false;
+    if (qq < nq) {
+      const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + qq]) / qden[q0 + qq]);
+      const SelMeta m = M[qq];
+      const int64_t lo_rank = (int64_t)m.below;
+      const int64_t nin = (int64_t)m.nb;
+      rk[qq] = k;
+      if (k >= lo_rank && k < lo_rank + nin && m.lo == m.hi) {
+        res[qq] = m.lo;  // every value in the bracket equals lo (an atom of D)
+      } else if (k >= lo_rank && k < lo_rank + nin && nin <= gcap) {
+        const uint64_t x = m.lo ^ m.hi;
+        tops[qq] = x ? 63 - __clzll((long long)x) : 0;
+        com[qq] = m.lo;
+        cnt[qq] = nin;
+        rk[qq] = k - lo_rank;
+        grp[qq] = true;
+      } else {
+        full[qq] = true;
       }
     }
-    __threadfence_block();
-    __syncthreads();
-    // 4. per quantile: select within the gathered bracket (the quantiles side
-    //    by side), or over all of D when the bracket missed
-    const uint64_t* arr[kSelQ];
-    int64_t cnt[kSelQ], rk[kSelQ];
-    int tops[kSelQ];
-    uint64_t com[kSelQ], res[kSelQ];
-    bool grp[kSelQ], full[kSelQ];
+  }
+  uint64_t gres[kSelQ];
+  radix_select_groups(L, arr, cnt, rk, tops, com, grp, gres);
 #pragma unroll
-    for (int qq = 0; qq < kSelQ; ++qq) {
-      arr[qq] = G + qq * gcap;
-      cnt[qq] = 0;
-      rk[qq] = 0;
-      tops[qq] = 0;
-      com[qq] = 0ull;
-      res[qq] = 0ull;
-      grp[qq] = false;
-      full[qq] = false;
-      if (qq < nq) {
-        const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + qq]) / qden[q0 + qq]);
-        const int64_t lo_rank = (int64_t)L.below[qq];
-        const int64_t nin = (int64_t)L.nb[qq];
-        rk[qq] = k;
-        if (k >= lo_rank && k < lo_rank + nin && L.lo[qq] == L.hi[qq]) {
-          res[qq] = L.lo[qq];  // every value in the bracket equals lo (an atom of D)
-        } else if (k >= lo_rank && k < lo_rank + nin && nin <= gcap) {
-          const uint64_t x = L.lo[qq] ^ L.hi[qq];
-          tops[qq] = x ? 63 - __clzll((long long)x) : 0;
-          com[qq] = L.lo[qq];
-          cnt[qq] = nin;
-          rk[qq] = k - lo_rank;
-          grp[qq] = true;
-        } else {
-          full[qq] = true;
-        }
-      }
-    }
-    uint64_t gres[kSelQ];
-    radix_select_groups(L, arr, cnt, rk, tops, com, grp, gres);
+  for (int qq = 0; qq < kSelQ; ++qq) {
+    if (grp[qq]) res[qq] = gres[qq];
+    if (full[qq]) res[qq] = radix_select(L, bits, R, rk[qq], 63, 0ull);
+  }
+  if (tid == 0) {
 #pragma unroll
-    for (int qq = 0; qq < kSelQ; ++qq) {
-      if (grp[qq]) res[qq] = gres[qq];
-      if (full[qq]) res[qq] = radix_select(L, bits, R, rk[qq], 63, 0ull);
-    }
-    if (tid == 0)
-      for (int qq = 0; qq < nq; ++qq)
-        qout[cell * n_q + q0 + qq] = __longlong_as_double((long long)res[qq]);
-    __syncthreads();
+    for (int qq = 0; qq < kSelQ; ++qq)
+      if (qq < nq) qout[cell * n_q + q0 + qq] = __longlong_as_double((long long)res[qq]);
   }
 }
 
@@ -2258,10 +2306,33 @@ hipError_t launch_fit_scan(int grid, const int64_t* x, int64_t n, const int64_t*
 
 hipError_t launch_select(const double* D, const DevCell* cells, int n_cells, int n_q,
                          const uint32_t* qnum, const uint32_t* qden, double* qout,
-                         uint64_t* gather, int64_t gcap, hipStream_t s) {
+                         uint64_t* gather, int64_t gcap, int64_t maxR, int n_cu, hipStream_t s) {
   if (n_cells <= 0 || n_q <= 0) return hipSuccess;
-  k_select<<<n_cells, 1024, 0, s>>>(D, cells, n_q, qnum, qden, qout, gather, gcap);
-  return hipGetLastError();
+  // the per-(cell, quantile) state follows the gather areas
+  SelMeta* meta = reinterpret_cast<SelMeta*>(gather + (size_t)n_cells * kSelQ * gcap);
+  // slices of at least 2,048 values, about two workgroups per compute unit
+  const int64_t unit = 256 * kSelUnroll;
+  int64_t slices = (2 * (int64_t)n_cu + n_cells - 1) / n_cells;
+  const int64_t most = (maxR + unit - 1) / unit;
+  if (slices > most) slices = most;
+  if (slices < 1) slices = 1;
+  int64_t chunk = (maxR + slices - 1) / slices;
+  chunk = (chunk + unit - 1) / unit * unit;
+  for (int q0 = 0; q0 < n_q; q0 += kSelQ) {
+    const int nq = (n_q - q0) < kSelQ ? (n_q - q0) : kSelQ;
+    k_sel_bracket<<<n_cells, 1024, 0, s>>>(D, cells, q0, nq, qnum, qden, meta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sel_gather<<<(unsigned)(n_cells * slices), 256, 0, s>>>(D, cells, nq, (int)slices, chunk,
+                                                              meta, gather, gcap);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_sel_finish<<<n_cells, 1024, 0, s>>>(D, cells, q0, nq, n_q, qnum, qden, meta, qout, gather,
+                                          gcap);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_count_ge(const double* Db, int64_t B, const double* Dobs,

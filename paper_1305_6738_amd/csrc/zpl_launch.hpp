@@ -31,9 +31,11 @@ hipError_t launch_fit_scan(int grid, const int64_t* x, int64_t n, const int64_t*
                            int n_cand, const double* ln, int64_t* scratch, int64_t stride,
                            double* ahat, double* D, int64_t* ntail, uint32_t* flags,
                            uint32_t* status, hipStream_t s);
+// gather: n_cells * kSelQ * gcap values, then n_cells * kSelQ * 32 bytes of
+// per-(cell, quantile) state; maxR bounds every cell's R.
 hipError_t launch_select(const double* D, const DevCell* cells, int n_cells, int n_q,
                          const uint32_t* qnum, const uint32_t* qden, double* qout,
-                         uint64_t* gather, int64_t gcap, hipStream_t s);
+                         uint64_t* gather, int64_t gcap, int64_t maxR, int n_cu, hipStream_t s);
 hipError_t launch_count_ge(const double* Db, int64_t B, const double* Dobs,
                            unsigned long long* count, hipStream_t s);
 hipError_t launch_count_cells(const double* D, const DevCell* cells, int n_cells,

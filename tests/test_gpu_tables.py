@@ -123,7 +123,7 @@ def test_table_split_by_the_memory_budget_is_bit_identical(ctx):
     equal those of one group (the default 64 GiB context)."""
     from paper_1305_6738_amd import Context
     R, budget = 50000, 2 << 30
-    per_run = R * 8 + 4 * min(32768, R * 3 // 20 + 1024) * 8 + 4096 * 8 + 3585 * 2
+    per_run = R * 8 + 4 * (min(32768, R * 3 // 20 + 1024) * 8 + 32) + 4096 * 8 + 3585 * 2
     gammas, ns, seeds = [1.75, 3.0], [10, 20], 250
     assert len(gammas) * len(ns) * seeds > (budget // 4) // per_run  # at least two groups
     say("table split by budget")
