@@ -457,9 +457,14 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
     if (m != kModeHeavy) P.lw_R += z.replicates;
   }
   // units: kBlock replicates (one per lane, or 64 per wave) for lane/wave
-  // cells, 8 replicates (2 per wave) for heavy cells; weights for the
-  // longest-first order come from the tuning table when there is one (the
-  // truncated law: draws plus its K-term sums, see trunc_cost)
+  // cells, 8 replicates (2 per wave) for heavy cells.  The longest-first
+  // order weighs a unit by how long it occupies its workgroup: per-replicate
+  // cost (from the tuning table when there is one; the truncated law: draws
+  // plus its K-term sums, see trunc_cost) times the replicates its busiest
+  // wave runs one after another -- min(count, 64) in the wave form, one per
+  // lane (64 in these units) in the lane form.  Weighing by count instead
+  // sent each wave-form cell's last, partial unit to the end of the queue,
+  // where it ran as long as a full one on an otherwise idle device.
   std::vector<std::pair<double, Unit>> tmp;
   for (int i = 0; i < n_cells; ++i) {
     const DevCell& d = P.cells[i];
@@ -477,7 +482,8 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
       if (d.mode == kModeHeavy)
         P.hunits.push_back(u);
       else
-        tmp.push_back({w * u.count, u});
+        tmp.push_back({w * (d.mode == kModeLane ? 64.0 : (double)std::min<int32_t>(u.count, 64)),
+                       u});
     }
   }
   // longest units first; ties by cell so a workgroup tends to keep its table
