@@ -125,6 +125,23 @@ def test_no_root_at_small_K(ctx, orc, form):
     assert r["status"] == -4 and r["alpha_hat"] == -64.0
 
 
+def test_large_support_in_the_heavy_form(ctx, orc):
+    """K = 3000 and 4096 with exponents at or below 0.25: most values lie
+    above the heavy form's 1,024-bin histogram, so the overflow (thousands
+    of values) takes the global sort before the K-term finish.  Every
+    replicate against the oracle."""
+    cells = [(0.25, 3000, 40, 5, 60, 4096), (0.0, 5000, 30, 5, 61, 4096),
+             (-0.5, 2000, 30, 5, 62, 3000)]
+    from paper_1305_6738_amd import plan_forms
+    assert plan_forms(cells) == ["heavy"] * 3
+    say("large support, heavy form")
+    g = run_cells(ctx, cells)
+    lo = 0
+    for cell in cells:
+        compare(orc, g, lo, cell)
+        lo += cell[2]
+
+
 def test_mixed_with_pure_cells_bit_identical(ctx):
     pure = [(2.5, 100, 400, 1, 0, 0), (1.75, 50, 300, 1, 1, 0)]
     trunc = [(1.0, 100, 400, 1, 2, 20), (0.5, 200, 300, 1, 3, 1000)]
