@@ -110,12 +110,23 @@ static double em_coef(int i /* 1-based */) {
   return bern_num[i - 1] / (bern_den[i - 1] * fact);
 }
 
-void orc_hurwitz3(double s, double q, double out[3]) {
+/* zeta(s, q) and its first two s-derivatives, each multiplied by r^s (r > 0):
+ * every power x^-s is taken as (x/r)^-s = exp(-s log1p((x - r)/r)), while the
+ * logarithms ln x the derivatives bring down stay as they are.  The factor r^s
+ * is common to all three and cancels in every ratio the method uses (the
+ * likelihood equation (2) and the CDF of eq. (1)); with r = xmin it keeps the
+ * sums representable, where x^-s alone underflows for s ln x > 708.  r = 1
+ * gives the plain values. */
+static double pow_rel(double x, double r, double s) {
+  return r == 1.0 ? pow(x, -s) : exp(-s * log1p((x - r) / r));
+}
+
+void orc_hurwitz3_scaled(double s, double q, double r, double out[3]) {
   const double a = q + (double)ORC_EM_N;
   const double L = log(a);
   const double sm1 = s - 1.0;
-  const double a1s = pow(a, 1.0 - s); /* a^(1-s) */
-  const double as = pow(a, -s);        /* a^(-s)  */
+  const double as = pow_rel(a, r, s);                             /* (a/r)^(-s)  */
+  const double a1s = r == 1.0 ? pow(a, 1.0 - s) : a * as;         /* a^(1-s) r^s */
   double z0 = 0.0, z1 = 0.0, z2 = 0.0;
 
   /* Bernoulli correction terms, smallest first. */
@@ -159,7 +170,7 @@ void orc_hurwitz3(double s, double q, double out[3]) {
   for (int j = ORC_EM_N - 1; j >= 0; --j) {
     double x = q + (double)j;
     double lx = log(x);
-    double t = pow(x, -s);
+    double t = pow_rel(x, r, s);
     z0 += t;
     z1 += -lx * t;
     z2 += lx * lx * t;
@@ -169,11 +180,20 @@ void orc_hurwitz3(double s, double q, double out[3]) {
   out[2] = z2;
 }
 
+void orc_hurwitz3(double s, double q, double out[3]) { orc_hurwitz3_scaled(s, q, 1.0, out); }
+
 void orc_zeta3(double s, double out[3]) { orc_hurwitz3(s, 1.0, out); }
 
 static double hurwitz0(double s, double q) {
   double z[3];
   orc_hurwitz3(s, q, z);
+  return z[0];
+}
+
+/* zeta(s, q) r^s (see orc_hurwitz3_scaled). */
+static double hurwitz0_rel(double s, double q, double r) {
+  double z[3];
+  orc_hurwitz3_scaled(s, q, r, z);
   return z[0];
 }
 
@@ -765,9 +785,10 @@ int orc_tz_simulate(double g, int K, int64_t n, uint64_t seed, uint32_t stream, 
 /* law, where xmin = 1).  xmin = 1 is the pure law and uses its functions.   */
 /* ------------------------------------------------------------------------ */
 void orc_hz_cdf_table(double alpha, int64_t xmin, double *T) {
-  const double z = hurwitz0(alpha, (double)xmin);
+  const double r = (double)xmin; /* both sums scaled by xmin^alpha */
+  const double z = hurwitz0_rel(alpha, r, r);
   for (int j = 1; j <= ORC_TABLE_H; ++j)
-    T[j - 1] = 1.0 - hurwitz0(alpha, (double)(xmin + j)) / z;
+    T[j - 1] = 1.0 - hurwitz0_rel(alpha, (double)(xmin + j), r) / z;
 }
 
 /* Tail of the law with cutoff: k >= m = xmin + H, the same floored-Pareto   */
@@ -827,7 +848,7 @@ double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
   double lo = 1.0 + 0x1p-20, hi = 64.0;
   {
     double z[3];
-    orc_hurwitz3(hi, q, z);
+    orc_hurwitz3_scaled(hi, q, q, z); /* scaled by q^s: q^-64 underflows from q of about 6.5e4 */
     if (!(m > -z[1] / z[0])) { /* m at or below mu(64): the root is above 64 */
       *flags |= ORC_FLAG_NOCONV;
       return hi;
@@ -837,7 +858,7 @@ double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
   for (int it = 0; it < 200; ++it) {
     double z[3];
-    orc_hurwitz3(a, q, z);
+    orc_hurwitz3_scaled(a, q, q, z);
     double r1 = z[1] / z[0];
     double g = -r1 - m;
     if (g == 0.0) return a;
@@ -861,7 +882,8 @@ double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
 /* D over the sorted values (all >= xmin): as ks_sorted with zeta(a, xmin)   */
 /* as the normaliser and F(xmin - 1) = 0.                                    */
 static double hz_ks_sorted(const int64_t *xs, int64_t n, double a, int64_t xmin) {
-  const double z = hurwitz0(a, (double)xmin);
+  const double r = (double)xmin; /* every sum scaled by xmin^a */
+  const double z = hurwitz0_rel(a, r, r);
   const double dn = (double)n;
   double D = 0.0;
   int64_t i = 0;
@@ -870,8 +892,8 @@ static double hz_ks_sorted(const int64_t *xs, int64_t n, double a, int64_t xmin)
     int64_t below = i;
     while (i < n && xs[i] == v) ++i;
     int64_t upto = i;
-    double Fv = 1.0 - hurwitz0(a, (double)v + 1.0) / z;
-    double Fv1 = (v - 1 < xmin) ? 0.0 : 1.0 - hurwitz0(a, (double)v) / z;
+    double Fv = 1.0 - hurwitz0_rel(a, (double)v + 1.0, r) / z;
+    double Fv1 = (v - 1 < xmin) ? 0.0 : 1.0 - hurwitz0_rel(a, (double)v, r) / z;
     double d1 = fabs((double)upto / dn - Fv);
     double d2 = fabs((double)below / dn - Fv1);
     if (d1 > D) D = d1;

@@ -43,11 +43,15 @@ MUTANTS = [
     ("bootstrap strict inequality", "if (Db[b] >= d) ++ge;", "if (Db[b] > d) ++ge;"),
     # the law with a lower cutoff xmin
     ("xmin draw offset", "return xmin - 1 + (int64_t)lo;", "return xmin + (int64_t)lo;"),
-    ("xmin table normalised by zeta(alpha)", "const double z = hurwitz0(alpha, (double)xmin);",
-     "const double z = hurwitz0(alpha, 1.0);"),
-    ("xmin KS normalised by zeta(a)", "const double z = hurwitz0(a, (double)xmin);",
-     "const double z = hurwitz0(a, 1.0);"),
-    ("xmin MLE with zeta(a)", "orc_hurwitz3(a, q, z);", "orc_hurwitz3(a, 1.0, z);"),
+    ("xmin table normalised by zeta(alpha)", "const double z = hurwitz0_rel(alpha, r, r);",
+     "const double z = hurwitz0_rel(alpha, 1.0, r);"),
+    ("xmin KS normalised by zeta(a)", "const double z = hurwitz0_rel(a, r, r);",
+     "const double z = hurwitz0_rel(a, 1.0, r);"),
+    ("xmin MLE with zeta(a)", "orc_hurwitz3_scaled(a, q, q, z);",
+     "orc_hurwitz3_scaled(a, 1.0, q, z);"),
+    ("xmin scaled integral term loses its factor a",
+     "const double a1s = r == 1.0 ? pow(a, 1.0 - s) : a * as;",
+     "const double a1s = r == 1.0 ? pow(a, 1.0 - s) : as;"),
     ("xmin cutoff rule counts xmin + 2", "tmp[n - 1] = xmin + 1;", "tmp[n - 1] = xmin + 2;"),
     ("xmin scan keeps the largest D", "if (best < 0 || D[c] < D[best]) best = c;",
      "if (best < 0 || D[c] > D[best]) best = c;"),
@@ -224,6 +228,11 @@ def _checks_xmin(orc):
     r = orc.hz_fit(np.full(10, 2), 2)
     if abs(r["S"] - (9 * math.log(2) + math.log(3))) > 1e-12:
         failed.append("xmin cutoff rule")
+    # a cutoff of 10^6: q^-s alone underflows there during the iteration
+    lx = math.log(10 ** 6)
+    a6, f6 = orc.hz_mle(lx + 0.67, 10 ** 6)
+    if f6 & orc.FLAG_NOCONV or abs(a6 - 2.4925361995999435) > 1e-12 * a6:
+        failed.append("xmin MLE at a large cutoff")
     sc = orc.hz_scan(np.array([1, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89]), [1, 2, 3, 5, 8])
     if sc["best"] != int(np.argmin(sc["D"])):
         failed.append("xmin scan")

@@ -238,3 +238,42 @@ def test_simulated_exponents_centre_on_alpha(orc):
         m, se = r["alpha_hat"].mean(), r["alpha_hat"].std(ddof=1) / 20
         assert abs(m - a) < 4 * se + 1e-3, (a, xmin, m, se)
         assert np.all(r["xmax"] >= xmin)
+
+
+@pytest.mark.parametrize("xmin", [10 ** 5, 10 ** 6, 10 ** 9, 2 ** 40])
+def test_mle_at_huge_cutoffs(orc, xmin):
+    """Cutoffs up to 2^40: q^-s underflows in FP64 from q of about 6.5e4 at
+    s = 64, which the bracket check and the iteration reach; the sums are
+    kept scaled by xmin^s.  The root matches mpmath's (its error there is the
+    FP64 rounding of m, about ulp(ln xmin)/d^2 for m = ln xmin + d)."""
+    lx = math.log(xmin)
+    for d in (0.1, 0.67, 2.0):
+        a, f = orc.hz_mle(lx + d, xmin)
+        with mp.workdps(40):
+            mm = mp.mpf(lx) + mp.mpf(d)
+            root = mp.findroot(lambda s: -mp.zeta(s, xmin, 1) / mp.zeta(s, xmin) - mm, 1 + 1 / d)
+        tol = 1e-13 + 4 * 2.0 ** -53 * lx / d ** 2
+        assert not (f & orc.FLAG_NOCONV) and abs(a - float(root)) <= tol * float(root), (xmin, d, a)
+
+
+def _em40(a, q, P=10):
+    """zeta(a, q) by Euler-Maclaurin at 40 digits (q large: converges at once)."""
+    with mp.workdps(40):
+        a, q = mp.mpf(a), mp.mpf(q)
+        acc = q ** (1 - a) / (a - 1) + q ** (-a) / 2
+        poch = a
+        for i in range(1, P + 1):
+            acc += mp.bernoulli(2 * i) / mp.factorial(2 * i) * poch * q ** (-a - 2 * i + 1)
+            poch *= (a + 2 * i - 1) * (a + 2 * i)
+        return acc
+
+
+@pytest.mark.parametrize("a,xmin", [(30.0, 10 ** 6), (2.5, 2 ** 40), (64.0, 10 ** 9)])
+def test_cdf_table_at_huge_cutoffs(orc, a, xmin):
+    T = orc.hz_cdf_table(a, xmin)
+    with mp.workdps(40):
+        Z = _em40(a, xmin)
+        for j in (1, 2, 5, 100, 4096):
+            want = 1 - _em40(a, xmin + j) / Z
+            assert abs(T[j - 1] - float(want)) < 4e-15, (a, xmin, j, T[j - 1], float(want))
+    assert np.all(np.diff(T) >= 0)
