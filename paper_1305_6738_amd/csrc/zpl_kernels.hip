@@ -439,11 +439,13 @@ __device__ __forceinline__ double wave_max_f64(double v) {
 // iz = 1/zeta(a, xmin): F(t) = 1 - zeta(a, t+1) iz for t >= xmin - 1 (the
 // first distinct value's lower term is then zero).  cut: the law with a lower
 // cutoff, whose survival values above 16 come from survival_next_cut (there
-// they are the normaliser's own scale, not a tail of zeta(a)).
+// they are the normaliser's own scale, not a tail of zeta(a)); xrel > 0: a
+// cutoff xrel above 17, every survival value (and iz) taken relative to
+// xrel^-a (survival_rel).
 __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_t* __restrict__ lc,
                                    int len, const EmCoef& E, const double (&suf)[17], int64_t n,
                                    const double* __restrict__ ln, int lane, double iz,
-                                   bool cut = false) {
+                                   bool cut = false, int64_t xrel = 0) {
   const double idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0;
@@ -471,12 +473,15 @@ __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_
     bool have = q0 == p16;  // zprev is zeta(a, vprev + 1)
     for (int q = q0; q < q1; ++q) {
       const int64_t v = lv[q];
-      const double zv = cut ? survival_next_cut(E, v, ln) : survival_next(E, v, ln);
+      const double zv = xrel ? survival_rel(E, v, xrel)
+                             : (cut ? survival_next_cut(E, v, ln) : survival_next(E, v, ln));
       double zv1;
       if (v - 1 == vprev)
-        zv1 = have ? zprev : (cut ? survival_next_cut(E, vprev, ln) : survival_next(E, vprev, ln));
+        zv1 = have ? zprev
+                   : (xrel ? survival_rel(E, vprev, xrel)
+                           : (cut ? survival_next_cut(E, vprev, ln) : survival_next(E, vprev, ln)));
       else
-        zv1 = zv + pow_neg(E.s, ln_value(v, ln));
+        zv1 = zv + (xrel ? pow_rel(E.s, v, xrel) : pow_neg(E.s, ln_value(v, ln)));
       const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
       C += lc[q];
       const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
@@ -517,8 +522,9 @@ __device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const u
 #pragma unroll
     for (int t = 1; t <= 16; ++t)
       if (xmin - 1 == t) zx = suf[t];
-    if (xmin > 17) zx = survival_next_cut(E, xmin - 1, ln);
-    D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / zx, true);
+    // above 17 every value is: survival values relative to xmin^-a
+    if (xmin > 17) zx = survival_rel(E, xmin - 1, xmin);
+    D = ks_distance_wave(lv, lc, len, E, suf, n, ln, lane, 1.0 / zx, true, xmin > 17 ? xmin : 0);
     ahat = a;
     flags = fl;
     return;
@@ -1668,11 +1674,14 @@ __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells
   if (xmin > 1) {  // T[k-1] = F(xmin + k - 1) = 1 - zeta(a, xmin + k)/zeta(a, xmin)
     const EmCoef E = em_coef(a);
     survival_head_cut(E, ln, suf);
-    auto zq = [&](int64_t q) {  // zeta(a, q), q >= 2 (static indices into suf: no scratch)
+    // zeta(a, q), q >= 2 (static indices into suf: no scratch); above a
+    // cutoff of 17 every value relative to xmin^-a (survival_rel)
+    auto zq = [&](int64_t q) {
       double z = 0.0;
 #pragma unroll
       for (int t = 1; t <= 16; ++t)
         if (q - 1 == t) z = suf[t];
+      if (xmin > 17) return survival_rel(E, q - 1, xmin);
       return q <= 17 ? z : survival_next_cut(E, q - 1, ln);
     };
     tables[(size_t)cell * kH + (k - 1)] = 1.0 - zq(xmin + k) / zq(xmin);

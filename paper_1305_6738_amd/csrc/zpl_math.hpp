@@ -316,13 +316,17 @@ ZPL_HD int64_t em_point(double s, int64_t q) {
 // (none when xmin >= q), largest k first, after the Euler-Maclaurin tail at
 // q = max(xmin, em_point(s, xmin)) and its derivatives (em_point keeps that
 // tail accurate at large s; it is 17 for s <= 4.375, as zeta3 uses for
-// xmin = 1).
+// xmin = 1).  All three are returned multiplied by xmin^s: every power is
+// taken as (k/xmin)^-s, the logarithms the derivatives bring down stay ln k.
+// The factor cancels in mu = -z1/z0 and in the variance, and without it k^-s
+// underflows for s ln k > 708 (at s = 64 from k of about 6.5e4).
 // ---------------------------------------------------------------------------
 ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
   const int64_t q0 = em_point(s, xmin);
   const int64_t qi = xmin < q0 ? q0 : xmin;
   const double q = (double)qi;
   const double L = ln_value(qi, ln);
+  const double ix = 1.0 / (double)xmin;
   const double iq = 1.0 / q, iq2 = iq * iq;
   const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
                        1.0 / 30240.0,      -1.0 / 1209600.0,
@@ -351,13 +355,14 @@ ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
   Q0 += q * ism1;
   Q1 += -q * ism1 * ism1;
   Q2 += 2.0 * q * ism1 * ism1 * ism1;
-  const double qs = pow_neg(s, L);
+  // powers relative to xmin: (k/xmin)^-s with ln(k/xmin) = log1p((k - xmin)/xmin)
+  const double qs = qi == xmin ? 1.0 : pow_neg(s, log1p((double)(qi - xmin) * ix));
   double z0 = qs * Q0;
   double z1 = qs * fma(-L, Q0, Q1);
   double z2 = qs * fma(L * L, Q0, fma(-2.0 * L, Q1, Q2));
   for (int64_t k = qi - 1; k >= xmin; --k) {
     const double lk = ln[k];
-    const double t = pow_neg(s, lk);
+    const double t = k == xmin ? 1.0 : pow_neg(s, log1p((double)(k - xmin) * ix));
     z0 += t;
     z1 = fma(-lk, t, z1);
     z2 = fma(lk * lk, t, z2);
@@ -523,6 +528,35 @@ ZPL_HD double survival_next_cut(const EmCoef& E, int64_t v, const double* __rest
   const int64_t q0 = em_point(E.s, v + 1);
   if (v >= q0 - 1) return survival_next(E, v, ln);
   return survival_cut_direct(E.s, v, q0, ln);
+}
+
+// zeta(a, v+1) xmin^a for the law with a cutoff xmin >= 17 and v >= xmin - 1:
+// as survival_next_cut, with every power relative to xmin,
+// (k/xmin)^-a = exp(-a log1p((k - xmin)/xmin)), so that it stays representable
+// however large xmin^-a is (ratios of these give the CDF; the factor cancels).
+__host__ __device__ __noinline__ static double survival_rel_direct(double s, int64_t v, int64_t q0,
+                                                                   int64_t xmin) {
+  const double ix = 1.0 / (double)xmin;
+  double z = hurwitz_tail(em_coef(s), (double)q0, log1p((double)(q0 - xmin) * ix));
+  for (int64_t k = q0 - 1; k > v; --k)
+    z += k == xmin ? 1.0 : pow_neg(s, log1p((double)(k - xmin) * ix));
+  return z;
+}
+
+// hurwitz_tail takes the logarithm only for its power q^-a, so handing it
+// ln(q/xmin) gives the tail relative to xmin^-a.
+ZPL_HD double survival_rel(const EmCoef& E, int64_t v, int64_t xmin) {
+  if (v < em_start(E.s) - 1) {  // direct terms below the tail, as survival_next_cut
+    const int64_t q0 = em_point(E.s, v + 1);
+    if (v < q0 - 1) return survival_rel_direct(E.s, v, q0, xmin);
+  }
+  const double lrel = v + 1 == xmin ? 0.0 : log1p((double)(v + 1 - xmin) / (double)xmin);
+  return hurwitz_tail(E, (double)v + 1.0, lrel);
+}
+
+// (v/xmin)^-a for v >= xmin: one term of survival_rel.
+ZPL_HD double pow_rel(double a, int64_t v, int64_t xmin) {
+  return v == xmin ? 1.0 : pow_neg(a, log1p((double)(v - xmin) / (double)xmin));
 }
 
 // survival_head with an accurate suf[16] = zeta(a, 17) (see em_start).

@@ -60,6 +60,9 @@ double hm_survival_cut(double a, int64_t v) {  // zeta(a, v+1), law with a cutof
   survival_head_cut(E, g_ln.data(), suf);
   return v <= 16 ? suf[v] : survival_next_cut(E, v, g_ln.data());
 }
+double hm_survival_rel(double a, int64_t v, int64_t xmin) {  // zeta(a, v+1) xmin^a
+  return survival_rel(em_coef(a), v, xmin);
+}
 double hm_mle_hz(double m, int64_t xmin, uint32_t* flags) {
   return mle_alpha_hz(m, xmin, g_ln.data(), flags);
 }

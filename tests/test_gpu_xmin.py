@@ -66,7 +66,9 @@ def compare(orc, g, lo, cell, reps=None):
 
 
 @pytest.mark.parametrize("a,xmin", [(2.5, 2), (1.6, 17), (3.3, 18), (2.0, 500), (1.8, 123456),
-                                    (30.0, 17), (50.0, 20), (12.0, 16)])
+                                    (30.0, 17), (50.0, 20), (12.0, 16),
+                                    # xmin^-a below FP64's range: sums relative to xmin^-a
+                                    (30.0, 10**6), (2.5, 2**40), (64.0, 10**9), (12.0, 4097)])
 def test_cdf_table_matches_oracle(ctx, orc, a, xmin):
     T = torch.zeros(4096, dtype=torch.float64, device="cuda")
     ctx.cdf_table(a, T, xmin=xmin)
@@ -76,7 +78,7 @@ def test_cdf_table_matches_oracle(ctx, orc, a, xmin):
 
 
 @pytest.mark.parametrize("a,xmin,n", [(2.5, 3, 1001), (1.6, 500, 600), (4.0, 2, 257),
-                                      (1.3, 40, 300), (2.2, 100000, 129)])
+                                      (1.3, 40, 300), (2.2, 100000, 129), (30.0, 10**9, 200)])
 def test_draws_bit_exact(ctx, orc, a, xmin, n):
     count = 5
     say("draws", a, xmin, n)
@@ -140,6 +142,44 @@ def test_large_exponents_at_small_cutoffs(ctx, orc):
             assert abs(r["D"] - ref["D"]) <= 1e-12, (xmin, extra)
             s = ctx.fit_scan(x, [xmin])
             assert (s["alpha_hat"][0], s["D"][0]) == (r["alpha_hat"], r["D"])
+
+
+HUGE = [(2.5, 200, 300, 5, 20, 0, 10**6), (30.0, 100, 200, 5, 21, 0, 10**9),
+        (1.5, 100, 200, 5, 22, 0, 2**40), (64.0, 50, 200, 5, 23, 0, 70000),
+        (27.0, 150, 200, 5, 24, 0, 2**33)]
+
+
+def test_huge_cutoffs(ctx, orc):
+    """Cutoffs where xmin^-a is below FP64's range (a ln xmin > 708), up to the
+    2^40 limit: the Hurwitz sums of eq. 2 and the CDF of eq. 1 are taken
+    relative to xmin^-a.  Every replicate against the oracle, the quantiles,
+    no bracket-end NOCONV where the exponent is far from 64, and fits of data
+    with a body below the cutoff (single fit and scan candidate agree bit for
+    bit)."""
+    say("huge cutoffs: cells")
+    g = run_cells(ctx, HUGE)
+    lo = 0
+    for ci, cell in enumerate(HUGE):
+        compare(orc, g, lo, cell)
+        D = g["D"][lo:lo + cell[2]]
+        for qi, (a, b) in enumerate(QS):
+            assert g["q"][ci, qi] == orc.quantile(D, a, b), (cell, (a, b))
+        if cell[0] < 60.0:
+            assert not np.any(g["flags"][lo:lo + cell[2]] & 8), cell
+        lo += cell[2]
+    say("huge cutoffs: fits")
+    for a, xmin in [(2.5, 10**6), (30.0, 10**9), (40.0, 2**40), (3.0, 4097), (64.0, 10**5)]:
+        tail, _ = orc.hz_sample(a, xmin, 2000, 9, 0, 0)
+        body = np.random.default_rng(xmin % 1000).integers(1, xmin, size=500)
+        x = np.concatenate([body, tail])
+        r = ctx.fit(x, xmin=xmin)
+        ref = orc.hz_fit(x, xmin)
+        assert ref["flags"] & 8 == 0 and r["flags"] & KEEP_FLAGS == ref["flags"] & KEEP_FLAGS
+        assert abs(r["alpha_hat"] - ref["alpha_hat"]) <= 1e-10 * ref["alpha_hat"], (a, xmin)
+        assert abs(r["D"] - ref["D"]) <= 1e-12, (a, xmin)
+        assert r["n_tail"] == ref["n_tail"] == 2000
+        s = ctx.fit_scan(x, [xmin])
+        assert (s["alpha_hat"][0], s["D"][0]) == (r["alpha_hat"], r["D"])
 
 
 def test_cutoff_cells_beside_pure_cells_bit_identical(ctx):

@@ -48,6 +48,8 @@ def hm(tmp_path_factory):
     L.hm_tail_from.restype = C.c_int64
     L.hm_survival_cut.argtypes = [C.c_double, C.c_int64]
     L.hm_survival_cut.restype = C.c_double
+    L.hm_survival_rel.argtypes = [C.c_double, C.c_int64, C.c_int64]
+    L.hm_survival_rel.restype = C.c_double
     L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
     L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
     L.hm_mle_trunc.restype = C.c_double
@@ -160,9 +162,10 @@ def test_exact_S_order_independent(hm):
                                  (10.0, 17), (20.0, 17), (40.0, 17), (64.0, 17), (54.0, 16),
                                  (30.0, 2), (25.0, 30), (50.0, 60), (64.0, 106), (64.0, 107)])
 def test_hurwitz3_at_a_cutoff(hm, s, q):
-    """zeta(s, q) and its s-derivatives for the law with a lower cutoff,
-    against partial sums at 40 digits (mpmath's own Hurwitz zeta is not
-    accurate enough at s = 50, q = 300) or mpmath where the sum is long."""
+    """zeta(s, q) and its s-derivatives for the law with a lower cutoff, each
+    multiplied by q^s (the library's scale, a common factor that cancels in
+    eq. 2), against partial sums at 40 digits (mpmath's own Hurwitz zeta is
+    not accurate enough at s = 50, q = 300) or mpmath where the sum is long."""
     out = np.zeros(3)
     hm.hm_hurwitz3(s, q, _p(out, C.c_double))
     with mp.workdps(40):
@@ -173,6 +176,7 @@ def test_hurwitz3_at_a_cutoff(hm, s, q):
                     mp.fsum(t * l * l for t, l in terms)]
         else:
             want = [mp.zeta(s, q), mp.zeta(s, q, 1), mp.zeta(s, q, 2)]
+        want = [w * mp.mpf(q) ** s for w in want]
     # q^-s = exp(-s ln q) inherits s times the rounding of ln q (about
     # s ln(q) 1.1e-16 relative); that factor is common to all three and
     # cancels in zeta'/zeta
@@ -309,3 +313,46 @@ def test_mle_edges_agree_within_the_conditioning_of_eq2(hm, orc):
                 continue
             assert ao < 64.0, (xmin, m, a, ao)
             assert abs(a - ao) <= 4 * eps * m / _var_cut(ao, xmin), (xmin, m, a, ao)
+
+
+def _zeta_rel(a, v, x):
+    """zeta(a, v+1) x^a in 40 digits: partial sum to v + 6001, then the
+    Euler-Maclaurin remainder (exact to far below FP64 there)."""
+    with mp.workdps(40):
+        a, q = mp.mpf(a), mp.mpf(v + 1)
+        M = q + 6000
+        head = mp.fsum((mp.mpf(k) / x) ** -a for k in range(v + 1, v + 6001))
+        tail = (M / x) ** -a * (M / (a - 1) + mp.mpf(1) / 2 + a / (12 * M))
+        return head + tail
+
+
+@pytest.mark.parametrize("a,xmin", [(2.5, 10**5), (30.0, 10**6), (64.0, 10**9),
+                                    (1.5, 2**40), (12.0, 4097)])
+def test_survival_relative_to_a_huge_cutoff(hm, a, xmin):
+    """zeta(a, v+1) xmin^a, the scaled survival the law with a cutoff above 17
+    uses, against 40 digits at v = xmin - 1 (the normaliser) and above: it
+    stays O(xmin/(a-1)) where xmin^-a itself underflows FP64."""
+    for v in (xmin - 1, xmin, xmin + 5, xmin + 150, 2 * xmin):
+        got = hm.hm_survival_rel(a, v, xmin)
+        ref = _zeta_rel(a, v, xmin)
+        assert abs(got - float(ref)) <= 4e-15 * float(ref), (a, xmin, v, got, ref)
+
+
+@pytest.mark.parametrize("xmin", [10**5, 10**6, 10**9, 2**40])
+def test_mle_at_huge_cutoffs_agrees_with_the_oracle(hm, orc, xmin):
+    """Eq. (2) for the law with a cutoff far above where x^-64 underflows
+    FP64 (xmin = 1e5 .. 2^40): the library's root agrees with the oracle's
+    within the conditioning bound 4 eps m / Var(ln X) (Var of ln X is about
+    1/(a-1)^2, so the root is ill-conditioned in proportion to ln xmin),
+    converges without flags, and the bracket end 64 is not returned."""
+    eps = 2.0 ** -53
+    lx = math.log(xmin)
+    for d in (0.05, 0.3, 0.67, 2.0, 8.0):
+        m = lx + d
+        f = C.c_uint32(0)
+        a = hm.hm_mle_hz(m, xmin, C.byref(f))
+        ao, fo = orc.hz_mle(m, xmin)
+        assert f.value & 8 == 0 and fo & 8 == 0, (xmin, d, f.value, fo)
+        assert a < 60.0, (xmin, d, a)
+        var = 1.0 / (ao - 1.0) ** 2
+        assert abs(a - ao) <= max(1e-10 * ao, 4 * eps * m / var), (xmin, d, a, ao)
