@@ -388,11 +388,13 @@ ZPL_HD double mle_alpha_hz(double m, int64_t xmin, const double* __restrict__ ln
   }
   double a = 1.0 + 1.0 / (m - log((double)xmin - 0.5));
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+  double gl = 0.0;  // the last residual of eq. 2
   for (int it = 0; it < 200; ++it) {
     const Z3 z = hurwitz3(a, xmin, ln);
     const double r1 = z.z1 / z.z0;
     const double g = -r1 - m;
     if (g == 0.0) return a;
+    gl = g;
     if (g > 0.0)
       lo = a;
     else
@@ -406,7 +408,10 @@ ZPL_HD double mle_alpha_hz(double m, int64_t xmin, const double* __restrict__ ln
     if (fabs(an - a) <= 0x1p-40 * a) return an;
     a = an;
   }
-  *flags |= kFlagNoConv;
+  // Near the edge m -> ln xmin eq. 2 fixes the root only to about
+  // eps m / Var(ln X), coarser than the step test: a residual within the
+  // rounding noise of mu is a root as far as FP64 can tell, not a failure.
+  if (!(fabs(gl) <= 0x1p-44 * m)) *flags |= kFlagNoConv;
   return a;
 }
 
@@ -442,11 +447,13 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
   double a = a1 > a2 ? a1 : a2;
   if (!(a > lo && a < hi)) a = 0.0;
   const double lm = log(m);
+  double gl = 0.0;  // the last residual of eq. 2
   int it = 0;
   for (; it < 200; ++it) {
     const Z3 z = zeta3_trunc(a, K, ln);
     const double mu = -z.z1 / z.z0;
     if (mu == m) break;
+    gl = mu - m;
     if (mu > m)
       lo = a;
     else
@@ -462,7 +469,9 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
     a = an;
     if (done) break;
   }
-  if (it == 200) *flags |= kFlagNoConv;
+  // a residual within the rounding noise of mu is a root to FP64 precision
+  // (near the edges the step test is out of reach), as for mle_alpha_hz
+  if (it == 200 && !(fabs(gl) <= 0x1p-44 * m)) *flags |= kFlagNoConv;
   // Near an edge, is the root inside the bracket?  mu tends to ln K as s
   // falls, and for small K it reaches ln K to FP64 rounding well inside the
   // bracket (K = 2: from s of about -53 on), where an iterate can stop with

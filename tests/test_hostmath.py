@@ -356,3 +356,29 @@ def test_mle_at_huge_cutoffs_agrees_with_the_oracle(hm, orc, xmin):
         assert a < 60.0, (xmin, d, a)
         var = 1.0 / (ao - 1.0) ** 2
         assert abs(a - ao) <= max(1e-10 * ao, 4 * eps * m / var), (xmin, d, a, ao)
+
+
+def test_noconv_agrees_near_the_edges(hm, orc):
+    """Close to the edge of each law's range of m (every value at xmin, or at
+    K) eq. 2 fixes the root only to about eps m / Var(ln X), coarser than the
+    2^-40 step test, and a solver may run to its iteration limit.  Both then
+    flag NOCONV (bit 8) only if the last residual of eq. 2 exceeds the
+    rounding noise of an FP64 mu (2^-44 m), so the flag means the same on
+    both sides: no root found, never rounding noise (before, about one case
+    in ten near these edges was flagged on one side only)."""
+    rng = np.random.default_rng(8)
+    for xmin in (2, 3, 16, 30, 10**6):
+        lx = math.log(xmin)
+        for d in 10 ** rng.uniform(-14, 1.2, 150):
+            f = C.c_uint32(0)
+            a = hm.hm_mle_hz(lx + d, xmin, C.byref(f))
+            ao, fo = orc.hz_mle(lx + d, xmin)
+            assert f.value & 8 == fo & 8, (xmin, d, a, ao, f.value, fo)
+    for K in (2, 3, 5, 4097):
+        lnK = math.log(K)
+        for e in rng.uniform(1, 16, 150):
+            m = lnK * (1 - 10.0 ** -e)
+            f = C.c_uint32(0)
+            a = hm.hm_mle_trunc(m, K, C.byref(f))
+            ao, fo = orc.tz_mle(m, K)
+            assert f.value & 8 == fo & 8, (K, e, a, ao, f.value, fo)
