@@ -67,6 +67,12 @@ MUTANTS = [
     ("trunc draw never returns 1", "  int lo = 1, hi = K;\n  while (lo < hi) {\n    int mid = lo + (hi - lo) / 2;",
      "  int lo = 2, hi = K;\n  while (lo < hi) {\n    int mid = lo + (hi - lo) / 2;"),
     ("trunc MLE equation sign", "double gval = -r1 - m;", "double gval = r1 - m;"),
+    ("trunc NOCONV on rounding noise",
+     "if (!(fabs(g_last) <= 0x1p-44 * m)) *flags |= ORC_FLAG_NOCONV;\n  return a;\n}\n\n/* KS distance (eq. 3) of a sorted sample under the truncated law",
+     "*flags |= ORC_FLAG_NOCONV;\n  return a;\n}\n\n/* KS distance (eq. 3) of a sorted sample under the truncated law"),
+    ("xmin NOCONV on rounding noise",
+     "if (!(fabs(g_last) <= 0x1p-44 * m)) *flags |= ORC_FLAG_NOCONV;\n  return a;\n}\n\n/* D over the sorted values",
+     "*flags |= ORC_FLAG_NOCONV;\n  return a;\n}\n\n/* D over the sorted values"),
     ("trunc KS below each value at the value", "double Fv1 = 1.0 - suf[v - 1] / z;",
      "double Fv1 = 1.0 - suf[v] / z;"),
     ("trunc KS upper term uses the count below", "double d1 = fabs((double)upto / dn - Fv);",
@@ -189,12 +195,30 @@ def _checks_trunc(orc):
         want = 1 - 1 / mp.fsum(mp.mpf(k) ** -a for k in range(1, K + 1))
     if abs(r["D"] - float(want)) > 1e-12:
         failed.append("trunc all-ones atom")
+    # K = 2 near the edges: the closed-form root log2((1 - p)/p), m = p ln 2,
+    # lies inside [-64, 64], so NOCONV must stay clear
+    for e in np.linspace(5, 14, 37):
+        for p in (10.0 ** -e, 1 - 10.0 ** -e):
+            if orc.tz_mle(math.log(2) * p, 2)[1] & 8:
+                failed.append("trunc NOCONV inside the bracket")
+                return failed
     return failed
 
 
 def _checks_xmin(orc):
     """Quick pins of the law with a lower cutoff."""
     failed = []
+    # near the edge m -> ln xmin: m above mu(64) (30 digits) has its root
+    # below 64, so NOCONV must stay clear
+    with mp.workdps(30):
+        for xmin in (2, 3):
+            w = [(mp.mpf(k) ** -64, mp.log(k)) for k in range(xmin, xmin + 40)]
+            mu64 = float(mp.fsum(t * l for t, l in w) / mp.fsum(t for t, _ in w))
+            for d in np.geomspace(1e-9, 1e-6, 40):
+                m = math.log(xmin) + float(d)
+                if m > mu64 * (1 + 1e-14) and orc.hz_mle(m, xmin)[1] & 8:
+                    failed.append("xmin NOCONV inside the bracket")
+                    break
     T = orc.hz_cdf_table(2.5, 7)
     with mp.workdps(30):
         want = (mp.mpf(7) ** -2.5 + mp.mpf(8) ** -2.5 + mp.mpf(9) ** -2.5) / mp.zeta(2.5, 7)

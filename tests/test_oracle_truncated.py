@@ -120,6 +120,28 @@ def test_mle_closed_form_K2(orc):
     assert abs(orc.tz_fit(np.array([1, 2]), 2)["alpha_hat"]) < 1e-14
 
 
+def test_mle_closed_form_K2_up_to_the_edges(orc):
+    """The same closed form over m = ln 2 p with p from 1e-15 to 1 - 1e-15:
+    where the root lies in [-64, 64] it is returned without NOCONV, within the
+    conditioning of eq. 2 (4 eps m / Var, Var = ln^2 2 p (1 - p)) and 1e-13;
+    beyond, the bracket end with NOCONV.  This pins the reading that a
+    residual within the rounding of an FP64 mu is a root: near the edges the
+    2^-40 step test alone is out of reach."""
+    eps = 2.0 ** -53
+    ln2 = math.log(2)
+    ps = [10.0 ** -e for e in np.linspace(1, 15, 57)]
+    for p in ps + [1 - q for q in ps]:
+        m = ln2 * p
+        want = math.log2((1 - p) / p)
+        a, f = orc.tz_mle(m, 2)
+        if abs(want) < 63.9:
+            var = ln2 * ln2 * p * (1 - p)
+            assert f & 8 == 0, (p, a, want, f)
+            assert abs(a - want) <= max(1e-13 * max(1.0, abs(want)), 4 * eps * m / var), (p, a, want)
+        elif abs(want) > 64.1:
+            assert f & 8 and a == math.copysign(64.0, want), (p, a, want, f)
+
+
 def test_mle_uniform_sample_gives_zero(orc):
     # each value once: mean ln x = ln(K!)/K = mu(0)
     for K in (5, 20, 300):
