@@ -67,7 +67,7 @@ typedef int32_t zpl_status;
 #define ZPL_FLAG_ALL_ONES 1u    /* every value was 1 (at xmin); one counted as 2 (xmin + 1) */
 #define ZPL_FLAG_TAIL_CAPPED 2u /* a tail proposal >= 2^63 was redrawn            */
 #define ZPL_FLAG_BISECT 4u      /* the MLE solver took a bisection step (info)    */
-#define ZPL_FLAG_NOCONV 8u      /* no MLE root in the bracket, or the iteration cap */
+#define ZPL_FLAG_NOCONV 8u      /* no MLE root in the bracket, or the iteration cap with the residual of eq. 2 above FP64 noise */
 
 typedef struct zpl_ctx zpl_ctx;
 
