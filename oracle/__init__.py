@@ -94,6 +94,8 @@ def _bind(L):
         L.orc_tail_draw.argtypes = [d, u64, u32, u32, u32, P(u32)]
         L.orc_tail_draw.restype = i64
         L.orc_sample.argtypes = [d, P(d), i64, u64, u32, u32, P(i64), P(u32)]
+        L.orc_mle_last_iters.argtypes = []
+        L.orc_mle_last_iters.restype = C.c_int
         L.orc_mle.argtypes = [d, P(u32)]
         L.orc_mle.restype = d
         L.orc_fit.argtypes = [P(i64), i64, P(d), P(d), P(d), P(u32)]
@@ -186,6 +188,11 @@ def tail_draw(alpha: float, seed: int, stream: int, rep: int, i: int):
     f = C.c_uint32(0)
     x = lib().orc_tail_draw(alpha, seed, stream, rep, i, C.byref(f))
     return x, f.value
+
+
+def mle_last_iters() -> int:
+    """Iterations of the calling thread's last MLE solve (any of the laws)."""
+    return int(lib().orc_mle_last_iters())
 
 
 def mle(m: float):

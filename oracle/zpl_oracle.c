@@ -280,16 +280,31 @@ void orc_sample(double alpha, const double *T, int64_t n, uint64_t seed,
 /* a bracket [1 + 2^-20, 64] that shrinks with the sign of g; a step leaving  */
 /* the bracket is replaced by bisection.                                     */
 /* ------------------------------------------------------------------------ */
+/* Reading shared by the three laws (pure, truncated, with a cutoff): eq. 2   */
+/* is solved to FP64 precision.  The iteration stops after a step of at most */
+/* 2^-40 max(|a|, 1) and returns the next iterate (Newton converges          */
+/* quadratically, so that iterate sits at the rounding noise of mu); after   */
+/* ORC_MLE_CAP iterations it stops, and NOCONV is set only when the last     */
+/* residual |mu(a) - m| exceeds 2^-44 m, the rounding noise of an FP64 mu:   */
+/* NOCONV means that no root was found, never rounding noise.                */
+#define ORC_MLE_CAP 200
+static _Thread_local int orc_iters;
+int orc_mle_last_iters(void) { return orc_iters; }
+
 double orc_mle(double m, uint32_t *flags) {
+  orc_iters = 0;
   double lo = 1.0 + 0x1p-20, hi = 64.0;
   double a = 1.0 + 1.0 / m; /* from -zeta'/zeta ~ 1/(a-1) near a = 1 */
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
-  for (int it = 0; it < 200; ++it) {
+  double g_last = 0.0;
+  for (int it = 0; it < ORC_MLE_CAP; ++it) {
+    orc_iters = it + 1;
     double z[3];
     orc_zeta3(a, z);
     double r1 = z[1] / z[0];
     double g = -r1 - m;
     if (g == 0.0) return a;
+    g_last = g;
     if (g > 0.0)
       lo = a;
     else
@@ -301,10 +316,10 @@ double orc_mle(double m, uint32_t *flags) {
       an = 0.5 * (lo + hi);
       *flags |= ORC_FLAG_BISECT;
     }
-    if (fabs(an - a) <= 0x1p-50 * a) return an;
+    if (fabs(an - a) <= 0x1p-40 * a) return an;
     a = an;
   }
-  *flags |= ORC_FLAG_NOCONV;
+  if (!(fabs(g_last) <= 0x1p-44 * m)) *flags |= ORC_FLAG_NOCONV;
   return a;
 }
 
@@ -598,6 +613,7 @@ int64_t orc_tz_draw(const double *T, int K, uint64_t seed, uint32_t stream, uint
 /* iterate sits at the rounding noise of mu, while a tighter threshold can  */
 /* lie below that noise when |g| < 1 and never be met.                      */
 double orc_tz_mle(double m, int K, uint32_t *flags) {
+  orc_iters = 0;
   double lo = -64.0, hi = 64.0;
   double z[3];
   orc_tz_norm3(hi, K, z);
@@ -613,7 +629,8 @@ double orc_tz_mle(double m, int K, uint32_t *flags) {
   double a = 1.0 + 1.0 / m;
   if (!(a > lo && a < hi)) a = 0.0;
   double g_last = 0.0;
-  for (int it = 0; it < 400; ++it) {
+  for (int it = 0; it < ORC_MLE_CAP; ++it) {
+    orc_iters = it + 1;
     orc_tz_norm3(a, K, z);
     double r1 = z[1] / z[0];
     double gval = -r1 - m;
@@ -847,6 +864,7 @@ int64_t orc_hz_draw(double alpha, int64_t xmin, const double *T, uint64_t seed,
 /* 64/xmin^2 ... 1/xmin): then NOCONV and the bracket end 64.                */
 double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
   if (xmin == 1) return orc_mle(m, flags);
+  orc_iters = 0;
   const double q = (double)xmin;
   double lo = 1.0 + 0x1p-20, hi = 64.0;
   {
@@ -860,7 +878,8 @@ double orc_hz_mle(double m, int64_t xmin, uint32_t *flags) {
   double a = 1.0 + 1.0 / (m - log(q - 0.5)); /* continuous Pareto from xmin - 1/2 */
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
   double g_last = 0.0;
-  for (int it = 0; it < 200; ++it) {
+  for (int it = 0; it < ORC_MLE_CAP; ++it) {
+    orc_iters = it + 1;
     double z[3];
     orc_hurwitz3_scaled(a, q, q, z);
     double r1 = z[1] / z[0];

@@ -28,7 +28,10 @@ extern "C" {
 #define ORC_FLAG_ALL_ONES     1u  /* every draw was 1; S replaced by ln 2   */
 #define ORC_FLAG_TAIL_CAPPED  2u  /* a tail proposal >= 2^63 was redrawn   */
 #define ORC_FLAG_BISECT       4u  /* the MLE solver took a bisection step  */
-#define ORC_FLAG_NOCONV       8u  /* the MLE solver hit its iteration cap  */
+#define ORC_FLAG_NOCONV       8u  /* the MLE solver found no root: its     */
+                                   /* iteration cap with a residual of eq. 2 */
+                                   /* above FP64 noise, or no root in the    */
+                                   /* bracket                                */
 
 /* Philox4x32-10 block function (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
@@ -66,6 +69,8 @@ void orc_sample(double alpha, const double *T, int64_t n, uint64_t seed,
 
 /* MLE of alpha from the mean log m = S/n (eq. 2), Newton with bisection. */
 double orc_mle(double m, uint32_t *flags);
+/* Iterations the calling thread's last MLE solve (any law) took. */
+int orc_mle_last_iters(void);
 
 /* Fit one dataset: S = sum ln x (all-ones rule applied), alpha_hat, D.
  * Returns 0, or -1 if n < 1 or any x < 1. */

@@ -247,9 +247,16 @@ ZPL_HD Z3 zeta3(double s, const double* __restrict__ ln) {
 // [1 + 2^-20, 64] that shrinks with the sign of mu - m; a step leaving the
 // bracket becomes a bisection.  Stops once |step| <= 2^-40 a: convergence is
 // quadratic, so the iterate after such a step is at the FP64 noise level of
-// mu (a tighter test would only chase that noise).
+// mu (a tighter test would only chase that noise).  The rule shared by the
+// three laws' solvers: at most kMleCap iterations, and at the cap kFlagNoConv
+// only when the last residual |mu - m| exceeds 2^-44 m (the rounding noise
+// of an FP64 mu), so the flag means that no root was found.  `iters`, when
+// given, receives the iteration count (host checks only).
 // ---------------------------------------------------------------------------
-ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags) {
+constexpr int kMleCap = 200;
+
+ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags,
+                        int* iters = nullptr) {
   double lo = 1.0 + 0x1p-20, hi = 64.0;
   // initial guess: mu ~ 1/(a-1) - gamma near a = 1; mu ~ ln2 2^-a for large a
   double a1 = 1.0 + 1.0 / (m + 0.5772156649015329);
@@ -257,10 +264,13 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
   double a = a1 > a2 ? a1 : a2;
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
   const double lm = log(m);
-  for (int it = 0; it < 100; ++it) {
+  double gl = 0.0;  // the last residual of eq. 2
+  int it = 0;
+  for (; it < kMleCap; ++it) {
     const Z3 z = zeta3(a, ln);
     const double mu = -z.z1 / z.z0;
-    if (mu == m) return a;
+    if (mu == m) break;
+    gl = mu - m;
     if (mu > m)
       lo = a;
     else
@@ -272,10 +282,12 @@ ZPL_HD double mle_alpha(double m, const double* __restrict__ ln, uint32_t* flags
       an = 0.5 * (lo + hi);
       *flags |= kFlagBisect;
     }
-    if (fabs(an - a) <= 0x1p-40 * a) return an;
+    const bool done = fabs(an - a) <= 0x1p-40 * a;
     a = an;
+    if (done) break;
   }
-  *flags |= kFlagNoConv;
+  if (iters) *iters = it < kMleCap ? it + 1 : it;
+  if (it == kMleCap && !(fabs(gl) <= 0x1p-44 * m)) *flags |= kFlagNoConv;
   return a;
 }
 
@@ -377,7 +389,8 @@ ZPL_HD Z3 hurwitz3(double s, int64_t xmin, const double* __restrict__ ln) {
 // step of at most 2^-40 a.  A root above 64 (m <= mu(64), a sample close to
 // a large cutoff) gives 64 with kFlagNoConv.  xmin >= 2.
 ZPL_HD double mle_alpha_hz(double m, int64_t xmin, const double* __restrict__ ln,
-                           uint32_t* flags) {
+                           uint32_t* flags, int* iters = nullptr) {
+  if (iters) *iters = 0;
   double lo = 1.0 + 0x1p-20, hi = 64.0;
   {
     const Z3 z = hurwitz3(hi, xmin, ln);
@@ -389,7 +402,8 @@ ZPL_HD double mle_alpha_hz(double m, int64_t xmin, const double* __restrict__ ln
   double a = 1.0 + 1.0 / (m - log((double)xmin - 0.5));
   if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
   double gl = 0.0;  // the last residual of eq. 2
-  for (int it = 0; it < 200; ++it) {
+  for (int it = 0; it < kMleCap; ++it) {
+    if (iters) *iters = it + 1;
     const Z3 z = hurwitz3(a, xmin, ln);
     const double r1 = z.z1 / z.z0;
     const double g = -r1 - m;
@@ -440,7 +454,7 @@ ZPL_HD Z3 zeta3_trunc(double s, uint32_t K, const double* __restrict__ ln) {
 // is checked against mu at the edge, and when m has no root inside the
 // bracket the edge is returned with kFlagNoConv.
 ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ ln,
-                              uint32_t* flags) {
+                              uint32_t* flags, int* iters = nullptr) {
   double lo = -64.0, hi = 64.0;
   double a1 = 1.0 + 1.0 / (m + 0.5772156649015329);
   double a2 = log2(ln[2] / m);
@@ -449,7 +463,7 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
   const double lm = log(m);
   double gl = 0.0;  // the last residual of eq. 2
   int it = 0;
-  for (; it < 200; ++it) {
+  for (; it < kMleCap; ++it) {
     const Z3 z = zeta3_trunc(a, K, ln);
     const double mu = -z.z1 / z.z0;
     if (mu == m) break;
@@ -471,7 +485,8 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
   }
   // a residual within the rounding noise of mu is a root to FP64 precision
   // (near the edges the step test is out of reach), as for mle_alpha_hz
-  if (it == 200 && !(fabs(gl) <= 0x1p-44 * m)) *flags |= kFlagNoConv;
+  if (iters) *iters = it < kMleCap ? it + 1 : it;
+  if (it == kMleCap && !(fabs(gl) <= 0x1p-44 * m)) *flags |= kFlagNoConv;
   // Near an edge, is the root inside the bracket?  mu tends to ln K as s
   // falls, and for small K it reaches ln K to FP64 rounding well inside the
   // bracket (K = 2: from s of about -53 on), where an iterate can stop with

@@ -28,6 +28,15 @@ int64_t hm_tail(double alpha, uint64_t seed, uint32_t stream, uint32_t rep, uint
                    stream, flags);
 }
 double hm_mle(double m, uint32_t* flags) { return mle_alpha(m, g_ln.data(), flags); }
+double hm_mle_it(double m, uint32_t* flags, int* iters) {
+  return mle_alpha(m, g_ln.data(), flags, iters);
+}
+double hm_mle_trunc_it(double m, uint32_t K, uint32_t* flags, int* iters) {
+  return mle_alpha_trunc(m, K, g_ln.data(), flags, iters);
+}
+double hm_mle_hz_it(double m, int64_t xmin, uint32_t* flags, int* iters) {
+  return mle_alpha_hz(m, xmin, g_ln.data(), flags, iters);
+}
 void hm_zeta3(double s, double* out) {
   Z3 z = zeta3(s, g_ln.data());
   out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;

@@ -53,6 +53,10 @@ def hm(tmp_path_factory):
     L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
     L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
     L.hm_mle_trunc.restype = C.c_double
+    for f, args in [("hm_mle_it", [C.c_double]), ("hm_mle_trunc_it", [C.c_double, C.c_uint32]),
+                    ("hm_mle_hz_it", [C.c_double, C.c_int64])]:
+        getattr(L, f).argtypes = args + [P(C.c_uint32), P(C.c_int)]
+        getattr(L, f).restype = C.c_double
     return L
 
 
@@ -382,3 +386,53 @@ def test_noconv_agrees_near_the_edges(hm, orc):
             a = hm.hm_mle_trunc(m, K, C.byref(f))
             ao, fo = orc.tz_mle(m, K)
             assert f.value & 8 == fo & 8, (K, e, a, ao, f.value, fo)
+
+
+def test_both_solvers_reach_the_cap_and_agree(hm, orc):
+    """The three laws share one stopping rule on both sides: at most 200
+    Newton iterations, and NOCONV at that cap only when the last residual of
+    eq. 2 exceeds 2^-44 m.  Pinned where both the library's solver and the
+    oracle's run into the cap: close to the edge m -> ln K (truncated law,
+    K = 2..6) or m -> ln xmin (the law with a cutoff, xmin = 2..4), where an
+    FP64 mu fixes the root more coarsely than the step test.  There both
+    count exactly 200 iterations, neither flags NOCONV (the residual is
+    rounding noise), and the roots agree within the conditioning bound.  The
+    pure law's solver never reaches the cap over its whole range of m."""
+    eps = 2.0 ** -53
+    rng = np.random.default_rng(1)
+    both = 0
+    for K in (2, 3, 4, 5, 6):
+        lnK = math.log(K)
+        for e in rng.uniform(1, 17, 600):
+            m = lnK * (1 - 10.0 ** -e)
+            f, it = C.c_uint32(0), C.c_int(0)
+            a = hm.hm_mle_trunc_it(m, K, C.byref(f), C.byref(it))
+            ao, fo = orc.tz_mle(m, K)
+            io = orc.mle_last_iters()
+            assert it.value <= 200 and io <= 200
+            assert f.value & 8 == fo & 8, (K, m, a, ao)
+            if it.value == 200 and io == 200:
+                both += 1
+                assert fo & 8 == 0, (K, m)
+                assert abs(a - ao) <= max(1e-10 * max(abs(ao), 1.0),
+                                          4 * eps * m / _var_trunc(ao, K)), (K, m, a, ao)
+    for xmin in (2, 3, 4):
+        lx = math.log(xmin)
+        for d in 10 ** rng.uniform(-15, 1.2, 600):
+            f, it = C.c_uint32(0), C.c_int(0)
+            a = hm.hm_mle_hz_it(lx + d, xmin, C.byref(f), C.byref(it))
+            ao, fo = orc.hz_mle(lx + d, xmin)
+            io = orc.mle_last_iters()
+            assert f.value & 8 == fo & 8, (xmin, d, a, ao)
+            if it.value == 200 and io == 200:
+                both += 1
+                assert fo & 8 == 0, (xmin, d)
+                assert abs(a - ao) <= max(1e-10 * ao, 4 * eps * (lx + d) / _var_cut(ao, xmin)), \
+                    (xmin, d, a, ao)
+    assert both >= 20, both
+    for m in 10 ** rng.uniform(-12, math.log10(43.0), 3000):
+        f, it = C.c_uint32(0), C.c_int(0)
+        a = hm.hm_mle_it(m, C.byref(f), C.byref(it))
+        ao, fo = orc.mle(m)
+        assert it.value < 200 and orc.mle_last_iters() < 200, m
+        assert f.value & 8 == 0 and fo & 8 == 0, m
