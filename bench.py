@@ -32,8 +32,49 @@ QS = [(9, 10), (95, 100), (99, 100), (999, 1000)]
 OPS_PER_DRAW = 40 + 3 + 4 + 2
 # MLE (about 5 Newton steps of 17 exp-equivalents x 20 ops) + KS + sums.
 OPS_PER_REPLICATE = 2000
+# Each 32x32->64 multiply of Philox is counted as two full-rate lane-ops (a low
+# and a high product, one issue cycle per wave64 instruction on SIMD16 each).
+INT_MUL_NOTE = "32x32->64 multiply = 2 full-rate lane-ops (low and high product)"
 # VALU lane-op peak: 256 CUs x 64 lanes x 2.4 GHz.
 PEAK_OPS = 256 * 64 * 2.4e9
+# Heavy tails add, per replicate (expected counts under the law, see heavy_ops):
+# a tail draw (x > 4096: a Philox block for the proposal and about five FP64
+# transcendentals for the floored Pareto and its acceptance test);
+# a distinct value above 16 (the KS terms: one Euler-Maclaurin survival value,
+# one power, two terms); a value above the 1024-bin histogram (its FP64 log
+# for S above the 4097-entry log table, and its share of a comparison sort).
+OPS_TAIL_DRAW = 80 + 5 * 25
+OPS_KS_VALUE = 60 + 25 + 5
+OPS_OVERFLOW_LOG = 30
+OPS_COMPARE = 4
+
+
+def law_counts(alpha, n, kmax_sum=1 << 20):
+    """Expected per-replicate counts of n draws from p(k) = k^-alpha/zeta(alpha):
+    distinct values above 16, values above 1024 and above 4096 (the head summed
+    directly, the far tail by n p(k) through the Hurwitz zeta)."""
+    import numpy as np
+    from scipy.special import zeta
+    z = zeta(alpha, 1)
+    k = np.arange(1, kmax_sum + 1, dtype=np.float64)
+    p = k ** -alpha / z
+    present = -np.expm1(n * np.log1p(-p))  # 1 - (1 - p)^n
+    distinct16 = present[16:].sum() + n * zeta(alpha, kmax_sum + 1) / z
+    above = lambda h: n * zeta(alpha, h + 1) / z  # noqa: E731
+    return {"distinct_above_16": float(distinct16), "above_1024": float(above(1024)),
+            "above_4096": float(above(4096))}
+
+
+def heavy_ops(alpha, n):
+    """Algorithmic lane-ops of one replicate in the heavy-tail regime: the
+    headline model (draws and the fixed MLE/KS share) plus the expected tail
+    draws, KS values above 16 and overflow values (log and sort comparisons)."""
+    import math
+    c = law_counts(alpha, n)
+    m = c["above_1024"]
+    return (n * OPS_PER_DRAW + OPS_PER_REPLICATE + c["above_4096"] * OPS_TAIL_DRAW
+            + c["distinct_above_16"] * OPS_KS_VALUE
+            + m * (OPS_OVERFLOW_LOG + OPS_COMPARE * max(math.log2(max(m, 2.0)), 1.0)))
 # Autotuning grid: the table's exponents x sample sizes spanning 10..1e5.
 TUNE_ALPHAS = [1.5 + 0.25 * i for i in range(9)]
 TUNE_NS = [10, 30, 100, 300, 1000, 3000, 10000, 30000, 100000]
@@ -44,6 +85,7 @@ def progress(msg):
 
 
 PROFILE = ROOT / "profiles" / "k_simulate_table_n1000.md"
+HEAVY_PROFILE = ROOT / "profiles" / "k_heavy_heavy_tail.md"
 KERNEL_SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
                   "paper_1305_6738_amd/csrc/zpl_math.hpp"]
 
@@ -56,23 +98,44 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the simulation kernel from the committed
+def _profile_fields(path):
+    """key: value lines of a committed profile summary, or {} when the kernel
+    sources changed since it was taken."""
+    if not path.exists():
+        return {}
+    vals = {}
+    for line in path.read_text().splitlines():
+        if ":" in line and line.split(":", 1)[0].replace("_", "").isalnum() and \
+                not line.startswith("|"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return {}
+    return vals
+
+
+def profiled_traffic(path=None):
+    """HBM bytes per launch of the profiled kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of
     known size), or None when the kernel sources changed since it was taken."""
-    if not PROFILE.exists():
-        return None
-    vals = {}
-    for line in PROFILE.read_text().splitlines():
-        if line.startswith("traffic_bytes_per_launch:") or line.startswith("kernel_source_sha256:"):
-            k, v = line.split(":", 1)
-            vals[k] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
-        return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(_profile_fields(path or PROFILE)["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def profiled_counters(path=None):
+    """Measured fractions of the committed profile (current sources only):
+    VALU busy at the measured clock, executed VALU lane-instructions per
+    second against the lane-op peak, FP64 FLOP rate against 78.6 TFLOP/s."""
+    v = _profile_fields(path or PROFILE)
+    out = {}
+    for k in ("valu_busy", "valu_lane_inst_frac", "fp64_frac", "clock_ghz", "waves_per_simd"):
+        try:
+            out["measured_" + k] = float(v[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def percentile(v, p):
@@ -80,31 +143,51 @@ def percentile(v, p):
     return float(np.percentile(np.asarray(v), p)) if len(v) else None
 
 
-def cpu_baseline(cells, target_s=15.0):
-    """The oracle on a bounded sample of the same cells (all host cores):
-    the first replicates of every cell, sized by a pilot run to take about
-    target_s seconds (at most the whole workload)."""
+def cpu_model():
+    """The host CPU's model name (first "model name" line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(cells, target_s=12.0, single_s=6.0):
+    """The oracle on a bounded sample of the same cells, on every host core
+    and on one thread: the first replicates of every cell, each run sized by
+    a pilot to take about target_s (all cores) or single_s (one thread)
+    seconds, at most the whole workload."""
     import oracle
     oracle.build(force=False)
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    pilot = 256
-    t0 = time.perf_counter()
-    for (a, n, R, seed, st) in cells:
-        oracle.simulate(a, n, seed, st, 0, pilot, nthreads=cores)
-    tp = time.perf_counter() - t0
     rmax = min(c[2] for c in cells)
-    reps = int(max(pilot, min(rmax, pilot * target_s / max(tp, 1e-3))))
-    t0 = time.perf_counter()
-    for (a, n, R, seed, st) in cells:
-        oracle.simulate(a, n, seed, st, 0, reps, nthreads=cores)
-    dt = time.perf_counter() - t0
+
+    def timed(threads, budget_s, pilot):
+        t0 = time.perf_counter()
+        for (a, n, R, seed, st) in cells:
+            oracle.simulate(a, n, seed, st, 0, pilot, nthreads=threads)
+        tp = time.perf_counter() - t0
+        reps = int(max(pilot, min(rmax, pilot * budget_s / max(tp, 1e-3))))
+        t0 = time.perf_counter()
+        for (a, n, R, seed, st) in cells:
+            oracle.simulate(a, n, seed, st, 0, reps, nthreads=threads)
+        return reps, time.perf_counter() - t0
+
+    reps, dt = timed(cores, target_s, 256)
+    reps1, dt1 = timed(1, single_s, 16)
     return {"value": len(cells) * reps / dt, "unit": "replicates/s", "cores": cores,
             "kind": "oracle",
-            "sample": "first %d replicates of each of the %d cells (%.1f s on %d threads)"
-                      % (reps, len(cells), dt, cores)}
+            "sample": "first %d replicates of each of the %d cells (%.1f s on %d threads); "
+                      "single thread: first %d of each (%.1f s)"
+                      % (reps, len(cells), dt, cores, reps1, dt1),
+            "single_thread_value": len(cells) * reps1 / dt1,
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def fit_latency(ctx, n_req=200):
@@ -119,13 +202,14 @@ def fit_latency(ctx, n_req=200):
             "what": "zpl_fit of a host int64 dataset (n log-uniform 50..1e5), H2D included"}
 
 
-def serving(ctx, qps=200.0, seconds=10.0, B=2500):
+def serving(ctx, qps=200.0, seconds=60.0, B=2500, budget=8 << 30, max_batch=0, seed=7):
     """Poisson request stream served with continuous batching (zpl_serve_*):
     each request fits its dataset and returns a B-replicate bootstrap p-value.
-    Latency is measured by the library from submit to results ready."""
+    Latency and queueing are measured by the library from submit to results
+    ready (queue: submit to admission)."""
     from inputs import serving_requests
-    reqs = serving_requests(duration_s=seconds, qps=qps, seed=7)
-    ctx.serve_start(mem_budget_bytes=8 << 30)
+    reqs = serving_requests(duration_s=seconds, qps=qps, seed=seed)
+    ctx.serve_start(mem_budget_bytes=budget, max_batch=max_batch)
     tickets = []
     t0 = time.perf_counter()
     try:
@@ -134,7 +218,7 @@ def serving(ctx, qps=200.0, seconds=10.0, B=2500):
             if ta > now:
                 time.sleep(ta - now)
             tickets.append(ctx.serve_submit(x, B, seed=k, stream_id=k))
-        lat, qms, bs, bad = [], [], [], 0
+        lat, qms, bs, launches, bad = [], [], [], [], 0
         for t in tickets:
             r = ctx.serve_poll(t, wait_ms=120000)
             if r is None or r["status"] != 0:
@@ -143,15 +227,20 @@ def serving(ctx, qps=200.0, seconds=10.0, B=2500):
             lat.append(r["latency_ms"])
             qms.append(r["queue_ms"])
             bs.append(r["batch_size"])
+            launches.append(r["launches"])
         elapsed = time.perf_counter() - t0
     finally:
         ctx.serve_stop()
-    return {"qps_offered": qps, "requests": len(tickets), "failed": bad,
+    return {"qps_offered": qps, "seconds": seconds, "requests": len(tickets), "failed": bad,
             "sustained_qps": len(tickets) / elapsed, "B": B,
+            "budget_bytes": budget, "max_active": max_batch or 256,
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-            "queue_p50_ms": percentile(qms, 50), "mean_batch": sum(bs) / max(len(bs), 1),
-            "what": "Poisson 200/s, n log-uniform 50..1e5 (90% Zipf, 10% lognormal), "
-                    "fit + B=2500 bootstrap per request, continuous batching"}
+            "queue_p50_ms": percentile(qms, 50), "queue_p99_ms": percentile(qms, 99),
+            "queued_over_1ms": int(sum(1 for q in qms if q > 1.0)),
+            "mean_batch": sum(bs) / max(len(bs), 1),
+            "mean_launches": sum(launches) / max(len(launches), 1),
+            "what": "Poisson %g/s, n log-uniform 50..1e5 (90%% Zipf, 10%% lognormal), "
+                    "fit + B=%d bootstrap per request, continuous batching" % (qps, B)}
 
 
 def config_runs(ctx, stream, torch):
@@ -179,11 +268,31 @@ def config_runs(ctx, stream, torch):
         ctx.simulate_cells(cells, quantiles=QS, stream=stream)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
+        tm = ctx.timing()
         draws = sum(c[1] * c[2] for c in cells)
         out[name] = {"what": what, "cells": len(cells), "replicates": R, "ms": ms,
-                     "replicates_per_s": R / (ms / 1e3), "draws_per_s": draws / (ms / 1e3)}
+                     "replicates_per_s": R / (ms / 1e3), "draws_per_s": draws / (ms / 1e3),
+                     "kernel_ms": tm}
+        if name == "heavy_tail":
+            out[name]["roofline"] = heavy_roofline(cells, tm)
         progress("%s: %.1f ms" % (name, ms))
     return out
+
+
+def heavy_roofline(cells, tm):
+    """Roofline of the heavy-tail configuration: the heavy_ops model over
+    every replicate against the simulation launches' time (HIP events: the
+    lane/wave launch plus the heavy launch, which runs most of these cells),
+    and the counters of the committed k_heavy profile while it is current."""
+    ops = sum(R * heavy_ops(a, n) for (a, n, R, s, st) in cells)
+    sec = (tm["simulate"] + tm["heavy"]) / 1e3
+    r = {"bound": "alu", "achieved": ops / sec / 1e12, "peak": PEAK_OPS / 1e12,
+         "unit": "Tops/s", "frac": ops / sec / PEAK_OPS, "kernel": "k_heavy",
+         "kernel_ms": tm["heavy"], "simulate_ms": tm["simulate"], "ops_per_launch": ops,
+         "traffic": profiled_traffic(HEAVY_PROFILE),
+         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)"}
+    r.update(profiled_counters(HEAVY_PROFILE))
+    return r
 
 
 PAPER_NS = [10, 20, 30, 40, 50, 100, 500, 1000, 2000, 3000, 4000, 5000, 10000, 20000, 50000]
@@ -278,11 +387,14 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-tables", action="store_true",
                     help="skip the timed run of all six tables at the paper's size")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--tune", default="measure",
                     help="'measure' (autotune before timing), 'none' (built-in rule) or "
                          "the path of a saved tuning table")
     ap.add_argument("--tune-out", default=None, help="save the measured tuning table here")
+    ap.add_argument("--workload", default="table_n1000", choices=["table_n1000", "heavy_tail"],
+                    help="cells of the timed region: the headline n = 1000 table slice, or "
+                         "the heavy tails (alpha 1.2..1.5, n = 10,000; for profiling k_heavy)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device once (a kernel of known "
                          "traffic that scales the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -304,7 +416,11 @@ def main(argv=None):
         torch.empty_like(src).copy_(src)
         torch.cuda.synchronize()
         progress("copy probe: %d MiB" % args.copy_probe_mib)
-    cells = table_slice(n=1000, R=args.replicates)
+    if args.workload == "heavy_tail":
+        from inputs import heavy_tail
+        cells = heavy_tail(R=args.replicates)
+    else:
+        cells = table_slice(n=1000, R=args.replicates)
     total_R = sum(c[2] for c in cells)
     ctx = Context(0)
     d = torch.empty(total_R, dtype=torch.float64, device="cuda")
@@ -345,21 +461,29 @@ def main(argv=None):
 
     # dominant kernel: the persistent simulation launch
     sim_avg_ms = sum(sim_ms) / len(sim_ms)
-    ops = sum(R * (n * OPS_PER_DRAW + OPS_PER_REPLICATE) for (a, n, R, s, st) in cells)
-    achieved = ops / (sim_avg_ms / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / PEAK_OPS, "traffic": profiled_traffic(),
-                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                "kernel": "k_simulate", "kernel_ms": sim_avg_ms,
-                "ops_per_launch": ops}
+    if args.workload == "heavy_tail":
+        roofline = heavy_roofline(cells, {k: sum(t[k] for t in all_ms) / len(all_ms)
+                                          for k in all_ms[0]})
+    else:
+        ops = sum(R * (n * OPS_PER_DRAW + OPS_PER_REPLICATE) for (a, n, R, s, st) in cells)
+        achieved = ops / (sim_avg_ms / 1e3)
+        roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
+                    "unit": "Tops/s", "frac": achieved / PEAK_OPS, "traffic": profiled_traffic(),
+                    "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                    "kernel": "k_simulate", "kernel_ms": sim_avg_ms,
+                    "ops_per_launch": ops, "int_multiply_rate": INT_MUL_NOTE}
+        roofline.update(profiled_counters(PROFILE))
 
     out = {"metric": METRIC, "value": value, "unit": "replicates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": "full-table slice n=1000: alpha 1.5..3.5 step 0.25 (9 cells) "
-                                  "x R=%d, seed 42, batched persistent launch" % args.replicates,
-                      "n": 1000, "cells": len(cells), "replicates_per_cell": args.replicates,
+           "config": {"workload": ("full-table slice n=1000: alpha 1.5..3.5 step 0.25 (9 cells) "
+                                   "x R=%d, seed 42, batched persistent launch" % args.replicates)
+                      if args.workload == "table_n1000" else
+                      ("heavy tails: alpha 1.2, 1.3, 1.4, 1.5 x n=10000 x R=%d, seed 42, "
+                       "batched persistent launch (profiling workload)" % args.replicates),
+                      "n": cells[0][1], "cells": len(cells), "replicates_per_cell": args.replicates,
                       "quantiles": ["%d/%d" % qq for qq in QS], "launch": "batched"},
            "kernel_ms": {k: sum(t[k] for t in all_ms) / len(all_ms) for k in all_ms[0]},
            "tuning": tuning,
@@ -413,6 +537,14 @@ def main(argv=None):
             out["serving"] = serving(ctx, seconds=args.serve_seconds)
             progress("serving: p50 %.2f ms p99 %.2f ms" % (out["serving"]["p50_ms"],
                                                           out["serving"]["p99_ms"]))
+            # a load point where admission throttles: five times the rate,
+            # 16 active slots and a 32 MiB budget (a request of 1e5 values
+            # needs about 4.4 MB of fit memory, so only a few fit at once)
+            out["serving_throttled"] = serving(ctx, qps=1000.0, seconds=8.0, budget=32 << 20,
+                                               max_batch=16, seed=8)
+            progress("serving (throttled): p50 %.2f ms p99 %.2f ms queue p99 %.2f ms" % (
+                out["serving_throttled"]["p50_ms"], out["serving_throttled"]["p99_ms"],
+                out["serving_throttled"]["queue_p99_ms"]))
         out["quantiles_first_cell"] = [float(v) for v in q[0]]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cells)

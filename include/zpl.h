@@ -253,44 +253,61 @@ zpl_status zpl_bootstrap_pvalue(zpl_ctx *ctx, const int64_t *x, int64_t n,
                                 double *p_value, uint32_t *flags, void *stream);
 
 /* --------------------------------------------------------------------------
- * Serving: parametric-bootstrap requests (zpl_bootstrap_pvalue's computation)
- * under continuous batching.  A scheduler thread admits queued requests while
- * their device memory fits mem_budget_bytes, fits all admitted datasets in
- * one launch and runs all of their bootstraps as the cells of one batched
- * simulation; requests submitted meanwhile join the next iteration.  A
- * request's result is bit-identical to zpl_bootstrap_pvalue on the same
- * (x, B, seed, stream_id), whatever it is batched with.
+ * Serving: parametric-bootstrap requests (zpl_bootstrap_pvalue's computation,
+ * Sect. 4's bespoke cutoff) under continuous batching.  A scheduler thread
+ * admits queued requests, oldest first, as active slots and device memory
+ * free up; fits each admitted dataset (eq. 2 and eq. 3) once; and then runs
+ * the bootstraps of every active request together: each simulation launch
+ * holds a window of replicates of every active request, the windows sized so
+ * that a launch is about one time slice of work shared equally between the
+ * requests.  A request that arrives while a launch runs joins the next one,
+ * so its work shares the device with the bootstraps already in flight and a
+ * short request is not held behind a long one; a request completes as soon
+ * as its last window has run.  A request's result is bit-identical to
+ * zpl_bootstrap_pvalue on the same (x, B, seed, stream_id), whatever it
+ * shares the launches with.
  * ------------------------------------------------------------------------ */
 typedef struct zpl_serve_opts {
-  uint64_t mem_budget_bytes; /* device memory per iteration (0 = 8 GiB)        */
-  int32_t max_batch;         /* requests per iteration (0 = 256)               */
+  uint64_t mem_budget_bytes; /* device memory of the active requests (0 = 8 GiB;
+                                at most the context's budget): 8 bytes per
+                                bootstrap replicate while active, plus the
+                                fit's dataset and scratch while it runs      */
+  int32_t max_batch;         /* active requests at once (0 = 256)             */
   int32_t max_queue;         /* queued requests before submit says BUSY (0 = 65536) */
-  int32_t reserved;          /* must be 0                                      */
+  int32_t slice_us;          /* target work per simulation launch, microseconds
+                                of the whole device (0 = 4000)               */
   int32_t reserved2;         /* must be 0                                      */
 } zpl_serve_opts;
 
 typedef struct zpl_serve_result {
   int32_t done;        /* 0: still queued or running; 1: fields below valid     */
-  zpl_status status;   /* ZPL_OK, ZPL_EINVAL (some x < 1), ZPL_ENOMEM (request
-                          alone exceeds the budget), ZPL_EDEVICE              */
+  zpl_status status;   /* ZPL_OK, ZPL_EINVAL (some x < 1), ZPL_ENOCONV (alpha_hat
+                          below 1.01, no bootstrap), ZPL_ENOMEM (the request
+                          alone exceeds the budget), ZPL_EDEVICE             */
   double alpha_hat;    /* eq. (2)                                             */
   double D;            /* eq. (3)                                             */
   double p_value;      /* #{b : D_b >= D} / B                                 */
   uint32_t flags;      /* fit flags (ZPL_FLAG_*)                               */
-  int32_t batch_size;  /* requests in the iteration that served this one       */
-  double queue_ms;     /* submit -> start of its iteration                     */
+  int32_t batch_size;  /* most requests that shared a simulation launch with it */
+  double queue_ms;     /* submit -> admission                                  */
   double latency_ms;   /* submit -> results ready                              */
+  int32_t launches;    /* simulation launches that ran its replicates          */
+  int32_t reserved;
 } zpl_serve_result;
 
 /* Start the scheduler on this context (opts may be NULL).  The scheduler
- * uses its own internal context and stream; the caller may keep using ctx. */
+ * uses its own internal context and stream; the caller may keep using ctx.
+ * ZPL_EINVAL if the serving budget exceeds the context's. */
 zpl_status zpl_serve_start(zpl_ctx *ctx, const zpl_serve_opts *opts);
 
-/* Queue one request: x[n] host int64 (copied before return), B bootstrap
- * replicates, random stream (seed, stream_id).  *ticket identifies it.
- * ZPL_EBUSY when max_queue requests are already waiting. */
-zpl_status zpl_serve_submit(zpl_ctx *ctx, const int64_t *x, int64_t n, int64_t B,
-                            uint64_t seed, uint32_t stream_id, uint64_t *ticket);
+/* Queue one request: x[n] int64 in host memory (x_on_device = 0) or device
+ * memory (1), copied before the call returns (a device dataset to a device
+ * buffer of the scheduler's, where it stays until its fit; such copies are
+ * not charged to the budget while queued); B bootstrap replicates; random
+ * stream (seed, stream_id).  *ticket identifies it.  ZPL_EBUSY when max_queue
+ * requests are already waiting. */
+zpl_status zpl_serve_submit(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t x_on_device,
+                            int64_t B, uint64_t seed, uint32_t stream_id, uint64_t *ticket);
 
 /* Result of a request, waiting up to wait_ms for it (0 = do not wait).  A
  * completed result is returned once; the ticket is then released.

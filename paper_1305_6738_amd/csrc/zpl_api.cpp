@@ -378,8 +378,13 @@ uint32_t choose_form(double alpha, int64_t n, const Tuning* t, uint32_t K = 0, i
   return kModeHeavy;
 }
 
+// rlo (optional): cell i covers replicates rlo[i] .. rlo[i] + replicates - 1
+// (a window of a longer cell, as the serving scheduler runs them); its
+// outputs still start at the cell's prefix position in the per-replicate
+// arrays.  Without it every cell covers replicates 0 .. replicates - 1.
 zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
-                     const Tuning* tune = nullptr, int n_cu = 256) {
+                     const Tuning* tune = nullptr, int n_cu = 256,
+                     const int64_t* rlo = nullptr) {
   P = Plan();
   P.cells.resize(n_cells);
   P.cell_unit_begin.assign(n_cells, 0);
@@ -423,12 +428,14 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
     if (z.replicates < 1 || z.replicates > ((int64_t)1 << 32))
       return fail(ZPL_EINVAL, "cell %d: replicates must be in [1, 2^32], got %lld", i,
                   (long long)z.replicates);
+    if (rlo && (rlo[i] < 0 || rlo[i] + z.replicates > ((int64_t)1 << 32)))
+      return fail(ZPL_EINVAL, "cell %d: replicate window out of range", i);
     DevCell& d = P.cells[i];
     std::memset(&d, 0, sizeof d);
     d.alpha = z.alpha;
     d.n = z.n;
     d.R = z.replicates;
-    d.out_off = P.total_R;
+    d.out_off = P.total_R - (rlo ? rlo[i] : 0);  // output index = out_off + replicate
     d.k0 = (uint32_t)z.seed;
     d.k1 = (uint32_t)(z.seed >> 32);
     d.stream = z.stream;
@@ -474,10 +481,11 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
       const double v = d.K ? trunc_cost(d.n, d.K) : tuned_cost(*tune, (int)d.mode, d.alpha, d.n);
       if (v > 0.0) w = v;
     }
+    const int64_t r0 = rlo ? rlo[i] : 0;
     for (int64_t r = 0; r < d.R; r += per) {
       Unit u;
       u.cell = i;
-      u.r0 = r;
+      u.r0 = r0 + r;
       u.count = (int32_t)std::min<int64_t>(per, d.R - r);
       if (d.mode == kModeHeavy)
         P.hunits.push_back(u);
@@ -632,7 +640,7 @@ zpl_status check_err_word(zpl_ctx* c, hipStream_t s) {
 // bootstrap.  quantiles may be NULL.
 zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint32_t* q_num,
                      const uint32_t* q_den, int n_q, double* quantiles, Outputs out,
-                     const zpl_sim_opts* opts, hipStream_t s) {
+                     const zpl_sim_opts* opts, hipStream_t s, const int64_t* rlo = nullptr) {
   zpl_sim_opts o = {ZPL_LAUNCH_BATCHED, ZPL_FORM_AUTO, 0, 0};
   if (opts) o = *opts;
   if (o.launch != ZPL_LAUNCH_BATCHED && o.launch != ZPL_LAUNCH_PLAIN)
@@ -645,8 +653,10 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
   for (int i = 0; i < n_q; ++i)
     if (q_den[i] == 0 || q_num[i] >= q_den[i])
       return fail(ZPL_EINVAL, "quantile %d: need num < den (got %u/%u)", i, q_num[i], q_den[i]);
+  if (rlo && (o.use_graph || n_q > 0))
+    return fail(ZPL_EINVAL, "replicate windows run without graphs or quantiles");
   Plan P;
-  ZPL_TRY(make_plan(cells, n_cells, o.form, P, &c->tune, c->n_cu));
+  ZPL_TRY(make_plan(cells, n_cells, o.form, P, &c->tune, c->n_cu, rlo));
   if (o.launch == ZPL_LAUNCH_PLAIN) plain_unit_order(P);
   const bool need_sel = quantiles && n_q > 0;
   const bool need_dbuf = need_sel && out.D == nullptr;
@@ -863,14 +873,26 @@ zpl_status stage_x(zpl_ctx* c, const int64_t* x, int64_t n, int32_t on_dev, hipS
 // ===========================================================================
 // Serving: continuous batching of bootstrap p-value requests.
 //
-// A scheduler thread owns an internal context and stream.  Each iteration it
-// admits queued requests while their device memory fits the budget, fits all
-// of their datasets in one launch, runs all of their B-replicate bootstraps
-// as the cells of one batched simulation, counts D_b >= D_obs per request in
-// one launch, and publishes the results.  Requests arriving meanwhile wait
-// for the next iteration.  Every draw is a pure function of (seed, stream,
-// replicate), so a request's result does not depend on what it is batched
-// with.
+// A scheduler thread owns an internal context and stream.  Each iteration:
+//   1. admits queued requests, oldest first, while an active slot is free and
+//      their device memory fits the budget (the fit's dataset and scratch
+//      while it runs, and 8 bytes per bootstrap replicate until the request
+//      completes);
+//   2. fits the newly admitted datasets (eq. 2 and eq. 3) in one batched
+//      launch (one wavefront per dataset below 2,048 values, one workgroup per
+//      larger dataset);
+//   3. runs one window of replicates of every active request's bootstrap, all
+//      of them as the cells of one batched simulation, the windows sized so
+//      that the launch holds about one time slice of work shared equally
+//      between the requests (a request needing less than its share finishes
+//      in this launch and its share goes to the others);
+//   4. counts D_b >= D_obs in each window and completes every request whose
+//      last window ran.
+// A request that arrives while a launch runs joins the next one and shares
+// the device with the requests already in flight, so a short request is not
+// held behind a long bootstrap.  Every draw is a pure function of (seed,
+// stream, replicate) and each replicate runs exactly once, so a request's
+// result does not depend on what it shares the launches with.
 // ===========================================================================
 namespace {
 
@@ -878,7 +900,9 @@ using Clock = std::chrono::steady_clock;
 
 struct Req {
   uint64_t ticket = 0;
-  std::vector<int64_t> x;
+  std::vector<int64_t> x;    // host dataset (submitted from host memory)
+  int64_t* xdev = nullptr;   // device copy (submitted from device memory), stream-ordered
+  int64_t n = 0;
   int64_t B = 0;
   uint64_t seed = 0;
   uint32_t stream_id = 0;
@@ -887,13 +911,41 @@ struct Req {
   zpl_status status = ZPL_OK;
   double ahat = 0.0, D = 0.0, p = 0.0;
   uint32_t flags = 0;
-  int32_t batch_size = 0;
+  // scheduling state (scheduler thread only)
+  int64_t next = 0;          // first bootstrap replicate not yet run
+  uint64_t ge = 0;           // replicates so far with D_b >= D_obs
+  double cost = 0.0;         // estimated ns per replicate, device busy
+  size_t held = 0;           // bytes charged while active
+  int32_t mix = 0;           // most requests that shared a launch with it
+  int32_t launches = 0;      // simulation launches that ran its replicates
 };
 
-size_t req_bytes(const Req& r) {
-  // dataset + its overflow/list scratch + bootstrap D + table and guide
-  return (size_t)r.x.size() * 8 * 4 + (size_t)r.B * 8 + sizeof(double) * kH +
-         sizeof(uint16_t) * (kGuide + 1) + 4096;
+// Device memory a request holds while active: the D values of its
+// replicates in the slice buffer (at most all B of them in one launch).
+size_t held_bytes(const Req& r) { return (size_t)r.B * 8 + 4096; }
+
+// Transient device memory of fitting a set of datasets: the concatenated
+// data, the per-set descriptors and outputs, the one-wave fits' scratch
+// (one area per wavefront of the batched launch, each sized for the largest
+// small dataset) and one workgroup fit's scratch, reused by every large one.
+size_t fit_bytes(int64_t total_n, int n_sets, int64_t max_small, int n_small, int64_t max_large,
+                 int n_cu) {
+  size_t b = (size_t)total_n * 8 + (size_t)n_sets * 64 + 4096;
+  if (n_small > 0)
+    b += (size_t)std::min(n_small, 2 * n_cu) * (size_t)heavy_stride(max_small) * 8;
+  if (max_large > 0) b += (size_t)heavy_stride(max_large) * 8;
+  return b;
+}
+
+// Estimated cost of one bootstrap replicate (ns with the device busy): the
+// tuned cost of the cheapest eligible form when a table is installed, else
+// about 2.2 ps per draw, more with heavy tails, and 2.5 ns per replicate (a
+// fit to MI355X's tuned costs over the table's exponents and sizes).
+double replicate_cost(const zpl_ctx* c, double alpha, int64_t n) {
+  double v;
+  (void)choose_form(alpha, n, &c->tune, 0, 1, c->n_cu, -1.0, &v);
+  if (v > 0.0) return v;
+  return 2.2e-3 * (double)n * (1.0 + 90.0 * tail_prob(alpha, kHW)) + 2.5;
 }
 
 }  // namespace
@@ -901,9 +953,11 @@ size_t req_bytes(const Req& r) {
 struct Server {
   zpl_ctx* eng = nullptr;  // internal context used only by the scheduler thread
   hipStream_t stream = nullptr;
+  hipStream_t submit_stream = nullptr;  // device datasets are copied on it
   uint64_t budget = 8ull << 30;
-  int max_batch = 256;
+  int max_active = 256;
   int max_queue = 1 << 16;
+  double slice_ns = 4e6;   // target work per simulation launch
   std::thread th;
   std::mutex mu;
   std::condition_variable cv;
@@ -913,57 +967,127 @@ struct Server {
   bool stop = false;
   std::string fatal;  // scheduler error, reported by later calls
   uint64_t iterations = 0, served = 0;
+  size_t used = 0;    // bytes held by active requests (scheduler thread)
+  std::vector<Req*> active;
 
   void loop();
-  zpl_status process(std::vector<Req*>& batch);
+  zpl_status fit_fresh(std::vector<Req*>& fresh);
+  zpl_status run_slice(std::vector<Req*>& finished);
+  void complete(Req* r, zpl_status st);
 };
 
-zpl_status Server::process(std::vector<Req*>& batch) {
+// Publishes a result (caller holds no lock).
+void Server::complete(Req* r, zpl_status st) {
+  std::lock_guard<std::mutex> lk(mu);
+  r->status = st;
+  r->t_done = Clock::now();
+  r->done = true;
+  if (r->xdev) {
+    (void)hipFreeAsync(r->xdev, stream);
+    r->xdev = nullptr;
+  }
+  r->x.clear();
+  r->x.shrink_to_fit();
+  ++served;
+  cv.notify_all();
+}
+
+// Uploads and fits the newly admitted datasets; a request that fails here
+// (invalid values, no root) is completed at once, the others become active.
+zpl_status Server::fit_fresh(std::vector<Req*>& fresh) {
   zpl_ctx* c = eng;
   hipStream_t s = stream;
-  const int nb = (int)batch.size();
-  // 1. datasets -> device (one concatenated buffer)
-  int64_t total = 0, max_n = 1;
-  for (Req* r : batch) {
-    total += (int64_t)r->x.size();
-    max_n = std::max<int64_t>(max_n, (int64_t)r->x.size());
-  }
+  const int nb = (int)fresh.size();
+  int64_t total = 0;
+  for (Req* r : fresh) total += r->n;
+  // 1. datasets -> one device buffer (host data through pinned staging)
   const size_t pin_need = sizeof(int64_t) * (size_t)total + (sizeof(int64_t) * 2 + 64) * nb + 4096;
   ZPL_TRY(ensure_pinned(c, pin_need));
   HIP_TRY(hipStreamSynchronize(s));
   char* pin = (char*)c->pin;
   int64_t* px = (int64_t*)pin;
-  int64_t off = 0;
-  for (Req* r : batch) {
-    std::memcpy(px + off, r->x.data(), sizeof(int64_t) * r->x.size());
-    off += (int64_t)r->x.size();
-  }
   ZPL_TRY(ensure(c, c->fit_x, sizeof(int64_t) * (size_t)std::max<int64_t>(total, 1)));
-  HIP_TRY(hipMemcpyAsync(c->fit_x.p, px, sizeof(int64_t) * (size_t)total, hipMemcpyHostToDevice, s));
+  int64_t* fx = (int64_t*)c->fit_x.p;
+  int64_t off = 0;
+  for (Req* r : fresh) {
+    if (r->xdev)
+      HIP_TRY(hipMemcpyAsync(fx + off, r->xdev, sizeof(int64_t) * (size_t)r->n,
+                             hipMemcpyDeviceToDevice, s));
+    else
+      std::memcpy(px + off, r->x.data(), sizeof(int64_t) * (size_t)r->n);
+    off += r->n;
+  }
+  // host-submitted data: one copy of the staged runs (device runs are skipped)
+  off = 0;
+  for (int i = 0; i < nb;) {
+    if (fresh[i]->xdev) {
+      off += fresh[i]->n;
+      ++i;
+      continue;
+    }
+    int64_t run = 0;
+    const int64_t start = off;
+    while (i < nb && !fresh[i]->xdev) {
+      run += fresh[i]->n;
+      off += fresh[i]->n;
+      ++i;
+    }
+    HIP_TRY(hipMemcpyAsync(fx + start, px + start, sizeof(int64_t) * (size_t)run,
+                           hipMemcpyHostToDevice, s));
+  }
+  // 2. fits: small datasets one wavefront each in one launch, large ones a
+  //    workgroup each (the same bits as zpl_fit either way)
+  std::vector<int> small, large;
+  int64_t max_small = 1, max_large = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (fresh[i]->n >= kFitBlockMin) {
+      large.push_back(i);
+      max_large = std::max(max_large, fresh[i]->n);
+    } else {
+      small.push_back(i);
+      max_small = std::max(max_small, fresh[i]->n);
+    }
+  }
   int64_t* pptr = (int64_t*)(pin + sizeof(int64_t) * total);
   int64_t* pns = pptr + nb;
+  std::vector<int64_t> xoff(nb);
   off = 0;
   for (int i = 0; i < nb; ++i) {
-    pptr[i] = (int64_t)(intptr_t)((int64_t*)c->fit_x.p + off);
-    pns[i] = (int64_t)batch[i]->x.size();
-    off += pns[i];
+    xoff[i] = off;
+    off += fresh[i]->n;
+  }
+  for (size_t k = 0; k < small.size(); ++k) {
+    pptr[k] = (int64_t)(intptr_t)(fx + xoff[small[k]]);
+    pns[k] = fresh[small[k]]->n;
   }
   ZPL_TRY(ensure(c, c->fit_ptrs, sizeof(int64_t) * nb));
   ZPL_TRY(ensure(c, c->fit_ns, sizeof(int64_t) * nb));
   ZPL_TRY(ensure(c, c->fit_out, (sizeof(double) * 2 + sizeof(uint32_t) * 2) * nb));
   ZPL_TRY(ensure(c, c->fit_st, sizeof(uint32_t) * nb));
-  HIP_TRY(hipMemcpyAsync(c->fit_ptrs.p, pptr, sizeof(int64_t) * nb, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(c->fit_ns.p, pns, sizeof(int64_t) * nb, hipMemcpyHostToDevice, s));
-  // 2. batched fit
-  const int grid = std::min(nb, c->n_cu * 2);
-  const int64_t stride = heavy_stride(max_n);
-  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)stride * grid));
   double* fa = (double*)c->fit_out.p;
   double* fd = fa + nb;
   uint32_t* ff = (uint32_t*)(fd + nb);
-  HIP_TRY(launch_fit(grid, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p, nb,
-                     c->ln, (int64_t*)c->heavy.p, stride, fa, fd, ff, (uint32_t*)c->fit_st.p, 0u,
-                     s));
+  uint32_t* fs = (uint32_t*)c->fit_st.p;
+  const int ns_small = (int)small.size();
+  const int grid = std::min(ns_small, c->n_cu * 2);
+  const int64_t sstride = heavy_stride(max_small);
+  const int64_t lstride = max_large > 0 ? heavy_stride(max_large) : 0;
+  ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)std::max<int64_t>(
+                                  (int64_t)grid * sstride, std::max<int64_t>(lstride, 1))));
+  if (ns_small > 0) {
+    HIP_TRY(hipMemcpyAsync(c->fit_ptrs.p, pptr, sizeof(int64_t) * ns_small,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c->fit_ns.p, pns, sizeof(int64_t) * ns_small, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_fit(grid, (const int64_t* const*)c->fit_ptrs.p, (const int64_t*)c->fit_ns.p,
+                       ns_small, c->ln, (int64_t*)c->heavy.p, sstride, fa, fd, ff, fs, 0u, s));
+  }
+  // large ones after the small ones' outputs, sharing one scratch area
+  for (size_t k = 0; k < large.size(); ++k) {
+    const int o = ns_small + (int)k;
+    const int i = large[k];
+    HIP_TRY(launch_fit_block(fx + xoff[i], fresh[i]->n, c->ln, (int64_t*)c->heavy.p,
+                             heavy_stride(fresh[i]->n), fa + o, fd + o, ff + o, fs + o, 0u, s));
+  }
   double* ha = (double*)(pns + nb);
   double* hd = ha + nb;
   uint32_t* hf = (uint32_t*)(hd + nb);
@@ -971,59 +1095,115 @@ zpl_status Server::process(std::vector<Req*>& batch) {
   HIP_TRY(hipMemcpyAsync(ha, fa, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(hd, fd, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(hf, ff, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(hs, c->fit_st.p, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hs, fs, sizeof(uint32_t) * nb, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // 3. one batched simulation over every valid request's bootstrap cell
-  std::vector<zpl_cell> cells;
-  std::vector<int> owner;
-  std::vector<double> dobs;
-  for (int i = 0; i < nb; ++i) {
-    Req* r = batch[i];
-    r->ahat = ha[i];
-    r->D = hd[i];
-    r->flags = hf[i];
-    if (hs[i] != 0u) {
-      r->status = ZPL_EINVAL;
+  // outputs are in small-then-large order
+  std::vector<int> order(small);
+  order.insert(order.end(), large.begin(), large.end());
+  for (int o = 0; o < nb; ++o) {
+    Req* r = fresh[order[o]];
+    r->ahat = ha[o];
+    r->D = hd[o];
+    r->flags = hf[o];
+    if (r->xdev) {
+      (void)hipFreeAsync(r->xdev, s);
+      r->xdev = nullptr;
+    }
+    r->x.clear();
+    r->x.shrink_to_fit();
+    if (hs[o] != 0u) {
+      used -= r->held;
+      complete(r, ZPL_EINVAL);
       continue;
     }
-    if (!(ha[i] >= kMinAlpha)) {
-      r->status = ZPL_ENOCONV;
+    if (!(r->ahat >= kMinAlpha)) {
+      used -= r->held;
+      complete(r, ZPL_ENOCONV);
       continue;
     }
-    cells.push_back(zpl_cell{ha[i], (int64_t)r->x.size(), r->B, r->seed, r->stream_id, 0});
-    owner.push_back(i);
-    dobs.push_back(hd[i]);
+    r->cost = replicate_cost(c, r->ahat, r->n);
+    active.push_back(r);
   }
-  if (!cells.empty()) {
-    const int nc = (int)cells.size();
-    int64_t sumB = 0, maxB = 1;
-    for (const zpl_cell& z : cells) {
-      sumB += z.replicates;
-      maxB = std::max(maxB, z.replicates);
-    }
-    ZPL_TRY(ensure(c, c->boot_d, sizeof(double) * (size_t)sumB));
-    Outputs out{(double*)c->boot_d.p, nullptr, nullptr, nullptr, nullptr};
-    ZPL_TRY(run_cells(c, cells.data(), nc, nullptr, nullptr, 0, nullptr, out, nullptr, s));
-    // 4. counts of D_b >= D_obs per cell
-    ZPL_TRY(ensure(c, c->count, (sizeof(unsigned long long) + sizeof(double)) * nc));
-    unsigned long long* cnt = (unsigned long long*)c->count.p;
-    double* ddev = (double*)(cnt + nc);
-    HIP_TRY(hipStreamSynchronize(s));  // the plan upload used the staging area
-    double* pd = (double*)c->pin;
-    std::memcpy(pd, dobs.data(), sizeof(double) * nc);
-    HIP_TRY(hipMemcpyAsync(ddev, pd, sizeof(double) * nc, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_fill_u32((uint32_t*)cnt, 2 * nc, 0u, s));
-    HIP_TRY(launch_count_cells((const double*)c->boot_d.p, (const DevCell*)c->cells.p, nc, ddev,
-                               cnt, maxB, s));
-    unsigned long long* hc = (unsigned long long*)(pd + nc);
-    HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(unsigned long long) * nc, hipMemcpyDeviceToHost, s));
-    ZPL_TRY(check_err_word(c, s));
-    for (int k = 0; k < nc; ++k) {
-      Req* r = batch[owner[k]];
-      r->p = (double)hc[k] / (double)r->B;
-      r->status = ZPL_OK;
-    }
+  return ZPL_OK;
+}
+
+// One simulation launch over a window of every active request's bootstrap,
+// then the counts; requests whose last window ran go to `finished`.
+zpl_status Server::run_slice(std::vector<Req*>& finished) {
+  zpl_ctx* c = eng;
+  hipStream_t s = stream;
+  const int na = (int)active.size();
+  // windows: the slice's work shared equally, smallest remaining first (a
+  // request needing less than its share leaves the rest to the others)
+  std::vector<int> ord(na);
+  for (int i = 0; i < na; ++i) ord[i] = i;
+  auto rem_work = [&](int i) { return (double)(active[i]->B - active[i]->next) * active[i]->cost; };
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return rem_work(a) < rem_work(b); });
+  std::vector<int64_t> win(na, 0);
+  double budget = slice_ns;
+  for (int k = 0; k < na; ++k) {
+    const int i = ord[k];
+    Req* r = active[i];
+    const double share = budget / (double)(na - k);
+    const double take = std::min(rem_work(i), share);
+    budget -= take;
+    int64_t w = (int64_t)std::ceil(take / std::max(r->cost, 1e-9));
+    w = std::max<int64_t>(1, std::min<int64_t>(w, r->B - r->next));
+    win[i] = w;
   }
+  std::vector<zpl_cell> cells(na);
+  std::vector<int64_t> rlo(na), base(na);
+  int64_t total = 0;
+  for (int i = 0; i < na; ++i) {
+    Req* r = active[i];
+    cells[i] = zpl_cell{r->ahat, r->n, win[i], r->seed, r->stream_id, 0, 0};
+    rlo[i] = r->next;
+    base[i] = total;
+    total += win[i];
+  }
+  ZPL_TRY(ensure(c, c->boot_d, sizeof(double) * (size_t)total));
+  Outputs out{(double*)c->boot_d.p, nullptr, nullptr, nullptr, nullptr};
+  ZPL_TRY(run_cells(c, cells.data(), na, nullptr, nullptr, 0, nullptr, out, nullptr, s,
+                    rlo.data()));
+  // counts of D_b >= D_obs per window: cells {out_off = window start, R = window}
+  ZPL_TRY(ensure(c, c->count, (sizeof(unsigned long long) + sizeof(double)) * na +
+                                  sizeof(DevCell) * na + 64));
+  unsigned long long* cnt = (unsigned long long*)c->count.p;
+  double* ddev = (double*)(cnt + na);
+  DevCell* ccells = (DevCell*)(ddev + na);
+  HIP_TRY(hipStreamSynchronize(s));  // the plan upload used the staging area
+  ZPL_TRY(ensure_pinned(c, (sizeof(double) + sizeof(unsigned long long)) * na +
+                               sizeof(DevCell) * na + 64));
+  double* pd = (double*)c->pin;
+  DevCell* pc = (DevCell*)(pd + na);
+  unsigned long long* hc = (unsigned long long*)(pc + na);
+  int64_t maxw = 1;
+  for (int i = 0; i < na; ++i) {
+    pd[i] = active[i]->D;
+    std::memset(&pc[i], 0, sizeof(DevCell));
+    pc[i].out_off = base[i];
+    pc[i].R = win[i];
+    maxw = std::max(maxw, win[i]);
+  }
+  HIP_TRY(hipMemcpyAsync(ddev, pd, sizeof(double) * na, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ccells, pc, sizeof(DevCell) * na, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_fill_u32((uint32_t*)cnt, 2 * na, 0u, s));
+  HIP_TRY(launch_count_cells((const double*)c->boot_d.p, ccells, na, ddev, cnt, maxw, s));
+  HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(unsigned long long) * na, hipMemcpyDeviceToHost, s));
+  ZPL_TRY(check_err_word(c, s));  // synchronises the stream
+  std::vector<Req*> still;
+  for (int i = 0; i < na; ++i) {
+    Req* r = active[i];
+    r->ge += hc[i];
+    r->next += win[i];
+    r->launches += 1;
+    r->mix = std::max(r->mix, na);
+    if (r->next >= r->B)
+      finished.push_back(r);
+    else
+      still.push_back(r);
+  }
+  active.swap(still);
   return ZPL_OK;
 }
 
@@ -1035,54 +1215,109 @@ void Server::loop() {
     stop = true;
   }
   for (;;) {
-    std::vector<Req*> batch;
+    std::vector<Req*> fresh;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop || !queue.empty(); });
-      if (queue.empty() && stop) break;
-      size_t mem = 0;
-      while (!queue.empty() && (int)batch.size() < max_batch) {
-        Req* r = queue.front();
-        const size_t m = req_bytes(*r);
-        if (!batch.empty() && mem + m > budget) break;  // admitted next iteration
-        queue.pop_front();
-        if (m > budget) {
-          r->status = ZPL_ENOMEM;
-          r->done = true;
-          r->t_done = Clock::now();
-          continue;
-        }
-        batch.push_back(r);
-        mem += m;
-      }
+      if (active.empty()) cv.wait(lk, [&] { return stop || !queue.empty(); });
+      if (queue.empty() && active.empty() && stop) break;
       if (!fatal.empty()) {
-        for (Req* r : batch) {
+        // no device work after a fatal error: fail everything still here
+        std::vector<Req*> all(queue.begin(), queue.end());
+        all.insert(all.end(), active.begin(), active.end());
+        queue.clear();
+        active.clear();
+        for (Req* r : all) {
           r->status = ZPL_EDEVICE;
-          r->done = true;
           r->t_done = Clock::now();
+          r->done = true;
         }
         cv.notify_all();
+        if (stop) break;
         continue;
       }
+      // admission: oldest first, while a slot is free and the memory the
+      // request holds plus the admitted fits' transient memory fit
+      int64_t tot = 0, ms = 1, ml = 0;
+      int nsml = 0;
+      while (!queue.empty() && (int)(active.size() + fresh.size()) < max_active) {
+        Req* r = queue.front();
+        const int64_t t2 = tot + r->n;
+        const bool lg = r->n >= kFitBlockMin;
+        const int64_t ms2 = lg ? ms : std::max(ms, r->n), ml2 = lg ? std::max(ml, r->n) : ml;
+        const int ns2 = nsml + (lg ? 0 : 1);
+        const size_t h = held_bytes(*r);
+        const size_t need = used + h +
+                            fit_bytes(t2, (int)fresh.size() + 1, ms2, ns2, ml2, eng->n_cu);
+        const size_t alone = h + fit_bytes(r->n, 1, lg ? 1 : r->n, lg ? 0 : 1, lg ? r->n : 0,
+                                           eng->n_cu);
+        if (alone > budget) {  // can never be admitted
+          queue.pop_front();
+          r->status = ZPL_ENOMEM;
+          r->t_done = Clock::now();
+          r->done = true;
+          if (r->xdev) {
+            (void)hipFreeAsync(r->xdev, stream);
+            r->xdev = nullptr;
+          }
+          cv.notify_all();
+          continue;
+        }
+        if (need > budget) break;  // admitted when memory frees up
+        queue.pop_front();
+        r->held = h;
+        used += h;
+        r->t_start = Clock::now();
+        fresh.push_back(r);
+        tot = t2;
+        ms = ms2;
+        ml = ml2;
+        nsml = ns2;
+      }
     }
-    if (batch.empty()) continue;
-    const Clock::time_point t0 = Clock::now();
-    for (Req* r : batch) r->t_start = t0;
-    const zpl_status st = process(batch);
-    std::lock_guard<std::mutex> lk(mu);
-    const Clock::time_point t1 = Clock::now();
-    if (st != ZPL_OK) fatal = "serving: " + g_err;
-    for (Req* r : batch) {
-      if (st != ZPL_OK) r->status = st;
-      r->batch_size = (int32_t)batch.size();
-      r->t_done = t1;
-      r->done = true;
+    zpl_status st = ZPL_OK;
+    if (!fresh.empty()) {
+      st = fit_fresh(fresh);
+      if (st == ZPL_ENOMEM) {  // only these requests fail
+        for (Req* r : fresh)
+          if (!r->done && std::find(active.begin(), active.end(), r) == active.end()) {
+            used -= r->held;
+            complete(r, ZPL_ENOMEM);
+          }
+        st = ZPL_OK;
+      }
     }
-    ++iterations;
-    served += batch.size();
-    cv.notify_all();
+    std::vector<Req*> finished;
+    if (st == ZPL_OK && !active.empty()) {
+      st = run_slice(finished);
+      if (st == ZPL_ENOMEM) {  // the launch did not fit: fail the active requests only
+        std::vector<Req*> failed;
+        failed.swap(active);
+        for (Req* r : failed) {
+          used -= r->held;
+          complete(r, ZPL_ENOMEM);
+        }
+        st = ZPL_OK;
+      }
+    }
+    for (Req* r : finished) {
+      used -= r->held;
+      r->p = (double)r->ge / (double)r->B;
+      complete(r, ZPL_OK);
+    }
+    if (st != ZPL_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      fatal = "serving: " + g_err;
+      cv.notify_all();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      ++iterations;
+    }
   }
-  if (stream) (void)hipStreamDestroy(stream);
+  if (stream) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipStreamDestroy(stream);
+  }
 }
 
 // ===========================================================================
@@ -1422,24 +1657,37 @@ zpl_status zpl_serve_start(zpl_ctx* c, const zpl_serve_opts* opts) {
   if (c->server) return fail(ZPL_EINVAL, "serving already started on this context");
   zpl_serve_opts o = {0, 0, 0, 0, 0};
   if (opts) o = *opts;
-  if (o.reserved != 0 || o.reserved2 != 0) return fail(ZPL_EINVAL, "opts.reserved must be 0");
+  if (o.reserved2 != 0) return fail(ZPL_EINVAL, "opts.reserved2 must be 0");
+  if (o.slice_us < 0 || o.max_batch < 0 || o.max_queue < 0)
+    return fail(ZPL_EINVAL, "opts: negative slice_us, max_batch or max_queue");
   Server* sv = new Server();
   if (o.mem_budget_bytes) sv->budget = o.mem_budget_bytes;
-  if (o.max_batch > 0) sv->max_batch = o.max_batch;
+  if (sv->budget > c->budget) {
+    const unsigned long long b = sv->budget, cb = c->budget;
+    delete sv;
+    return fail(ZPL_EINVAL, "serving budget %llu exceeds the context's budget %llu", b, cb);
+  }
+  if (o.max_batch > 0) sv->max_active = o.max_batch;
   if (o.max_queue > 0) sv->max_queue = o.max_queue;
+  if (o.slice_us > 0) sv->slice_ns = 1e3 * (double)o.slice_us;
   zpl_status st = zpl_create(&sv->eng, c->device, c->budget);
   if (st != ZPL_OK) {
     delete sv;
     return st;
   }
   sv->eng->tune = c->tune;
+  if (hipStreamCreateWithFlags(&sv->submit_stream, hipStreamNonBlocking) != hipSuccess) {
+    zpl_destroy(sv->eng);
+    delete sv;
+    return fail(ZPL_EDEVICE, "serving: could not create the submit stream");
+  }
   sv->th = std::thread([sv] { sv->loop(); });
   c->server = sv;
   return ZPL_OK;
 }
 
-zpl_status zpl_serve_submit(zpl_ctx* c, const int64_t* x, int64_t n, int64_t B, uint64_t seed,
-                            uint32_t stream_id, uint64_t* ticket) {
+zpl_status zpl_serve_submit(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
+                            int64_t B, uint64_t seed, uint32_t stream_id, uint64_t* ticket) {
   g_err.clear();
   if (!c || !x || !ticket) return fail(ZPL_EINVAL, "NULL argument");
   Server* sv = c->server;
@@ -1447,19 +1695,34 @@ zpl_status zpl_serve_submit(zpl_ctx* c, const int64_t* x, int64_t n, int64_t B, 
   if (n < 1 || n > ((int64_t)1 << 31)) return fail(ZPL_EINVAL, "n must be in [1, 2^31]");
   if (B < 1 || B > ((int64_t)1 << 32)) return fail(ZPL_EINVAL, "B must be in [1, 2^32]");
   Req* r = new Req();
-  r->x.assign(x, x + n);
+  r->n = n;
+  if (x_on_device) {
+    // a device copy that stays on the device until the request's fit
+    HIP_TRY(hipSetDevice(c->device));
+    const size_t bytes = sizeof(int64_t) * (size_t)n;
+    hipError_t e = hipMallocAsync((void**)&r->xdev, bytes, sv->submit_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r->xdev, x, bytes, hipMemcpyDeviceToDevice, sv->submit_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sv->submit_stream);
+    if (e != hipSuccess) {
+      if (r->xdev) (void)hipFree(r->xdev);
+      delete r;
+      return fail(e == hipErrorOutOfMemory ? ZPL_ENOMEM : ZPL_EDEVICE,
+                  "serving: device dataset copy: %s", hipGetErrorString(e));
+    }
+  } else {
+    r->x.assign(x, x + n);
+  }
   r->B = B;
   r->seed = seed;
   r->stream_id = stream_id;
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (!sv->fatal.empty()) {
+    if (!sv->fatal.empty() || (int)sv->queue.size() >= sv->max_queue) {
+      if (r->xdev) (void)hipFreeAsync(r->xdev, sv->submit_stream);
       delete r;
-      return fail(ZPL_EDEVICE, "%s", sv->fatal.c_str());
-    }
-    if ((int)sv->queue.size() >= sv->max_queue) {
-      delete r;
+      if (!sv->fatal.empty()) return fail(ZPL_EDEVICE, "%s", sv->fatal.c_str());
       return fail(ZPL_EBUSY, "serving queue full (%d requests)", sv->max_queue);
     }
     r->ticket = sv->next_ticket++;
@@ -1490,7 +1753,8 @@ zpl_status zpl_serve_poll(zpl_ctx* c, uint64_t ticket, int32_t wait_ms, zpl_serv
   res->D = r->D;
   res->p_value = r->p;
   res->flags = r->flags;
-  res->batch_size = r->batch_size;
+  res->batch_size = r->mix;
+  res->launches = r->launches;
   using ms = std::chrono::duration<double, std::milli>;
   res->queue_ms = ms(r->t_start - r->t_submit).count();
   res->latency_ms = ms(r->t_done - r->t_submit).count();
@@ -1510,7 +1774,14 @@ zpl_status zpl_serve_stop(zpl_ctx* c) {
   }
   sv->cv.notify_all();
   if (sv->th.joinable()) sv->th.join();
-  for (auto& kv : sv->reqs) delete kv.second;
+  for (auto& kv : sv->reqs) {
+    if (kv.second->xdev) (void)hipFreeAsync(kv.second->xdev, sv->submit_stream);
+    delete kv.second;
+  }
+  if (sv->submit_stream) {
+    (void)hipStreamSynchronize(sv->submit_stream);
+    (void)hipStreamDestroy(sv->submit_stream);
+  }
   zpl_destroy(sv->eng);
   delete sv;
   c->server = nullptr;

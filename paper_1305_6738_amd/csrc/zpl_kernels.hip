@@ -162,15 +162,6 @@ __device__ __forceinline__ uint64_t defer_entry(uint64_t m, uint64_t timax, uint
   return m > timax ? ((1ull << 63) | o | i) : (o | m);
 }
 
-// Deferred draw of the heavy form: its uniform's integer m, its index in the
-// replicate (bit 31 = tail).
-struct QEntry {
-  uint64_t m;
-  uint32_t i;
-  uint32_t owner;
-};
-constexpr uint32_t kTailBit = 0x80000000u;
-
 __device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k0,
                                               uint32_t k1, uint32_t i, uint32_t rep,
                                               uint32_t stream, uint32_t* flags) {
@@ -182,27 +173,6 @@ __device__ __noinline__ int64_t tail_draw_from_dev(double m0, double beta, doubl
                                                    uint32_t rep, uint32_t stream,
                                                    uint32_t* flags) {
   return tail_draw_from(m0, beta, gm, k0, k1, i, rep, stream, flags);
-}
-
-// Resolves a deferred draw of a cell with a lower cutoff (xmin = 1 for the
-// pure law): the table index j is the value xmin - 1 + j, the tail starts at
-// xmin + kH.
-__device__ __forceinline__ int64_t resolve_x(const QEntry& e, uint32_t rep, const DevCell& c,
-                                             const uint64_t* __restrict__ T,
-                                             const uint32_t* __restrict__ guide, uint32_t& fl) {
-  if (e.i & kTailBit)
-    return tail_draw_from_dev((double)(c.xmin + kH), c.beta, c.gm, c.k0, c.k1, e.i & ~kTailBit,
-                              rep, c.stream, &fl);
-  return (c.xmin - 1) + (int64_t)slow_search(e.m, T, guide);
-}
-
-// Resolves a deferred draw.
-__device__ __forceinline__ int64_t resolve(const QEntry& e, uint32_t rep, const DevCell& c,
-                                           const uint64_t* __restrict__ T,
-                                           const uint32_t* __restrict__ guide, uint32_t& fl) {
-  if (e.i & kTailBit)
-    return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, e.i & ~kTailBit, rep, c.stream, &fl);
-  return (int64_t)slow_search(e.m, T, guide);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,14 +223,13 @@ __device__ __forceinline__ double ks_distance(Src& src, const EmCoef& E,
 
 // KS distance (eq. 3) under the truncated law on 1..K: F(t) = P(t)/Z with
 // P(t) = sum_{k<=t} k^-a accumulated in ascending k as the distinct values
-// are visited, and Z = Z_K(a) summed from K down.  Same terms as
+// are visited, and Z = Z_K(a) (zeta3_trunc_fast: Euler-Maclaurin for large
+// K, else the K terms from K down).  Same terms as
 // ks_distance: |F(v) - C(v)/n| and |F(v-1) - C(v-1)/n| per distinct v.
 template <class Src>
 __device__ __forceinline__ double ks_distance_trunc(Src& src, double a, uint32_t K, int64_t n,
                                                     const double* __restrict__ ln) {
-  double Z = 0.0;
-  for (int k = (int)K; k >= 2; --k) Z += pow_neg(a, ln[k]);
-  Z += 1.0;
+  const double Z = zeta3_trunc_fast(a, K, ln).z0;  // the normaliser Z_K(a)
   const double iz = 1.0 / Z, idn = 1.0 / (double)n;
   int64_t C = 0;
   double D = 0.0, P = 0.0;
@@ -548,41 +517,6 @@ __device__ __forceinline__ void finish_replicate_wave(const int64_t* lv, const u
 // ---------------------------------------------------------------------------
 // Wave-cooperative helpers for the wave and heavy forms.
 // ---------------------------------------------------------------------------
-// In-place ascending bitonic sort of a[0..P) (P a power of two) by one wave.
-// Between stages: wave_sync for LDS, Barrier() for global memory.
-template <class Sync>
-__device__ void wave_bitonic(int64_t* a, int P, int lane, Sync sync) {
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < P; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const int64_t x = a[i], y = a[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      sync();
-    }
-  }
-}
-
-// First index in the ascending a[0..n) holding a value >= v.
-__device__ __forceinline__ int lower_bound_i64(const int64_t* a, int n, int64_t v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < v)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // Ordering of one wave's global-memory stores before its later loads.
 __device__ __forceinline__ void wave_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -605,7 +539,7 @@ struct Summary {
   int len;
 };
 
-__device__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int oc, int64_t* lv,
+__device__ __noinline__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int oc, int64_t* lv,
                               uint32_t* lc, int lane, const double* __restrict__ ln, int64_t n,
                               bool want_fp) {
   const uint64_t below = lanes_below(lane);
@@ -638,16 +572,26 @@ __device__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int 
   }
   const int hlen = len;
   // 2. runs of equal values in the sorted overflow array; the last lane of a
-  //    run adds the run's terms
+  //    run adds the run's terms.  A run starts at the last start position at
+  //    or below its end: in this chunk (ballot of starts), else the carried
+  //    start of a run that began in an earlier chunk.
+  int run0 = 0;  // start of the run open at the chunk boundary (wave-uniform)
   for (int p0 = 0; p0 < oc; p0 += 64) {
     const int p = p0 + lane;
     const bool valid = p < oc;
     const int64_t v = valid ? ov[p] : 0;
-    const bool end = valid && ((p == oc - 1) || (ov[p + 1] != v));
+    // neighbours read at clamped indices (always inside ov[0..oc))
+    const int64_t vn = ov[p + 1 < oc ? p + 1 : oc - 1];
+    const int64_t vp = ov[p > 0 ? (p - 1 < oc ? p - 1 : oc - 1) : 0];
+    const bool end = valid && ((p == oc - 1) || (vn != v));
+    const bool start = valid && ((p == 0) || (vp != v));
     const uint64_t m = __ballot(end);
+    const uint64_t sm = __ballot(start);
     if (end) {
       const int pos = len + __popcll(m & below);
-      const uint32_t cnt = (uint32_t)(p + 1 - lower_bound_i64(ov, oc, v));
+      const uint64_t sb = sm & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+      const int first = sb ? p0 + 63 - __clzll((long long)sb) : run0;
+      const uint32_t cnt = (uint32_t)(p + 1 - first);
       lv[pos] = v;
       lc[pos] = cnt;
       u128_add_mul(S, cnt, ln_fixed(v, ln));
@@ -657,6 +601,7 @@ __device__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int 
       }
     }
     len += __popcll(m);
+    if (sm) run0 = p0 + 63 - __clzll((long long)sm);
   }
   // 3. exact S (and fingerprint, max) over the histogram part of the list
   if (packed) {
@@ -714,50 +659,151 @@ __device__ __forceinline__ int next_pow2(int v) {
   return p;
 }
 
-// Passes j = jtop..1 of bitonic stage k on one 64-element chunk held one
-// element per lane (element i = chunk base + lane), exchanged by shuffles:
-// the lower index of each pair keeps the smaller value when the block of
-// size k holding it sorts ascending, the larger otherwise.
-__device__ __forceinline__ int64_t chunk_passes_reg(int64_t v, int i, int k, int jtop, int lane) {
-  const bool up = (i & k) == 0;
-  for (int j = jtop; j > 0; j >>= 1) {
-    const int64_t o = (int64_t)shfl_xor_u64((uint64_t)v, j);
-    const bool lower = (lane & j) == 0;
-    const int64_t lo = o < v ? o : v, hi = o < v ? v : o;
-    v = (lower == up) ? lo : hi;
-  }
-  return v;
+// Compare-exchange of a (the lower index) and b: the smaller value goes to a
+// when the block holding them sorts ascending (up), the larger otherwise.
+__device__ __forceinline__ void cmpx(int64_t& a, int64_t& b, bool up) {
+  const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  a = up ? lo : hi;
+  b = up ? hi : lo;
 }
 
-// Bitonic sort of the global array g[0..P) (P a power of two, at least 128)
-// by one wave: wave_bitonic's passes in its order, but every pass with
-// j < 64 runs on 64-element chunks in registers, so only the passes with
-// j >= 64 go through memory (21 instead of 78 for 4,096 values).
+// Passes j = jtop..1 of bitonic stage k on a block of 64 E elements held E
+// per lane: element t of this lane has index base + lane + 64 t.  Passes with
+// j >= 64 pair registers t and t | j/64 of the same lane; passes with j < 64
+// pair lanes (shuffles).  Every index is a compile-time register number.
+template <int E>
+__device__ __forceinline__ void block_passes(int64_t (&v)[E], int base, int k, int jtop,
+                                             int lane) {
+#pragma unroll
+  for (int tj = E / 2; tj >= 1; tj >>= 1) {
+    if ((tj << 6) <= jtop) {
+#pragma unroll
+      for (int t = 0; t < E; ++t)
+        if ((t & tj) == 0) cmpx(v[t], v[t | tj], ((base + lane + 64 * t) & k) == 0);
+    }
+  }
+#pragma unroll
+  for (int j = 32; j > 0; j >>= 1) {
+    if (j <= jtop) {
+      const bool lower = (lane & j) == 0;
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const bool up = ((base + lane + 64 * t) & k) == 0;
+        const int64_t o = (int64_t)shfl_xor_u64((uint64_t)v[t], j);
+        const int64_t lo = o < v[t] ? o : v[t], hi = o < v[t] ? v[t] : o;
+        v[t] = (lower == up) ? lo : hi;
+      }
+    }
+  }
+}
+
+// Every stage k <= 64 E of a block (a full bitonic sort when the block is the
+// whole array; else a sort whose direction alternates with the block index,
+// as the network's first stages leave it).
+template <int E>
+__device__ __forceinline__ void block_sort(int64_t (&v)[E], int base, int lane) {
+  for (int k = 2; k <= 64 * E; k <<= 1) block_passes<E>(v, base, k, k >> 1, lane);
+}
+
+template <int E>
+__device__ __forceinline__ void block_load(int64_t (&v)[E], const int64_t* a, int lane) {
+#pragma unroll
+  for (int t = 0; t < E; ++t) v[t] = a[lane + 64 * t];
+}
+template <int E>
+__device__ __forceinline__ void block_store(const int64_t (&v)[E], int64_t* a, int lane) {
+#pragma unroll
+  for (int t = 0; t < E; ++t) a[lane + 64 * t] = v[t];
+}
+
+// Ascending bitonic sort of a[0..P) (P a power of two, 128..512) by one wave,
+// entirely in registers (P / 64 values per lane); a is LDS or global memory,
+// read once and written once by the calling wave.
+__device__ __forceinline__ void wave_sort_small(int64_t* a, int P, int lane) {
+  if (P == 128) {
+    int64_t v[2];
+    block_load<2>(v, a, lane);
+    block_sort<2>(v, 0, lane);
+    block_store<2>(v, a, lane);
+  } else if (P == 256) {
+    int64_t v[4];
+    block_load<4>(v, a, lane);
+    block_sort<4>(v, 0, lane);
+    block_store<4>(v, a, lane);
+  } else {
+    int64_t v[8];
+    block_load<8>(v, a, lane);
+    block_sort<8>(v, 0, lane);
+    block_store<8>(v, a, lane);
+  }
+}
+
+// G consecutive passes j1, j1/2, ..., j1 >> (G-1) (all >= 512) of bitonic
+// stage k over g[0..P) in one round trip: each group of 2^G elements differing
+// only in those index bits is loaded into registers, put through the G passes
+// and stored back.  The block direction (index & k) is the same for a whole
+// group, since k is above every bit that varies in it.
+template <int G>
+__device__ __forceinline__ void mem_group(int64_t* g, int P, int k, int j1, int lane) {
+  constexpr int NE = 1 << G;
+  const int p = 31 - __builtin_clz((unsigned)j1);
+  const int low = p - G + 1;
+  const int lowmask = (1 << low) - 1;
+  for (int q = lane; q < (P >> G); q += 64) {
+    const int b = ((q >> low) << (p + 1)) | (q & lowmask);
+    const bool up = (b & k) == 0;
+    int64_t v[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) v[e] = g[b + (e << low)];
+#pragma unroll
+    for (int sft = G - 1; sft >= 0; --sft) {
+#pragma unroll
+      for (int e = 0; e < NE; ++e)
+        if ((e & (1 << sft)) == 0) cmpx(v[e], v[e | (1 << sft)], up);
+    }
+#pragma unroll
+    for (int e = 0; e < NE; ++e) g[b + (e << low)] = v[e];
+  }
+}
+
+// Ascending bitonic sort of the global array g[0..P) (P a power of two, at
+// least 128) by one wave.  Arrays of up to 512 values are sorted in registers.
+// Larger ones: every 512-value block is first sorted in registers (the
+// network's stages up to 512); each later stage k runs its passes with
+// j >= 512 through memory, up to three per round trip (mem_group), and its
+// passes with j <= 256 on 512-value blocks in registers.  A 4,096-value
+// array takes 7 round trips through memory instead of 78 passes.
 __device__ void wave_sort_global(int64_t* g, int P, int lane) {
-  for (int base = 0; base < P; base += 64) {
-    int64_t v = g[base + lane];
-    for (int k = 2; k <= 64; k <<= 1) v = chunk_passes_reg(v, base + lane, k, k >> 1, lane);
-    g[base + lane] = v;
+  if (P <= 512) {
+    wave_sort_small(g, P, lane);
+    wave_sync_global();
+    return;
+  }
+  for (int base = 0; base < P; base += 512) {
+    int64_t v[8];
+    block_load<8>(v, g + base, lane);
+    block_sort<8>(v, base, lane);
+    block_store<8>(v, g + base, lane);
   }
   wave_sync_global();
-  for (int k = 128; k <= P; k <<= 1) {
-    for (int j = k >> 1; j >= 64; j >>= 1) {
-      for (int i = lane; i < P; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const int64_t x = g[i], y = g[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            g[i] = y;
-            g[ixj] = x;
-          }
-        }
-      }
+  for (int k = 1024; k <= P; k <<= 1) {
+    int j = k >> 1;
+    while (j >= 512) {
+      const int G = min(3, 31 - __builtin_clz((unsigned)j) - 8);
+      if (G == 3)
+        mem_group<3>(g, P, k, j, lane);
+      else if (G == 2)
+        mem_group<2>(g, P, k, j, lane);
+      else
+        mem_group<1>(g, P, k, j, lane);
       wave_sync_global();
+      j >>= G;
     }
-    for (int base = 0; base < P; base += 64) {
-      const int64_t v = chunk_passes_reg(g[base + lane], base + lane, k, 32, lane);
-      g[base + lane] = v;
+    for (int base = 0; base < P; base += 512) {
+      int64_t v[8];
+      block_load<8>(v, g + base, lane);
+      block_passes<8>(v, base, k, 256, lane);
+      block_store<8>(v, g + base, lane);
     }
     wave_sync_global();
   }
@@ -842,34 +888,6 @@ __device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
   for (int k = tid; k < kH; k += nthreads) T[k] = table_int(Tg[k]);
   for (int b = tid; b < kGuide; b += nthreads)
     guide[b] = (uint32_t)g[b] | ((uint32_t)g[b + 1] << 16);
-}
-
-// Moves queue entries [m, qn) to the front after lanes resolved [0, m).
-template <class Region>
-__device__ __forceinline__ void queue_compact(Region* L, int m, int lane) {
-  const int rem = (int)L->qn - m;
-  const bool ha = lane < rem, hb = lane + 64 < rem;
-  uint64_t ua = 0u, ub = 0u;
-  uint32_t ia = 0u, ib = 0u;
-  if (ha) {
-    ua = L->q[m + lane].m;
-    ia = L->q[m + lane].i;
-  }
-  if (hb) {
-    ub = L->q[m + 64 + lane].m;
-    ib = L->q[m + 64 + lane].i;
-  }
-  wave_sync();
-  if (ha) {
-    L->q[lane].m = ua;
-    L->q[lane].i = ia;
-  }
-  if (hb) {
-    L->q[64 + lane].m = ub;
-    L->q[64 + lane].i = ib;
-  }
-  if (lane == 0) L->qn = (uint32_t)rem;
-  wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -1036,10 +1054,6 @@ struct WaveSlot {
   uint32_t off, len, flags, esc;
 };
 
-struct WaveSync {
-  __device__ void operator()() const { wave_sync(); }
-};
-
 __device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
   if (x <= kHW) {
     atomicAdd(&L->hist[x - 1], 1u);
@@ -1051,16 +1065,20 @@ __device__ __forceinline__ void wave_insert(WaveRegion* L, int64_t x) {
 
 // Resolves ring entries [qh, qh + m) (one per lane) into the histogram (see
 // lane_drain).
+// xm: the lane's largest value counted in the histogram so far.
 __device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qh, uint32_t rep,
                                            const DevCell& c, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, uint32_t& fl,
-                                           int lane) {
+                                           int& xm, int lane) {
   wave_sync();
+  int64_t v = 0;
   if (lane < m) {
     uint32_t p = qh + (uint32_t)lane;
     if (p >= (uint32_t)kRing) p -= (uint32_t)kRing;
-    wave_insert(L, resolve_entry(L->ring[p], rep, c, T, guide, fl));
+    v = resolve_entry(L->ring[p], rep, c, T, guide, fl);
+    wave_insert(L, v);
   }
+  xm = max(xm, v <= kHW ? (int)v : 0);
 }
 
 // Draw blocks per lane per iteration of the wave form's loop.
@@ -1077,16 +1095,24 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
   const int64_t n = c.n;
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   int done = 0;
+  // histogram bins [0, hi) may be nonzero: the whole histogram at first (the
+  // region's LDS held other data), afterwards the 256-bin blocks up to the
+  // previous replicate's largest histogram value (the list build packs its
+  // entries below that too)
+  int hi = kHW;
   while (done < nrep) {
     // fill a batch of replicates while the list area has room for a worst case
     int q = 0;
     uint32_t used = 0;
     while (done + q < nrep && q < 64 && used + (uint32_t)(kHW + kCW) <= (uint32_t)kListCap) {
       const uint32_t r = (uint32_t)(r0 + done + q);
-      for (int k = lane; k < kHW; k += 64) L->hist[k] = 0u;
+      for (int k = lane; k < hi; k += 64) L->hist[k] = 0u;
       if (lane == 0) L->ovc = 0u;
       wave_sync();
-      // values 1..3 take most draws: counted in registers, not LDS atomics
+      int xm = 0;  // the lane's largest value counted in the histogram
+      // values 1..3 take most draws: counted per wave from ballots in
+      // wave-uniform control flow (scalar counts, no LDS atomics and no
+      // per-lane registers to sum across lanes afterwards)
       uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
       uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
       const uint64_t timax = table_int(c.tmax);
@@ -1114,14 +1140,15 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           x[d] = valid ? xd : -1;
           def[d] = valid && xd == 0;
           big = big || x[d] > kHW;
-          // values 1..3 take most draws: counted in registers, not LDS
-          // atomics; the others add 1 to their bin, and lanes with nothing to
-          // add put a zero into their own pad slot (no divergent branch)
-          c1 += x[d] == 1 ? 1u : 0u;
-          c2 += x[d] == 2 ? 1u : 0u;
-          c3 += x[d] == 3 ? 1u : 0u;
+          // values 1..3 are counted from ballots (the loop is wave-uniform);
+          // the others add 1 to their bin, and lanes with nothing to add put
+          // a zero into their own pad slot (no divergent branch)
+          c1 += (uint32_t)__popcll(__ballot(x[d] == 1));
+          c2 += (uint32_t)__popcll(__ballot(x[d] == 2));
+          c3 += (uint32_t)__popcll(__ballot(x[d] == 3));
           const bool hb = x[d] > 3 && x[d] <= kHW;
           atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], hb ? 1u : 0u);
+          xm = max(xm, x[d] <= kHW ? x[d] : 0);
         }
         if (__ballot(big) != 0ull) {  // values above the histogram
 #pragma unroll
@@ -1134,16 +1161,17 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
                              0);
         }, lane);
         while (qn >= 64u) {
-          wave_drain(L, 64, qh, r, c, T, guide, fl, lane);
+          wave_drain(L, 64, qh, r, c, T, guide, fl, xm, lane);
           qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
           qn -= 64u;
         }
       }
-      if (qn > 0u) wave_drain(L, (int)qn, qh, r, c, T, guide, fl, lane);
-      c1 = wave_sum_u32(c1);
-      c2 = wave_sum_u32(c2);
-      c3 = wave_sum_u32(c3);
+      if (qn > 0u) wave_drain(L, (int)qn, qh, r, c, T, guide, fl, xm, lane);
       fl = wave_or_u32(fl);
+      // bins the list build reads: whole 256-bin blocks up to the largest
+      // histogram value (every lane's xm is defined: set in converged code)
+      hi = ((int)wave_max_i64((int64_t)xm) + 255) & ~255;
+      hi = hi < 256 ? 256 : hi;
       wave_sync();
       if (lane == 0) {
         L->hist[0] += c1;
@@ -1173,9 +1201,11 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         const int P = next_pow2((int)oc);
         for (int k = (int)oc + lane; k < P; k += 64) L->ov[k] = INT64_MAX;
         wave_sync();
-        wave_bitonic(L->ov, P, lane, WaveSync{});
+        static_assert(kCW <= 512, "the wave form's overflow is sorted in registers");
+        wave_sort_small(L->ov, P, lane);  // one LDS read and one write per value
+        wave_sync();
       }
-      const Summary s = build_list(L->hist, kHW, L->ov, (int)oc, lv + used, lc + used, lane,
+      const Summary s = build_list(L->hist, hi, L->ov, (int)oc, lv + used, lc + used, lane,
                                    ln, n, out.fp != nullptr || out.xmax != nullptr);
       if (lane == 0) {
         WaveSlot sl;
@@ -1268,10 +1298,10 @@ __global__ __launch_bounds__(kBlock, 1) void k_simulate(
 // replicate that overflowed the lane or wave form.
 // ---------------------------------------------------------------------------
 struct alignas(16) HeavyWave {
-  uint32_t hist[kHeavyHist];
-  QEntry q[kQCap];
+  uint32_t hist[kHeavyHist + 64];  // values 1..kHeavyHist; then one zero-add pad slot per lane
+  uint64_t ring[kRing];            // deferred draws (simulated replicates)
+  uint32_t ones[64];  // per-lane count of values equal to 1 (the most frequent value)
   uint32_t ovc;
-  uint32_t qn;
 };
 
 struct HeavyLds {
@@ -1280,6 +1310,7 @@ struct HeavyLds {
   HeavyWave w[kHeavyWaves];
   int item;
 };
+static_assert(2 * sizeof(HeavyLds) <= 160 * 1024, "two heavy workgroups per compute unit");
 
 struct GlobalSync {
   __device__ void operator()() const { wave_sync_global(); }
@@ -1296,19 +1327,20 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
                            bool& ok, int64_t xmin = 1) {
   const int lane = lane_id();
   for (int k = lane; k < kHeavyHist; k += 64) W->hist[k] = 0u;
-  if (lane == 0) {
-    W->ovc = 0u;
-    W->qn = 0u;
-  }
+  W->ones[lane] = 0u;
+  if (lane == 0) W->ovc = 0u;
   wave_sync_global();
-  uint32_t c1 = 0, fl = 0;
+  uint32_t fl = 0;
   bool bad = false;
   const int64_t xhi = K ? (int64_t)K : INT64_MAX;
+  // sink runs in divergent code (partial draw blocks, deferred draws): the
+  // ones go to the lane's own LDS counter (no contention on bin 1), summed
+  // from LDS once every lane is back
   auto sink = [&](int64_t x) {
     if (x < 1 || x > xhi) {
       bad = true;
     } else if (x == 1) {
-      ++c1;
+      atomicAdd(&W->ones[lane], 1u);
     } else if (x <= kHeavyHist) {
       atomicAdd(&W->hist[x - 1], 1u);
     } else {
@@ -1317,7 +1349,8 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
     }
   };
   fill(sink, fl);
-  c1 = wave_sum_u32(c1);
+  wave_sync();
+  const uint32_t c1 = wave_sum_u32(W->ones[lane]);
   fl = wave_or_u32(fl);
   const uint32_t anybad = wave_or_u32(bad ? 1u : 0u);
   if (lane == 0) W->hist[0] += c1;
@@ -1342,6 +1375,59 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
   xmax = s.xmax;
 }
 
+// Adds one value per lane (lanes with valid set) to a simulated heavy-form
+// replicate, in wave-uniform control flow: ones to the wave's scalar count
+// (ballot), 2..kHeavyHist to the LDS histogram (lanes with nothing to add put
+// a zero into their own pad slot), larger values to the global overflow array
+// at positions from a ballot prefix (no atomics on a shared counter).
+__device__ __forceinline__ void heavy_put(HeavyWave* W, int64_t* gov, int64_t v, bool valid,
+                                          uint32_t& ones, uint32_t& ovn, int lane,
+                                          uint64_t below) {
+  ones += (uint32_t)__popcll(__ballot(valid && v == 1));
+  const bool hb = valid && v >= 2 && v <= kHeavyHist;
+  atomicAdd(&W->hist[hb ? (int)v - 1 : kHeavyHist + lane], hb ? 1u : 0u);
+  const bool big = valid && v > kHeavyHist;
+  const uint64_t mb = __ballot(big);
+  if (mb != 0ull) {
+    if (big) gov[ovn + (uint32_t)__popcll(mb & below)] = v;
+    ovn += (uint32_t)__popcll(mb);
+  }
+}
+
+// Resolves a deferred draw of a cell with a lower cutoff (xmin = 1 for the
+// pure law): the table index j is the value xmin - 1 + j, the tail starts at
+// xmin + kH.
+__device__ __forceinline__ int64_t resolve_entry_cut(uint64_t e, uint32_t rep, const DevCell& c,
+                                                     const uint64_t* __restrict__ T,
+                                                     const uint32_t* __restrict__ guide,
+                                                     uint32_t& fl) {
+  if (e >> 63)
+    return tail_draw_from_dev((double)(c.xmin + kH), c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep,
+                              c.stream, &fl);
+  return (c.xmin - 1) + (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide);
+}
+
+// Resolves ring entries [qh, qh + m) (one per lane) into the replicate.
+__device__ __forceinline__ void heavy_drain(HeavyWave* W, int64_t* gov, int m, uint32_t qh,
+                                            uint32_t rep, const DevCell& c,
+                                            const uint64_t* __restrict__ T,
+                                            const uint32_t* __restrict__ guide, uint32_t& fl,
+                                            uint32_t& ones, uint32_t& ovn, int lane,
+                                            uint64_t below) {
+  wave_sync();  // entries appended by other lanes
+  int64_t v = 0;
+  if (lane < m) {
+    uint32_t p = qh + (uint32_t)lane;
+    if (p >= (uint32_t)kRing) p -= (uint32_t)kRing;
+    v = resolve_entry_cut(W->ring[p], rep, c, T, guide, fl);
+  }
+  heavy_put(W, gov, v, lane < m, ones, ovn, lane, below);
+}
+
+// One simulated replicate by one wave: the wave form's draw loop (two Philox
+// blocks per lane per iteration, guide lookups in phases, deferred draws in a
+// ring resolved 64 at a time) with the values above the LDS histogram in the
+// wave's global overflow array; then heavy_core's sort, list and finish.
 __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
                                 const uint32_t* __restrict__ guide, const DevCell& c,
                                 uint32_t rep, int64_t* gov, int64_t* lv, uint32_t* lc,
@@ -1351,40 +1437,50 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   const uint64_t timax = table_int(c.tmax);
   const int64_t off = c.xmin - 1;  // table index j is the value off + j
-  auto fill = [&](auto sink, uint32_t& fl) {
-    for (uint32_t j0 = 0; j0 < nblk; j0 += 64u) {
-      const uint32_t j = j0 + (uint32_t)lane;
-      if (j < nblk) {
-        const Words4 w = philox4x32_10(j, rep, c.stream, 0u, c.k0, c.k1);
+  auto fill = [&](auto, uint32_t& fl) {
+    const uint64_t below = lanes_below(lane);
+    uint32_t ones = 0, ovn = 0;  // wave-uniform
+    uint32_t qh = 0, qn = 0;     // deferred-draw ring, wave-uniform
+    for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
+      // round keys per block (see lane_wave); the cell is the wave's, so its
+      // key is uniform: read from the first lane into scalar registers
+      uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c.k0);
+      uint32_t k1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c.k1);
+      asm volatile("" : "+s"(k0), "+s"(k1));
+      uint64_t U[2 * kWaveBlocks];
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const uint32_t i = 2u * j + (uint32_t)half;
-          if (half == 1 && (int64_t)i >= n) break;
-          const uint64_t m = half ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
-          const int x = fast_draw(m, timax, T, guide);
-          if (x) {
-            sink(off + (int64_t)x);
-          } else {
-            const uint32_t slot = atomicAdd(&W->qn, 1u);
-            W->q[slot] = QEntry{m, m > timax ? (i | kTailBit) : i, 0u};
-          }
-        }
+      for (int b = 0; b < kWaveBlocks; ++b) {
+        const Words4 w = philox4x32_10(j0 + 64u * (uint32_t)b + (uint32_t)lane, rep, c.stream,
+                                       0u, k0, k1);
+        U[2 * b] = m53(w.w0, w.w1);
+        U[2 * b + 1] = m53(w.w2, w.w3);
       }
-      wave_sync();
-      while (W->qn >= 64u) {
-        const QEntry e = W->q[lane];
-        sink(resolve_x(e, rep, c, T, guide, fl));
-        wave_sync();
-        queue_compact(W, 64, lane);
+      int xf[2 * kWaveBlocks];
+      fast_draw4(U, timax, T, guide, xf);
+      bool def[2 * kWaveBlocks];
+#pragma unroll
+      for (int d = 0; d < 2 * kWaveBlocks; ++d) {
+        const uint32_t i =
+            2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
+        const bool valid = (int64_t)i < n;
+        def[d] = valid && xf[d] == 0;
+        heavy_put(W, gov, off + (int64_t)xf[d], valid && xf[d] != 0, ones, ovn, lane, below);
+      }
+      ring_append(W->ring, qh, qn, def, [&](int d) {
+        return defer_entry(U[d], timax,
+                           2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1),
+                           0);
+      }, lane);
+      while (qn >= 64u) {
+        heavy_drain(W, gov, 64, qh, rep, c, T, guide, fl, ones, ovn, lane, below);
+        qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
+        qn -= 64u;
       }
     }
-    for (int m = (int)W->qn; m > 0; m = (int)W->qn) {
-      if (lane < m) {
-        const QEntry e = W->q[lane];
-        sink(resolve_x(e, rep, c, T, guide, fl));
-      }
-      wave_sync();
-      queue_compact(W, m, lane);
+    if (qn > 0u) heavy_drain(W, gov, (int)qn, qh, rep, c, T, guide, fl, ones, ovn, lane, below);
+    if (lane == 0) {
+      W->ones[0] = ones;
+      W->ovc = ovn;
     }
   };
   double a = 0.0, D = 0.0;
@@ -2226,7 +2322,7 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
     if (v != 0)
       v += c.xmin - 1;
     else
-      v = resolve_x(QEntry{m, m > timax ? (i | kTailBit) : i, 0u}, rep, c, T, guide, fl);
+      v = resolve_entry_cut(defer_entry(m, timax, i, 0), rep, c, T, guide, fl);
     x[t] = v;
     if (fl) atomicOr(&flags[rr], fl);
   }

@@ -30,9 +30,6 @@ constexpr int kCL = 8;
 // plus up to kCW larger values in LDS; finishes run one replicate per lane.
 constexpr int kHW = 1024;
 constexpr int kCW = 512;
-// Deferred draws (multi-entry guide brackets and tail draws) wait in a
-// per-wave queue and are resolved 64 at a time, one per lane.
-constexpr int kQCap = 192;
 // Compact (value, count) list capacity per wave for deferred finishes.
 constexpr int kListCap = 16 * (kHW + kCW);
 // Heavy form: 4 wave64 per workgroup, values above kHeavyHist in per-wave

@@ -448,6 +448,139 @@ ZPL_HD Z3 zeta3_trunc(double s, uint32_t K, const double* __restrict__ ln) {
   return Z3{z0, z1, z2};
 }
 
+// M_k(z) = int_0^1 v^k e^(z v) dv for k = 0, 1, 2: the power series
+// sum_m z^m / (m! (m + k + 1)) for |z| <= 2 (32 terms by Horner's rule; the
+// last is below 2^-80 of the sum), else the closed forms
+// M_0 = (e^z - 1)/z, M_1 = (e^z (z - 1) + 1)/z^2, M_2 = (e^z (z^2 - 2z + 2) - 2)/z^3
+// (the largest cancellation there, at z = -2, costs under two bits).
+struct MomentCoef {
+  double c[3][32];  // 1 / (m! (m + k + 1))
+};
+constexpr MomentCoef moment_coef() {
+  MomentCoef t{};
+  double f = 1.0;  // m!
+  for (int m = 0; m < 32; ++m) {
+    if (m > 0) f *= (double)m;
+    for (int k = 0; k < 3; ++k) t.c[k][m] = 1.0 / (f * (double)(m + k + 1));
+  }
+  return t;
+}
+
+ZPL_HD void moments012(double z, double& m0, double& m1, double& m2) {
+  if (fabs(z) <= 2.0) {
+    constexpr MomentCoef C = moment_coef();
+    double a0 = C.c[0][31], a1 = C.c[1][31], a2 = C.c[2][31];
+#pragma unroll
+    for (int m = 30; m >= 0; --m) {
+      a0 = fma(a0, z, C.c[0][m]);
+      a1 = fma(a1, z, C.c[1][m]);
+      a2 = fma(a2, z, C.c[2][m]);
+    }
+    m0 = a0;
+    m1 = a1;
+    m2 = a2;
+    return;
+  }
+  const double ez = exp(z), iz = 1.0 / z;
+  m0 = expm1(z) * iz;
+  m1 = fma(ez, z - 1.0, 1.0) * iz * iz;
+  m2 = fma(ez, fma(z, z - 2.0, 2.0), -2.0) * iz * iz * iz;
+}
+
+// Z_K(s) and its first two s-derivatives with Euler-Maclaurin summation of
+// the terms k = q0..K, for every real s (the truncated law allows s <= 1):
+// sum_{k=q0..K} k^-s = I + (q0^-s + K^-s)/2
+//                      + sum_i c_i (s)_{2i-1} (q0^(-s-2i+1) - K^(-s-2i+1)),
+// I = int_{q0}^{K} x^-s dx = q0^(1-s) D M_0(u D) with u = 1 - s, D = ln(K/q0)
+// (and I' = -q0^(1-s) (ln q0 D M_0 + D^2 M_1), I'' = q0^(1-s) (ln^2 q0 D M_0
+// + 2 ln q0 D^2 M_1 + D^3 M_2), the moments M_k of moments012, which keep
+// s = 1 regular), the rising factorials and their derivatives by the
+// product rule (no division by s + j, which vanishes at negative integers).
+// q0 = em_start(|s|) (17 up to |s| = 4.375) keeps eight Bernoulli terms
+// below 1e-16 relative, as for the Hurwitz zeta; k = 1..q0-1 are summed
+// directly.  Used once K is 48 or more above q0, where it is cheaper than the
+// K direct terms (a few exps against K).
+// Out of line: it is long, and inlined into every finish it would crowd the
+// registers of the draw loops around them.
+__host__ __device__ __noinline__ static Z3 zeta3_trunc_em(double s, uint32_t K,
+                                                          const double* __restrict__ ln) {
+  const int64_t q0 = em_start(fabs(s));
+  const double c[8] = {1.0 / 12.0,         -1.0 / 720.0,
+                       1.0 / 30240.0,      -1.0 / 1209600.0,
+                       1.0 / 47900160.0,   -691.0 / 1307674368000.0,
+                       1.0 / 74724249600.0, -3617.0 / 10670622842880000.0};
+  const double qa = (double)q0, qb = (double)K;
+  const double la = ln[q0], lb = ln[K];
+  const double fa = pow_neg(s, la), fb = pow_neg(s, lb);  // q0^-s, K^-s
+  const double ia2 = 1.0 / (qa * qa), ib2 = 1.0 / (qb * qb);
+  // Bernoulli terms: (s)_{2i-1} and its s-derivatives P1, P2
+  double P = s, P1 = 1.0, P2 = 0.0;
+  double Ea = fa / qa, Eb = fb / qb;  // q^(-s-2i+1)
+  double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    // value c P (Ea - Eb); d/ds: c (P1 (Ea - Eb) - P (la Ea - lb Eb));
+    // d2/ds2: c (P2 (Ea - Eb) - 2 P1 (la Ea - lb Eb) + P (la^2 Ea - lb^2 Eb))
+    const double d0 = Ea - Eb;
+    const double d1 = fma(la, Ea, -lb * Eb);
+    const double d2 = fma(la * la, Ea, -(lb * lb) * Eb);
+    b0 = fma(c[i], P * d0, b0);
+    b1 = fma(c[i], fma(P1, d0, -P * d1), b1);
+    b2 = fma(c[i], fma(P2, d0, fma(-2.0 * P1, d1, P * d2)), b2);
+#pragma unroll
+    for (int j = 1; j <= 2; ++j) {  // times (s + 2i + j - ... ): two more factors
+      const double f = s + (double)(2 * i + j);
+      P2 = fma(P2, f, 2.0 * P1);
+      P1 = fma(P1, f, P);
+      P *= f;
+    }
+    Ea *= ia2;
+    Eb *= ib2;
+  }
+  // the integral
+  const double D = lb - la;
+  double m0, m1, m2;
+  moments012((1.0 - s) * D, m0, m1, m2);
+  const double g = fa * qa;  // q0^(1-s)
+  const double i0 = g * D * m0;
+  const double i1 = -g * fma(la * D, m0, D * D * m1);
+  const double i2 = g * fma(la * la * D, m0, fma(2.0 * la * D * D, m1, D * D * D * m2));
+  // the end terms (f(q0) + f(K))/2
+  double z0 = i0 + 0.5 * (fa + fb) + b0;
+  double z1 = i1 - 0.5 * fma(la, fa, lb * fb) + b1;
+  double z2 = i2 + 0.5 * fma(la * la, fa, (lb * lb) * fb) + b2;
+  // direct terms q0-1 down to 2, then 1
+  if (q0 == 17) {
+    double pw[17];
+    small_powers(s, ln, pw);
+#pragma unroll
+    for (int k = 16; k >= 2; --k) {
+      const double lk = ln[k];
+      const double t = pw[k];
+      z0 += t;
+      z1 = fma(-lk, t, z1);
+      z2 = fma(lk * lk, t, z2);
+    }
+  } else {
+    for (int k = (int)q0 - 1; k >= 2; --k) {
+      const double lk = ln[k];
+      const double t = pow_neg(s, lk);
+      z0 += t;
+      z1 = fma(-lk, t, z1);
+      z2 = fma(lk * lk, t, z2);
+    }
+  }
+  z0 += 1.0;
+  return Z3{z0, z1, z2};
+}
+
+// The truncated law's sums: Euler-Maclaurin once K is 48 or more above the
+// direct range, else the K direct terms.
+ZPL_HD Z3 zeta3_trunc_fast(double s, uint32_t K, const double* __restrict__ ln) {
+  if ((int64_t)K >= em_start(fabs(s)) + 48) return zeta3_trunc_em(s, K, ln);
+  return zeta3_trunc(s, K, ln);
+}
+
 // MLE of eq. (2) with the finite sums: mu(s) = -Z_K'/Z_K decreases strictly
 // from ln K (s -> -inf) to 0 (s -> +inf).  The same safeguarded Newton
 // iteration as mle_alpha on [-64, 64]; an iterate ending at the bracket edge
@@ -464,7 +597,7 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
   double gl = 0.0;  // the last residual of eq. 2
   int it = 0;
   for (; it < kMleCap; ++it) {
-    const Z3 z = zeta3_trunc(a, K, ln);
+    const Z3 z = zeta3_trunc_fast(a, K, ln);
     const double mu = -z.z1 / z.z0;
     if (mu == m) break;
     gl = mu - m;
@@ -494,7 +627,7 @@ ZPL_HD double mle_alpha_trunc(double m, uint32_t K, const double* __restrict__ l
   // edge then too.
   if (fabs(a) > 63.0 || (a < 0.0 && m >= ln[K] * (1.0 - 0x1p-50))) {
     const double e = a > 0.0 ? 64.0 : -64.0;
-    const Z3 z = zeta3_trunc(e, K, ln);
+    const Z3 z = zeta3_trunc_fast(e, K, ln);
     const double mue = -z.z1 / z.z0;
     if (a > 0.0 ? !(m > mue) : !(m < mue)) {
       *flags |= kFlagNoConv;

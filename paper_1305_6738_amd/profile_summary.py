@@ -1,9 +1,10 @@
-"""Summarise the output of profile.sh (rocprofv3 CSV files) as Markdown: the
-simulation kernel's average duration, its HBM traffic per launch (FETCH_SIZE
-and WRITE_SIZE scaled by a copy of known size), and VALU / FP64 / LDS /
-occupancy fractions from the SQ counters.
+"""Summarise the output of profile.sh (rocprofv3 CSV files) as Markdown: one
+kernel's average duration, its HBM traffic per launch (FETCH_SIZE and
+WRITE_SIZE scaled by a copy of known size), the clock measured over its
+dispatches (GRBM_COUNT / duration), and VALU / FP64 / LDS / occupancy
+fractions from the SQ counters at that clock.
 
-    python profile_summary.py OUT_DIR > summary.md
+    python profile_summary.py OUT_DIR KERNEL "WORKLOAD TITLE" "BENCH ARGS" > summary.md
 """
 import collections
 import csv
@@ -12,10 +13,10 @@ import sys
 from pathlib import Path
 
 ROOT = Path(__file__).resolve().parent.parent
-KERNEL = "k_simulate"
 COPY_MIB = 256
-CLOCK_HZ = 2.4e9
+NOMINAL_HZ = 2.4e9
 N_CU, SIMD_PER_CU = 256, 4
+STEPS = 5  # the timed steps of profile.sh's bench command
 SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
            "paper_1305_6738_amd/csrc/zpl_math.hpp"]
 
@@ -43,12 +44,11 @@ def last_dispatches(cs, key, count):
     return [c for _, c in sel[-count:]]
 
 
-def main(out_dir):
+def main(out_dir, kernel, title, bench_args):
     out = Path(out_dir)
     trace = list(csv.DictReader(open(out / "trace" / "run_kernel_trace.csv")))
-    sim = [r for r in trace if KERNEL in r["Kernel_Name"]]
-    steps = 5  # the timed steps of profile.sh's bench command
-    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in sim[-steps:]]
+    sim = [r for r in trace if kernel in r["Kernel_Name"]]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in sim[-STEPS:]]
     dur = sum(durs) / len(durs)
     stats = list(csv.DictReader(open(out / "trace" / "run_kernel_stats.csv")))
     fetch, write = counters(out / "fetch"), counters(out / "write")
@@ -57,56 +57,69 @@ def main(out_dir):
     kib = COPY_MIB * 1024.0
     sf = kib / copy_f[0]["FETCH_SIZE"] if copy_f else 1.0
     sw = kib / copy_w[0]["WRITE_SIZE"] if copy_w else 1.0
-    f_k = [c["FETCH_SIZE"] for c in last_dispatches(fetch, KERNEL, steps)]
-    w_k = [c["WRITE_SIZE"] for c in last_dispatches(write, KERNEL, steps)]
+    f_k = [c["FETCH_SIZE"] for c in last_dispatches(fetch, kernel, STEPS)]
+    w_k = [c["WRITE_SIZE"] for c in last_dispatches(write, kernel, STEPS)]
     fb = sum(f_k) / len(f_k) * sf * 1024.0
     wb = sum(w_k) / len(w_k) * sw * 1024.0
-    sq = last_dispatches(counters(out / "sq"), KERNEL, steps)[-1]
-    sq2 = last_dispatches(counters(out / "sq2"), KERNEL, steps)[-1]
-    simd_cycles = dur * CLOCK_HZ * N_CU * SIMD_PER_CU
-    cu_cycles = dur * CLOCK_HZ * N_CU
+    sq = last_dispatches(counters(out / "sq"), kernel, STEPS)[-1]
+    sq2 = last_dispatches(counters(out / "sq2"), kernel, STEPS)[-1]
+    # the clock over the kernel's dispatch: GRBM_COUNT ticks once per GPU clock
+    clock = sq2["GRBM_COUNT"] / dur if sq2.get("GRBM_COUNT") else NOMINAL_HZ
+    gui = sq2.get("GRBM_GUI_ACTIVE", 0.0) / max(sq2.get("GRBM_COUNT", 0.0), 1.0)
+    simd_cycles = dur * clock * N_CU * SIMD_PER_CU
+    cu_cycles = dur * clock * N_CU
     valu_busy = sq["SQ_ACTIVE_INST_VALU"] * 4.0 / simd_cycles
     lane_util = sq["SQ_THREAD_CYCLES_VALU"] / (sq["SQ_ACTIVE_INST_VALU"] * 64.0)
+    inst_frac = sq["SQ_INSTS_VALU"] * 64.0 / (dur * clock * N_CU * 64.0)
     fp64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] / dur / 78.6e12
     lds_busy = sq["SQ_LDS_IDX_ACTIVE"] / cu_cycles
     conflict = sq["SQ_LDS_BANK_CONFLICT"] / max(sq["SQ_LDS_IDX_ACTIVE"], 1.0)
     waves_per_simd = sq["SQ_WAVE_CYCLES"] * 4.0 / simd_cycles
     p = print
-    p("# %s on the n = 1000 table slice (9 cells x 100,000 replicates), MI355X" % KERNEL)
+    p("# %s on %s, MI355X" % (kernel, title))
     p()
-    p("Made by `paper_1305_6738_amd/profile.sh` (rocprofv3 on `bench.py --steps 5 --warmup 2 "
-      "--no-extras --no-cpu-baseline --tune paper_1305_6738_amd/tuning/mi355x.json "
-      "--copy-probe-mib 256`), summarised by `paper_1305_6738_amd/profile_summary.py`.")
+    p("Made by `paper_1305_6738_amd/profile.sh` (rocprofv3 on `bench.py %s`), summarised by "
+      "`paper_1305_6738_amd/profile_summary.py`." % bench_args)
     p()
     p("kernel_source_sha256: `%s`" % source_hash())
     p()
     p("| Figure | Value |")
     p("|---|---|")
-    p("| %s average duration, timed steps (kernel trace) | %.3f ms |" % (KERNEL, dur * 1e3))
+    p("| %s average duration, timed steps (kernel trace) | %.3f ms |" % (kernel, dur * 1e3))
     for r in stats:
-        if KERNEL in r["Name"]:
+        if kernel in r["Name"]:
             p("| %s average over all dispatches (rocprofv3 --stats) | %.3f ms (%s calls) |"
-              % (KERNEL, float(r["AverageNs"]) * 1e-6, r["Calls"]))
+              % (kernel, float(r["AverageNs"]) * 1e-6, r["Calls"]))
+    p("| clock over the dispatch (GRBM_COUNT / duration); GUI active share | %.3f GHz; %.1f %% |"
+      % (clock / 1e9, 100 * gui))
     p("| copy probe: FETCH_SIZE / WRITE_SIZE read for %d MiB | %.0f / %.0f KiB (scale %.3f / %.3f) |"
       % (COPY_MIB, copy_f[0]["FETCH_SIZE"] if copy_f else 0, copy_w[0]["WRITE_SIZE"] if copy_w else 0, sf, sw))
     p("| HBM bytes fetched per launch (scaled) | %.4g |" % fb)
     p("| HBM bytes written per launch (scaled) | %.4g |" % wb)
     p("| VALU busy (active VALU cycles / SIMD cycles) | %.1f %% |" % (100 * valu_busy))
     p("| VALU lane utilisation (thread cycles / 64 per active cycle) | %.1f %% |" % (100 * lane_util))
+    p("| executed VALU lane-instructions / lane-op peak at that clock | %.1f %% |" % (100 * inst_frac))
     p("| FP64 FLOP rate / 78.6 TFLOP/s | %.2f %% |" % (100 * fp64))
     p("| LDS busy (SQ_LDS_IDX_ACTIVE / CU cycles) | %.1f %% |" % (100 * lds_busy))
     p("| LDS bank-conflict cycles / LDS active cycles | %.1f %% |" % (100 * conflict))
-    p("| waves resident per SIMD (occupancy; LDS allows 2) | %.2f |" % waves_per_simd)
+    p("| waves resident per SIMD (occupancy) | %.2f |" % waves_per_simd)
     p("| VALU / SALU / LDS instructions per launch (wave-level) | %.4g / %.4g / %.4g |"
       % (sq["SQ_INSTS_VALU"], sq2["SQ_INSTS_SALU"], sq2["SQ_INSTS_LDS"]))
     p("| INT32 / INT64 VALU instructions | %.4g / %.4g |"
       % (sq2["SQ_INSTS_VALU_INT32"], sq2["SQ_INSTS_VALU_INT64"]))
+    p("| SQ_WAIT_INST_ANY / SQ_BUSY_CYCLES | %.4g / %.4g |"
+      % (sq2["SQ_WAIT_INST_ANY"], sq2["SQ_BUSY_CYCLES"]))
     p()
     p("traffic_bytes_per_launch: `%.6g`" % (fb + wb))
+    p("clock_ghz: `%.4f`" % (clock / 1e9))
+    p("valu_busy: `%.4f`" % valu_busy)
+    p("valu_lane_inst_frac: `%.4f`" % inst_frac)
+    p("fp64_frac: `%.5f`" % fp64)
+    p("waves_per_simd: `%.3f`" % waves_per_simd)
     p()
-    p("Clock assumed 2.4 GHz for the cycle-based fractions; SQ counters from the last timed "
-      "launch, traffic averaged over the timed launches.")
+    p("Cycle-based fractions use the measured clock; SQ counters from the last timed launch, "
+      "traffic averaged over the timed launches.")
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    main(sys.argv[1], sys.argv[2], sys.argv[3], sys.argv[4])

@@ -40,13 +40,14 @@ class Cell(C.Structure):
 
 class ServeOpts(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch", C.c_int32),
-                ("max_queue", C.c_int32), ("reserved", C.c_int32), ("reserved2", C.c_int32)]
+                ("max_queue", C.c_int32), ("slice_us", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class ServeResult(C.Structure):
     _fields_ = [("done", C.c_int32), ("status", C.c_int32), ("alpha_hat", C.c_double),
                 ("D", C.c_double), ("p_value", C.c_double), ("flags", C.c_uint32),
-                ("batch_size", C.c_int32), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+                ("batch_size", C.c_int32), ("queue_ms", C.c_double), ("latency_ms", C.c_double),
+                ("launches", C.c_int32), ("reserved", C.c_int32)]
 
 
 class TuneEntry(C.Structure):
@@ -93,7 +94,7 @@ def lib() -> C.CDLL:
         L.zpl_bootstrap_pvalue.restype = i32
         L.zpl_serve_start.argtypes = [vp, P(ServeOpts)]
         L.zpl_serve_start.restype = i32
-        L.zpl_serve_submit.argtypes = [vp, vp, i64, i64, u64, u32, P(u64)]
+        L.zpl_serve_submit.argtypes = [vp, vp, i64, i32, i64, u64, u32, P(u64)]
         L.zpl_serve_submit.restype = i32
         L.zpl_serve_poll.argtypes = [vp, u64, i32, P(ServeResult)]
         L.zpl_serve_poll.restype = i32
@@ -350,15 +351,19 @@ class Context:
         return {"alpha_hat": a.value, "D": D.value, "p_value": p.value, "flags": f.value}
 
     # -- serving (continuous batching) ---------------------------------------
-    def serve_start(self, mem_budget_bytes: int = 0, max_batch: int = 0, max_queue: int = 0):
-        o = ServeOpts(int(mem_budget_bytes), int(max_batch), int(max_queue), 0, 0)
+    def serve_start(self, mem_budget_bytes: int = 0, max_batch: int = 0, max_queue: int = 0,
+                    slice_us: int = 0):
+        o = ServeOpts(int(mem_budget_bytes), int(max_batch), int(max_queue), int(slice_us), 0)
         _check(lib().zpl_serve_start(self._h, C.byref(o)))
 
     def serve_submit(self, x, B: int, seed: int, stream_id: int = 0) -> int:
-        a = np.ascontiguousarray(np.asarray(x), dtype=np.int64)
+        """Queue a request; x is a host array or an int64 device tensor."""
+        ptr, n, on_dev, keep = _xarg(x)
         t = C.c_uint64()
-        _check(lib().zpl_serve_submit(self._h, C.c_void_p(a.ctypes.data), a.size, int(B),
-                                      int(seed), int(stream_id), C.byref(t)))
+        st = lib().zpl_serve_submit(self._h, ptr, n, on_dev, int(B), int(seed), int(stream_id),
+                                    C.byref(t))
+        del keep
+        _check(st)
         return t.value
 
     def serve_poll(self, ticket: int, wait_ms: int = 0) -> Optional[dict]:
@@ -368,7 +373,7 @@ class Context:
             return None
         return {"status": r.status, "alpha_hat": r.alpha_hat, "D": r.D, "p_value": r.p_value,
                 "flags": r.flags, "batch_size": r.batch_size, "queue_ms": r.queue_ms,
-                "latency_ms": r.latency_ms}
+                "latency_ms": r.latency_ms, "launches": r.launches}
 
     def serve_stop(self):
         _check(lib().zpl_serve_stop(self._h))

@@ -85,6 +85,13 @@ void hm_zeta3_trunc(double s, uint32_t K, double* out) {
   Z3 z = zeta3_trunc(s, K, g_ln.data());
   out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;
 }
+void hm_zeta3_trunc_em(double s, uint32_t K, double* out) {
+  Z3 z = zeta3_trunc_em(s, K, g_ln.data());
+  out[0] = z.z0; out[1] = z.z1; out[2] = z.z2;
+}
+void hm_moments012(double z, double* out) {
+  moments012(z, out[0], out[1], out[2]);
+}
 double hm_mle_trunc(double m, uint32_t K, uint32_t* flags) {
   return mle_alpha_trunc(m, K, g_ln.data(), flags);
 }

@@ -94,15 +94,28 @@ def test_bad_request_fails_alone(ctx):
     assert all(res[t]["status"] == 0 for t in tickets)
 
 
+def _stride(n):
+    p2 = 1
+    while p2 < n:
+        p2 <<= 1
+    half = max(p2, 2 * (1024 + n))
+    half = (half + 1) & ~1
+    return 2 * half
+
+
 def test_memory_admission_limits_batches(ctx):
-    # equal-size requests, and a budget with room for two of them but not
-    # three (a request is charged 32 B per data point, 8 B per bootstrap
-    # replicate and about 44 KB of table, guide and fixed scratch)
+    # equal-size requests (n = 3,000: each fitted by a workgroup) and a budget
+    # that admits two together but not a third: an active request holds 8 B
+    # per bootstrap replicate + 4 KiB, and admitting k datasets of n values
+    # also needs their data, 64 B each, 4 KiB and one workgroup fit's scratch
     rng = np.random.default_rng(9)
-    xs = [rng.zipf(2.0, 3000).astype(np.int64) for _ in range(12)]
-    B = 2000
-    per = 3000 * 32 + B * 8 + 45000
-    ctx.serve_start(mem_budget_bytes=2 * per + 1024)
+    n, B = 3000, 2000
+    xs = [rng.zipf(2.0, n).astype(np.int64) for _ in range(12)]
+    held = 8 * B + 4096
+    fit = lambda k: k * n * 8 + k * 64 + 4096 + _stride(n) * 8  # noqa: E731
+    budget = 2 * held + fit(2) + 1024
+    assert budget < 3 * held + fit(3)
+    ctx.serve_start(mem_budget_bytes=budget)
     try:
         tickets = [ctx.serve_submit(x, B, 11, k) for k, x in enumerate(xs)]
         huge = ctx.serve_submit(np.ones(10, np.int64), 1 << 30, 1, 1)  # alone > budget
@@ -112,3 +125,75 @@ def test_memory_admission_limits_batches(ctx):
     assert max(res[t]["batch_size"] for t in tickets) == 2
     assert all(res[t]["status"] == 0 for t in tickets)
     assert res[huge]["status"] == -2
+
+
+def test_serving_budget_above_context_budget_is_rejected():
+    from paper_1305_6738_amd import Context, zpl
+    with Context(0, mem_budget_bytes=1 << 30) as c:
+        with pytest.raises(zpl.ZplError):
+            c.serve_start(mem_budget_bytes=2 << 30)
+
+
+def test_late_small_request_overlaps_and_finishes_first(ctx):
+    """A short request submitted while a long bootstrap is in flight joins the
+    next launch, shares it with the long one and completes before it; both
+    results equal their bootstraps run alone (zpl_bootstrap_pvalue)."""
+    import time
+    rng = np.random.default_rng(21)
+    long_x = rng.zipf(2.2, 20000).astype(np.int64)
+    small_x = rng.zipf(2.7, 300).astype(np.int64)
+    ctx.serve_start(slice_us=2000)
+    try:
+        tl = ctx.serve_submit(long_x, 1000000, 5, 1)
+        time.sleep(0.01)  # the long request is admitted and its launches run
+        ts = ctx.serve_submit(small_x, 500, 6, 2)
+        rs = ctx.serve_poll(ts, wait_ms=60000)
+        long_pending = ctx.serve_poll(tl, wait_ms=0) is None
+        rl = ctx.serve_poll(tl, wait_ms=120000)
+    finally:
+        ctx.serve_stop()
+    say("small", rs, "long", rl)
+    assert rs["status"] == 0 and rl["status"] == 0
+    assert long_pending, "the long bootstrap finished before the short request"
+    assert rs["batch_size"] >= 2  # its launch also ran the long bootstrap's replicates
+    assert rl["launches"] > rs["launches"]
+    for x, B, seed, st, r in ((small_x, 500, 6, 2, rs), (long_x, 1000000, 5, 1, rl)):
+        d = ctx.bootstrap_pvalue(x, B, seed, st)
+        assert (d["alpha_hat"], d["D"], d["p_value"], d["flags"]) == \
+            (r["alpha_hat"], r["D"], r["p_value"], r["flags"])
+
+
+def test_device_datasets_equal_host_datasets(ctx):
+    xs = _datasets(13, 8)
+    ctx.serve_start()
+    try:
+        th = [ctx.serve_submit(x, 300, 40 + k, k) for k, x in enumerate(xs)]
+        td = [ctx.serve_submit(torch.from_numpy(x).cuda(), 300, 40 + k, k)
+              for k, x in enumerate(xs)]
+        res = _collect(ctx, th + td)
+    finally:
+        ctx.serve_stop()
+    for a, b in zip(th, td):
+        for f in ("status", "alpha_hat", "D", "p_value", "flags"):
+            assert res[a][f] == res[b][f], f
+
+
+def test_one_large_dataset_among_many_small_ones(ctx):
+    """A dataset of two million values admitted beside 255 small ones: the
+    batched fit's scratch is charged as it is allocated, and every request
+    completes (none fails the scheduler)."""
+    rng = np.random.default_rng(17)
+    big = rng.zipf(2.0, 2_000_000).astype(np.int64)
+    smalls = [rng.zipf(2.5, 100).astype(np.int64) for _ in range(255)]
+    ctx.serve_start(mem_budget_bytes=256 << 20)
+    try:
+        tickets = [ctx.serve_submit(big, 200, 3, 0)]
+        tickets += [ctx.serve_submit(x, 200, 3, 1 + k) for k, x in enumerate(smalls)]
+        res = _collect(ctx, tickets)
+    finally:
+        ctx.serve_stop()
+    assert all(r["status"] == 0 for r in res.values()), \
+        sorted(set(r["status"] for r in res.values()))
+    d = ctx.bootstrap_pvalue(big, 200, 3, 0)
+    r = res[tickets[0]]
+    assert (d["alpha_hat"], d["D"], d["p_value"]) == (r["alpha_hat"], r["D"], r["p_value"])

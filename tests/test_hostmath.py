@@ -51,6 +51,8 @@ def hm(tmp_path_factory):
     L.hm_survival_rel.argtypes = [C.c_double, C.c_int64, C.c_int64]
     L.hm_survival_rel.restype = C.c_double
     L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
+    L.hm_zeta3_trunc_em.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
+    L.hm_moments012.argtypes = [C.c_double, P(C.c_double)]
     L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
     L.hm_mle_trunc.restype = C.c_double
     for f, args in [("hm_mle_it", [C.c_double]), ("hm_mle_trunc_it", [C.c_double, C.c_uint32]),
@@ -230,6 +232,53 @@ def test_truncated_sums_vs_oracle(hm, orc, K):
         tol = 4e-16 * K + 2.3e-16 * abs(s) * math.log(K)
         for i in range(3):
             assert abs(out[i] - ref[i]) <= tol * abs(ref[i]) + 1e-300, (K, s, i)
+
+
+def test_moments_of_the_integral(hm):
+    """M_k(z) = int_0^1 v^k e^(zv) dv, k = 0..2 (series for |z| <= 2, closed
+    forms beyond) against mpmath quadrature at 30 digits, on both sides of
+    the switch and at z = 0."""
+    mp.mp.dps = 30
+    for z in (-300.0, -40.0, -4.0, -2.0000001, -2.0, -1.0, -1e-9, 0.0, 1e-12, 0.5, 1.999999,
+              2.0, 2.0000001, 3.0, 50.0, 400.0):
+        out = (C.c_double * 3)()
+        hm.hm_moments012(z, out)
+        for k in range(3):
+            ref = mp.quad(lambda v: v ** k * mp.e ** (z * v), [0, 1])
+            assert abs(out[k] - float(ref)) <= 4e-16 * abs(float(ref)), (z, k, out[k], ref)
+
+
+@pytest.mark.parametrize("K", [65, 66, 100, 500, 1000, 4096])
+def test_truncated_em_sums_vs_direct(hm, orc, K):
+    """Z_K, Z_K', Z_K'' by Euler-Maclaurin above q0 = max(17, ceil(1.6|s| + 10))
+    against the oracle's direct sums (pow per term), over the whole exponent
+    range, through s = 1 (where the integral term's 1/(1 - s) form is
+    singular) and both sides of every q0 step."""
+    for s in (-64.0, -40.0, -10.0, -4.375, -3.0, -1.0, -0.5, 0.0, 0.25, 0.999999, 1.0,
+              1.000001, 1.5, 2.5, 4.375, 4.376, 10.0, 40.0, 64.0):
+        q0 = max(17, math.ceil(1.6 * abs(s) + 10))
+        if K < q0 + 48:
+            continue
+        out = (C.c_double * 3)()
+        hm.hm_zeta3_trunc_em(s, K, out)
+        ref = orc.tz_norm3(s, K)
+        for i in range(3):
+            tol = (4e-16 * K + 2.3e-16 * abs(s) * math.log(K) + 2e-15) * abs(ref[i])
+            assert abs(out[i] - ref[i]) <= tol + 1e-300, (K, s, i, out[i], ref[i])
+
+
+def test_truncated_em_sums_vs_mpmath(hm):
+    """Z_K(s) and its derivatives at 30 digits (mpmath partial sums), where
+    the oracle is not involved."""
+    mp.mp.dps = 30
+    for K, s in ((1000, 0.5), (1000, 1.0), (1000, 2.5), (4096, -2.0), (300, 7.0)):
+        out = (C.c_double * 3)()
+        hm.hm_zeta3_trunc_em(s, K, out)
+        ks = [mp.mpf(k) for k in range(1, K + 1)]
+        ref = [mp.fsum(k ** -s for k in ks), -mp.fsum(mp.log(k) * k ** -s for k in ks),
+               mp.fsum(mp.log(k) ** 2 * k ** -s for k in ks)]
+        for i in range(3):
+            assert abs(out[i] - float(ref[i])) <= 2e-15 * abs(float(ref[i])), (K, s, i)
 
 
 @pytest.mark.parametrize("K", [2, 20, 1000, 4096])
