@@ -539,7 +539,7 @@ struct Summary {
   int len;
 };
 
-__device__ __noinline__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int oc, int64_t* lv,
+__device__ Summary build_list(uint32_t* hist, int nbins, const int64_t* ov, int oc, int64_t* lv,
                               uint32_t* lc, int lane, const double* __restrict__ ln, int64_t n,
                               bool want_fp) {
   const uint64_t below = lanes_below(lane);
