@@ -242,6 +242,28 @@ zpl_status zpl_fit_truncated(zpl_ctx *ctx, const int64_t *x, int64_t n, int32_t 
                              uint32_t kmax, double *alpha_hat, double *D, uint32_t *flags,
                              void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): zpl_fit
+ * (kmax = 0) or zpl_fit_truncated (kmax = K in 2..4096) of a device dataset
+ * into device outputs.  The call enqueues one kernel on `stream` and returns:
+ * it allocates nothing, copies nothing to the host and does not synchronise.
+ *   x_dev[n]        device int64; 1 <= n <= 2^20 (ZPL_EINVAL above that).
+ *   alpha_hat_dev, D_dev    device double[1];  flags_dev device uint32[1]
+ *                   (ZPL_FLAG_*; ZPL_FLAG_NOCONV where zpl_fit would return
+ *                   ZPL_ENOCONV).
+ *   status_dev      device uint32[1]: 0, or 2 when some x is out of range
+ *                   (below 1, or above kmax); then the other outputs are not
+ *                   written.
+ * Results are bit-identical to zpl_fit / zpl_fit_truncated on the same data.
+ * Scratch: a fixed device array of 2^22 + 4096 int64 (32 MiB and 32 KiB) per
+ * GPU, the library's own, held until the process ends and shared by every
+ * call on that GPU; it keeps the last call's contents (nothing in it must
+ * start at zero).  Calls whose work overlaps on one GPU (other streams, other
+ * contexts on the same device) race on it: serialise them. */
+zpl_status zpl_fit_noalloc(zpl_ctx *ctx, const int64_t *x_dev, int64_t n, uint32_t kmax,
+                           double *alpha_hat_dev, double *D_dev, uint32_t *flags_dev,
+                           uint32_t *status_dev, void *stream);
+
 /* Bespoke cutoff of Sect. 4 as a parametric-bootstrap p-value: fit x, then
  * simulate B replicates of n draws at alpha_hat (random stream (seed,
  * stream_id)), refit each by MLE (the tables apply only to MLE fits), and

@@ -115,6 +115,9 @@ struct zpl_ctx {
   uint64_t budget = 0;
   uint64_t used = 0;
   double* ln = nullptr;
+  // device address of the allocation-free fit's fixed scratch array on this
+  // context's GPU (looked up once, at creation)
+  int64_t* noalloc_scratch = nullptr;
   // scratch, grow-only
   DevBuf cells, tables, guides, units, hunits, queues, esc, esc_cnt, err, list_v, list_c,
       wslots, heavy, dbuf, gather, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d,
@@ -1347,6 +1350,14 @@ zpl_status zpl_create(zpl_ctx** out, int32_t device, uint64_t mem_budget_bytes) 
     delete c;
     return fail(ZPL_ENOMEM, "hipMalloc(ln): %s", hipGetErrorString(e));
   }
+  // the allocation-free fit's array: its device address on this GPU (the
+  // symbol itself is only a host-side stand-in)
+  e = noalloc_scratch_address(&c->noalloc_scratch);
+  if (e != hipSuccess || !c->noalloc_scratch) {
+    (void)hipFree(c->ln);
+    delete c;
+    return fail(ZPL_EDEVICE, "hipGetSymbolAddress(noalloc scratch): %s", hipGetErrorString(e));
+  }
   e = launch_ln_table(c->ln, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -1526,6 +1537,29 @@ zpl_status zpl_fit(zpl_ctx* c, const int64_t* x, int64_t n, int32_t x_on_device,
   ZPL_TRY(fit_device(c, xd, n, s, alpha_hat, D, flags, &st));
   if (st & kErrBadValue) return fail(ZPL_EINVAL, "every x must be >= 1");
   if (*flags & ZPL_FLAG_NOCONV) return fail(ZPL_ENOCONV, "MLE iteration cap reached");
+  return ZPL_OK;
+}
+
+zpl_status zpl_fit_noalloc(zpl_ctx* c, const int64_t* x_dev, int64_t n, uint32_t kmax,
+                           double* alpha_hat_dev, double* D_dev, uint32_t* flags_dev,
+                           uint32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!c || !x_dev || !alpha_hat_dev || !D_dev || !flags_dev || !status_dev)
+    return fail(ZPL_EINVAL, "NULL argument");
+  if (n < 1 || n > kNoAllocMaxN)
+    return fail(ZPL_EINVAL, "n must be in [1, %lld] (the fixed scratch of the allocation-free "
+                "fit holds one dataset of at most that size), got %lld",
+                (long long)kNoAllocMaxN, (long long)n);
+  if (kmax != 0 && (kmax < 2 || kmax > (uint32_t)kH))
+    return fail(ZPL_EINVAL, "kmax must be 0 or in [2, %d], got %u", kH, kmax);
+  const int64_t stride = heavy_stride(n);
+  if (stride > kNoAllocStride)
+    return fail(ZPL_EINVAL, "dataset of %lld values needs %lld scratch words, more than the "
+                "fixed %lld", (long long)n, (long long)stride, (long long)kNoAllocStride);
+  HIP_TRY(hipSetDevice(c->device));
+  // the workgroup fit gives the same bits as the one-wave fit at every n
+  HIP_TRY(launch_fit_block(x_dev, n, c->ln, c->noalloc_scratch, stride, alpha_hat_dev, D_dev,
+                           flags_dev, status_dev, kmax, (hipStream_t)stream));
   return ZPL_OK;
 }
 

@@ -2399,6 +2399,16 @@ hipError_t launch_fit_block(const int64_t* x, int64_t n, const double* ln, int64
   return hipGetLastError();
 }
 
+// Scratch of the allocation-free fit (overflow values and compact list of
+// one dataset, the heavy layout), one copy per GPU for the life of the
+// process.  Host code never passes this name to a kernel: it stands for the
+// host-side shadow; the device address comes from noalloc_scratch_address.
+static __device__ __align__(256) int64_t zpl_noalloc_scratch[kNoAllocStride];
+
+hipError_t noalloc_scratch_address(int64_t** p) {
+  return hipGetSymbolAddress((void**)p, HIP_SYMBOL(zpl_noalloc_scratch));
+}
+
 hipError_t launch_fit_scan(int grid, const int64_t* x, int64_t n, const int64_t* xmins,
                            int n_cand, const double* ln, int64_t* scratch, int64_t stride,
                            double* ahat, double* D, int64_t* ntail, uint32_t* flags,

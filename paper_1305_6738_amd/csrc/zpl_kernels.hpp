@@ -36,6 +36,13 @@ constexpr int kListCap = 16 * (kHW + kCW);
 // global scratch (sorted there).
 constexpr int kHeavyWaves = 4;
 constexpr int kHeavyHist = 1024;
+// Allocation-free fit: the overflow values and the compact list of one
+// dataset of up to kNoAllocMaxN values live in a fixed device array of
+// kNoAllocStride int64 (the heavy layout's stride for that n:
+// 2 * max(2^20, 2 * (kHeavyHist + 2^20))).
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 20;
+constexpr int64_t kNoAllocStride = 2 * (2 * ((int64_t)kHeavyHist + kNoAllocMaxN));
+
 // Quantiles per selection pass and the per-(cell, quantile) capacity of the
 // bracket gather scratch.
 constexpr int kSelQ = 4;

@@ -27,6 +27,9 @@ hipError_t launch_fit(int grid, const int64_t* const* xs, const int64_t* ns, int
 hipError_t launch_fit_block(const int64_t* x, int64_t n, const double* ln, int64_t* scratch,
                             int64_t stride, double* ahat, double* D, uint32_t* flags,
                             uint32_t* status, uint32_t K, hipStream_t s);
+// Device address of the fixed scratch array of the allocation-free fit
+// (kNoAllocStride int64) on the current device.
+hipError_t noalloc_scratch_address(int64_t** p);
 hipError_t launch_fit_scan(int grid, const int64_t* x, int64_t n, const int64_t* xmins,
                            int n_cand, const double* ln, int64_t* scratch, int64_t stride,
                            double* ahat, double* D, int64_t* ntail, uint32_t* flags,

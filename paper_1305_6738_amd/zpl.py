@@ -118,6 +118,8 @@ def lib() -> C.CDLL:
         L.zpl_fit_scan.restype = i32
         L.zpl_fit_xmin.argtypes = [vp, vp, i64, i32, i64, P(d), P(d), P(i64), P(u32), vp]
         L.zpl_fit_xmin.restype = i32
+        L.zpl_fit_noalloc.argtypes = [vp, vp, i64, u32, vp, vp, vp, vp, vp]
+        L.zpl_fit_noalloc.restype = i32
         _lib = L
     return _lib
 
@@ -128,7 +130,7 @@ def exported_symbols() -> list:
             "zpl_serve_start", "zpl_serve_submit", "zpl_serve_poll", "zpl_serve_stop",
             "zpl_sample_draws", "zpl_cdf_table", "zpl_autotune", "zpl_set_tuning",
             "zpl_plan_forms", "zpl_fit_truncated", "zpl_critical_table", "zpl_fit_scan",
-            "zpl_fit_xmin"]
+            "zpl_fit_xmin", "zpl_fit_noalloc"]
 
 
 FORM_NAMES = {FORM_LANE: "lane", FORM_WAVE: "wave", FORM_HEAVY: "heavy"}
@@ -338,6 +340,25 @@ class Context:
         if st not in (OK, ENOCONV):
             _check(st)
         return {"alpha_hat": a.value, "D": D.value, "flags": f.value, "status": st}
+
+    # -- zpl_fit_noalloc ----------------------------------------------------
+    def fit_noalloc(self, x, alpha_hat_out, D_out, flags_out, status_out, kmax: int = 0,
+                    stream=None):
+        """zpl_fit_noalloc: enqueue the fit of the device dataset x (int64
+        tensor) into the one-element device tensors alpha_hat_out, D_out
+        (float64), flags_out and status_out (int32/uint32); no allocation, no
+        synchronisation."""
+        import torch
+        if not getattr(x, "is_cuda", False) or x.dtype != torch.int64 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous int64 device tensor")
+        for t, dt in ((alpha_hat_out, torch.float64), (D_out, torch.float64),
+                      (flags_out, torch.int32), (status_out, torch.int32)):
+            if t.dtype not in (dt, torch.uint32) or t.numel() < 1:
+                raise ValueError("outputs: one-element float64 / int32 device tensors")
+        _check(lib().zpl_fit_noalloc(self._h, C.c_void_p(x.data_ptr()), int(x.numel()),
+                                     int(kmax), C.c_void_p(_dptr(alpha_hat_out)),
+                                     C.c_void_p(_dptr(D_out)), C.c_void_p(_dptr(flags_out)),
+                                     C.c_void_p(_dptr(status_out)), _stream(stream)))
 
     # -- zpl_bootstrap_pvalue -----------------------------------------------
     def bootstrap_pvalue(self, x, B: int, seed: int, stream_id: int = 0, stream=None) -> dict:
