@@ -39,6 +39,25 @@ def counters(d):
     return out
 
 
+def num_xcc(d):
+    """XCDs (accelerator complex dies) of the GPU agent: block counters such as
+    GRBM_COUNT are summed over them."""
+    for r in csv.DictReader(open(Path(d) / "run_agent_info.csv")):
+        if r.get("Agent_Type") == "GPU":
+            return max(int(r.get("Num_Xcc", 1) or 1), 1)
+    return 1
+
+
+def dispatch_seconds(d, key):
+    """{dispatch id: duration in s} of the kernel's dispatches in a counter run
+    (its own timestamps: counters serialise the dispatches)."""
+    out = {}
+    for r in csv.DictReader(open(Path(d) / "run_counter_collection.csv")):
+        if key in r["Kernel_Name"]:
+            out[int(r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    return out
+
+
 def last_dispatches(cs, key, count):
     sel = [(k, c) for k, (n, c) in cs.items() if key in n]
     return [c for _, c in sel[-count:]]
@@ -63,8 +82,12 @@ def main(out_dir, kernel, title, bench_args):
     wb = sum(w_k) / len(w_k) * sw * 1024.0
     sq = last_dispatches(counters(out / "sq"), kernel, STEPS)[-1]
     sq2 = last_dispatches(counters(out / "sq2"), kernel, STEPS)[-1]
-    # the clock over the kernel's dispatch: GRBM_COUNT ticks once per GPU clock
-    clock = sq2["GRBM_COUNT"] / dur if sq2.get("GRBM_COUNT") else NOMINAL_HZ
+    # the clock over the kernel's last counted dispatch: GRBM_COUNT ticks once
+    # per GPU clock on each XCD and the counter reads the sum over the XCDs
+    xcc = num_xcc(out / "sq2")
+    d2 = dispatch_seconds(out / "sq2", kernel)
+    d2s = d2[max(d2)] if d2 else dur
+    clock = sq2["GRBM_COUNT"] / xcc / d2s if sq2.get("GRBM_COUNT") else NOMINAL_HZ
     gui = sq2.get("GRBM_GUI_ACTIVE", 0.0) / max(sq2.get("GRBM_COUNT", 0.0), 1.0)
     simd_cycles = dur * clock * N_CU * SIMD_PER_CU
     cu_cycles = dur * clock * N_CU
@@ -90,8 +113,8 @@ def main(out_dir, kernel, title, bench_args):
         if kernel in r["Name"]:
             p("| %s average over all dispatches (rocprofv3 --stats) | %.3f ms (%s calls) |"
               % (kernel, float(r["AverageNs"]) * 1e-6, r["Calls"]))
-    p("| clock over the dispatch (GRBM_COUNT / duration); GUI active share | %.3f GHz; %.1f %% |"
-      % (clock / 1e9, 100 * gui))
+    p("| clock over the dispatch (GRBM_COUNT / %d XCDs / duration); GUI active share | %.3f GHz; %.1f %% |"
+      % (xcc, clock / 1e9, 100 * gui))
     p("| copy probe: FETCH_SIZE / WRITE_SIZE read for %d MiB | %.0f / %.0f KiB (scale %.3f / %.3f) |"
       % (COPY_MIB, copy_f[0]["FETCH_SIZE"] if copy_f else 0, copy_w[0]["WRITE_SIZE"] if copy_w else 0, sf, sw))
     p("| HBM bytes fetched per launch (scaled) | %.4g |" % fb)
