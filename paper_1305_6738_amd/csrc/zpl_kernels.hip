@@ -84,22 +84,6 @@ __device__ __forceinline__ uint64_t m53(uint32_t hi, uint32_t lo) {
   return ((((uint64_t)hi) << 32 | (uint64_t)lo) >> 11) | 1ull;
 }
 
-// Guide bin of U = m 2^-53.  U < 1/2: kGA bins uniform in U, bin m >> 44.
-// U > 1/2: e = 1 - U = (2^53 - m) 2^-53 exactly; the bin is given by the
-// octave and the top kGBits mantissa bits of e, which are the biased
-// exponent and mantissa fields of the double (2^53 - m) (exact, < 2^53)
-// shifted by 53 octaves.  Both parts are computed and one selected.
-__device__ __forceinline__ int guide_index(uint64_t m) {
-  const uint32_t mh = (uint32_t)(m >> 32);
-  const int ia = (int)(mh >> 12);
-  const double e = (double)((1ull << 53) - m);
-  const int q = (int)((uint32_t)(__double_as_longlong(e) >> 32) >> (20 - kGBits));
-  // bin = kGA + ((1021 - E) << kGBits) + (2^kGBits - 1 - s) for e = 2^(E-1023)(1.s...),
-  // and q = ((E + 53) << kGBits) | s
-  const int ib = kGA + ((1074 << kGBits) + ((1 << kGBits) - 1)) - q;
-  return mh < (1u << 20) ? ia : ib;
-}
-
 // Packed guide entry: bracket low in bits 0..15, high in bits 16..31.
 // Returns the draw, or 0 when it must be deferred.  A bracket with lo == hi
 // always has TI[lo] >= m, so the result is lo when TI[lo] >= m, hi when the
@@ -112,8 +96,8 @@ __device__ __forceinline__ int fast_select(uint32_t gg, uint64_t ti, uint64_t m,
 }
 
 __device__ __forceinline__ int fast_draw(uint64_t m, uint64_t timax, const uint64_t* __restrict__ T,
-                                         const uint32_t* __restrict__ guide) {
-  const uint32_t gg = guide[guide_index(m)];
+                                         const uint32_t* __restrict__ guide, int sh) {
+  const uint32_t gg = guide[guide_index(m, sh)];
   uint64_t ti = T[(int)(gg & 0xffffu) - 1];
   asm volatile("" : "+v"(ti));  // keep the read unconditional (no divergent branch)
   return fast_select(gg, ti, m, timax);
@@ -124,10 +108,11 @@ __device__ __forceinline__ int fast_draw(uint64_t m, uint64_t timax, const uint6
 // flight together: two LDS round trips per four draws instead of eight.
 __device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], uint64_t timax,
                                            const uint64_t* __restrict__ T,
-                                           const uint32_t* __restrict__ guide, int (&x)[4]) {
+                                           const uint32_t* __restrict__ guide, int sh,
+                                           int (&x)[4]) {
   uint32_t gg[4];
 #pragma unroll
-  for (int d = 0; d < 4; ++d) gg[d] = guide[guide_index(m[d])];
+  for (int d = 0; d < 4; ++d) gg[d] = guide[guide_index(m[d], sh)];
   uint64_t t[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
@@ -138,8 +123,8 @@ __device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], uint64_t tima
 
 // Full search of a deferred body draw.
 __device__ __forceinline__ int slow_search(uint64_t m, const uint64_t* __restrict__ T,
-                                           const uint32_t* __restrict__ guide) {
-  const uint32_t gg = guide[guide_index(m)];
+                                           const uint32_t* __restrict__ guide, int sh) {
+  const uint32_t gg = guide[guide_index(m, sh)];
   int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -151,8 +136,6 @@ __device__ __forceinline__ int slow_search(uint64_t m, const uint64_t* __restric
   return lo;
 }
 
-// Integer form of the table value F(kH) above which a uniform is a tail draw.
-__device__ __forceinline__ uint64_t table_int(double t) { return (uint64_t)(t * 0x1p53); }
 
 // Deferred draw of the lane and wave forms in 8 bytes.  Bit 63 clear: a body
 // draw, bits 0..52 = m.  Bit 63 set: a tail draw, bits 0..31 = its index in
@@ -168,12 +151,6 @@ __device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k
   return tail_draw(beta, gm, k0, k1, i, rep, stream, flags);
 }
 
-__device__ __noinline__ int64_t tail_draw_from_dev(double m0, double beta, double gm,
-                                                   uint32_t k0, uint32_t k1, uint32_t i,
-                                                   uint32_t rep, uint32_t stream,
-                                                   uint32_t* flags) {
-  return tail_draw_from(m0, beta, gm, k0, k1, i, rep, stream, flags);
-}
 
 // ---------------------------------------------------------------------------
 // KS distance (eq. 3) over the distinct values of one replicate, in
@@ -815,7 +792,7 @@ __device__ __forceinline__ int64_t resolve_entry(uint64_t e, uint32_t rep, const
                                                  uint32_t& fl) {
   if (e >> 63)
     return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep, c.stream, &fl);
-  return (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide);
+  return (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide, (int)c.gsh);
 }
 
 // Ring of deferred draws (lane and wave forms).  Before an iteration's
@@ -962,7 +939,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
     bool def[2 * kLaneBlocks];
     bool big = false;
     int xf[2 * kLaneBlocks];
-    fast_draw4(U, timax, T, guide, xf);
+    fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) {
       const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
@@ -1131,7 +1108,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         bool def[2 * kWaveBlocks];
         bool big = false;
         int xf[2 * kWaveBlocks];
-        fast_draw4(U, timax, T, guide, xf);
+        fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
 #pragma unroll
         for (int d = 0; d < 2 * kWaveBlocks; ++d) {
           const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
@@ -1401,10 +1378,10 @@ __device__ __forceinline__ int64_t resolve_entry_cut(uint64_t e, uint32_t rep, c
                                                      const uint64_t* __restrict__ T,
                                                      const uint32_t* __restrict__ guide,
                                                      uint32_t& fl) {
-  if (e >> 63)
-    return tail_draw_from_dev((double)(c.xmin + kH), c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep,
-                              c.stream, &fl);
-  return (c.xmin - 1) + (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide);
+  if (e >> 63)  // inline: heavy tails resolve thousands per replicate
+    return tail_draw_from((double)(c.xmin + kH), c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep,
+                          c.stream, &fl);
+  return (c.xmin - 1) + (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide, (int)c.gsh);
 }
 
 // Resolves ring entries [qh, qh + m) (one per lane) into the replicate.
@@ -1456,7 +1433,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
         U[2 * b + 1] = m53(w.w2, w.w3);
       }
       int xf[2 * kWaveBlocks];
-      fast_draw4(U, timax, T, guide, xf);
+      fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
       bool def[2 * kWaveBlocks];
 #pragma unroll
       for (int d = 0; d < 2 * kWaveBlocks; ++d) {
@@ -1828,6 +1805,9 @@ __global__ __launch_bounds__(1024) void k_table_trunc(const DevCell* __restrict_
 // b < kGA hold U in [b/(2 kGA), (b+1)/(2 kGA)); the others hold U with
 // e = 1 - U in one (octave, sub-bin) cell, i.e. U in (1 - e_hi, 1 - e_lo].
 // Entry kGuide is the sentinel kH.
+// Guide entry b: 1 + the first index k with floor(T[k] 2^53) >= the smallest
+// m of bin b (kH when none), the smallest value a uniform of the bin maps to;
+// the cell's layout from its table (guide_layout).
 __global__ __launch_bounds__(256) void k_guide(DevCell* __restrict__ cells,
                                               const double* __restrict__ tables,
                                               uint16_t* __restrict__ guides) {
@@ -1835,26 +1815,14 @@ __global__ __launch_bounds__(256) void k_guide(DevCell* __restrict__ cells,
   const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (b > kGuide) return;
   const double* T = tables + (size_t)cell * kH;
+  const int sh = guide_layout(T);
   int g = kH;
   if (b < kGuide) {
-    // first index with T >= target (part A) or T > target (part B)
-    double target;
-    bool strict;
-    if (b < kGA) {
-      target = (double)b / (double)(2 * kGA);
-      strict = false;
-    } else {
-      const int o = (b - kGA) >> kGBits;
-      const int s = ((1 << kGBits) - 1) - ((b - kGA) & ((1 << kGBits) - 1));
-      const double e_hi = ldexp(1.0 + (double)(s + 1) / (double)(1 << kGBits), -(o + 2));
-      target = 1.0 - e_hi;
-      strict = true;
-    }
+    const uint64_t mmin = guide_bin_min(b, sh);
     int lo = 0, hi = kH;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      const bool ok = strict ? (T[mid] > target) : (T[mid] >= target);
-      if (ok)
+      if (table_int(T[mid]) >= mmin)
         hi = mid;
       else
         lo = mid + 1;
@@ -1867,6 +1835,7 @@ __global__ __launch_bounds__(256) void k_guide(DevCell* __restrict__ cells,
     c.tmax = T[kH - 1];
     c.beta = c.alpha - 1.0;
     c.gm = tail_g(c.beta, (double)(c.xmin + kH));
+    c.gsh = (uint32_t)sh;
   }
 }
 
@@ -2318,7 +2287,7 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
     const uint64_t m = (i & 1u) ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
     const uint64_t timax = table_int(c.tmax);
     uint32_t fl = 0;
-    int64_t v = fast_draw(m, timax, T, guide);
+    int64_t v = fast_draw(m, timax, T, guide, (int)c.gsh);
     if (v != 0)
       v += c.xmin - 1;
     else

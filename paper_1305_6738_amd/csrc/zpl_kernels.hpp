@@ -8,10 +8,19 @@ namespace zpl {
 
 // Two-part guide table over U.  For U < 1/2: kGA bins uniform in U.  For
 // U > 1/2: bins on e = 1 - U (exact in FP64), one per (octave of e, top
-// kGBits mantissa bits), ordered so that the bin index increases with U.
-// Entry g[b] is the smallest k a uniform in bin b can map to, so U in bin b
-// maps into [g[b], g[b+1]].  On the Zipf law the survival is close to a power
-// of k, so log-scale bins keep most brackets one or two entries wide.
+// kGBits + gsh mantissa bits), ordered so that the bin index increases with
+// U.  Entry g[b] is the smallest k a uniform in bin b can map to, so U in bin
+// b maps into [g[b], g[b+1]].  On the Zipf law the survival is close to a
+// power of k, so log-scale bins keep most brackets one or two entries wide.
+// gsh (0..kGuideShMax, per cell) refines the bins when the table's part of
+// U > 1/2 spans few octaves of e (heavy tails: at alpha = 1.2 the table ends
+// at e = 0.17, two octaves): the 3,328 entries then cover 52 >> gsh octaves,
+// and indices of deeper octaves (tail draws) are clamped to the last entry.
+// gsh = kGuideUniform selects a uniform layout instead, for a table whose
+// support is bounded (the truncated law: no tail) and spread out: 2048 bins
+// uniform in U (bin m >> 42, entries from 2048 on unused).
+constexpr int kGuideShMax = 4;
+constexpr int kGuideUniform = 8;
 constexpr int kGA = 256;
 constexpr int kGBits = 6;
 constexpr int kOctaves = 52;  // e in [2^-53, 1/2)
@@ -65,7 +74,7 @@ struct DevCell {
   uint32_t stream;  // Philox counter word 2
   uint32_t mode;    // Mode
   uint32_t K;       // 0: the pure law; else the truncated law on 1..K
-  uint32_t pad;
+  uint32_t gsh;     // guide refinement: 2^(kGBits + gsh) bins per octave of 1 - U
   int64_t xmin;     // lower cutoff of the pure law (1: none); values >= xmin
 };
 

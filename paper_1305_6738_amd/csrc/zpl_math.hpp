@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "zpl_kernels.hpp"
+
 #define ZPL_HD __host__ __device__ __forceinline__
 
 namespace zpl {
@@ -841,6 +843,93 @@ ZPL_HD DD dd_log(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// Guide table over the uniform (layout in zpl_kernels.hpp).  The sampler
+// compares the uniform's odd 53-bit integer m (U = m 2^-53) with the table as
+// integers TI[k] = floor(T[k] 2^53): F(k) >= U exactly when TI[k] >= m.
+// ---------------------------------------------------------------------------
+ZPL_HD uint64_t table_int(double t) { return (uint64_t)(t * 0x1p53); }
+
+// Guide bin of U = m 2^-53 with sh refinement bits.  U < 1/2: kGA bins
+// uniform in U, bin m >> 44.  U > 1/2: e = 1 - U = (2^53 - m) 2^-53 exactly;
+// the bin is given by the octave and the top kGBits + sh mantissa bits of e,
+// which are the biased exponent and mantissa fields of the double (2^53 - m)
+// (exact, < 2^53) shifted by 53 octaves; bins past the last entry (octaves
+// of e below the table's end: tail draws, when sh > 0) are clamped to it.
+// Both parts are computed and one selected.
+ZPL_HD int guide_index(uint64_t m, int sh) {
+  const bool uni = sh == kGuideUniform;  // the uniform layout: bin m >> 42 for every m
+  const uint32_t mh = (uint32_t)(m >> 32);
+  const int ia = (int)(mh >> (uni ? 10 : 12));
+  const uint32_t lim = uni ? (1u << 21) : (1u << 20);
+  const double e = (double)((1ull << 53) - m);
+  const int nb = kGBits + (uni ? 0 : sh);
+  const int q = (int)((uint32_t)(__builtin_bit_cast(uint64_t, e) >> 32) >> (20 - nb));
+  // bin = kGA + ((1021 - E) << nb) + (2^nb - 1 - s) for e = 2^(E-1023)(1.s...),
+  // and q = ((E + 53) << nb) | s
+  const int ib = kGA + ((1074 << nb) + ((1 << nb) - 1)) - q;
+  const int ibc = ib < kGuide - 1 ? ib : kGuide - 1;
+  return mh < lim ? ia : ibc;
+}
+
+// The refinement of a cell's log-scale guide: the largest sh <= kGuideShMax
+// whose 52 >> sh octaves of e still reach the octave of the table's end
+// (e = 2^53 - timax, rounded to the next odd m: conservative), so that every
+// uniform that is not a tail draw has an unclamped bin.
+ZPL_HD int guide_refinement(uint64_t timax) {
+  if (timax < (1ull << 52)) return 0;
+  const uint64_t mt = (timax < (1ull << 53) - 1 ? timax : (1ull << 53) - 1) | 1ull;
+  const int o_last = (guide_index(mt, 0) - kGA) >> kGBits;
+  int sh = 0;
+  for (int s = 1; s <= kGuideShMax; ++s)
+    if (((o_last + 1) << (kGBits + s)) <= kGuide - kGA) sh = s;
+  return sh;
+}
+
+// First index k in T[0..kH) with T[k] >= t (kH when none).
+ZPL_HD int table_lower_bound(const double* T, double t) {
+  int lo = 0, hi = kH;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (T[mid] >= t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+// The cell's guide layout: the uniform one for a bounded support (no tail,
+// T[kH] = 1) whose values between the median and the upper quartile span
+// more than the 64 log-scale bins of that octave of U (the truncated law at
+// small exponents, nearly uniform on 1..K, where the log bins are several
+// values wide); else the log-scale layout with guide_refinement.
+ZPL_HD int guide_layout(const double* T) {
+  const uint64_t timax = table_int(T[kH - 1]);
+  if (timax >= (1ull << 53) &&
+      table_lower_bound(T, 0.75) - table_lower_bound(T, 0.5) > (1 << kGBits))
+    return kGuideUniform;
+  return guide_refinement(timax);
+}
+
+// The smallest m a uniform in bin b (0 <= b < kGuide) can have, in integers
+// (a bin of the U > 1/2 part can be narrower than the spacing of doubles
+// near 1, where 1 - e rounds).  In units of 2^-53 the bin's e lies below
+// e_hi = (2^nb + s + 1) 2^(51 - o - nb), so its largest integer e is
+// (2^nb + s) >> (o + nb - 51), or e_hi - 1 when e_hi is an integer.  The
+// guide entry is then 1 + the first index k with TI[k] >= guide_bin_min(b).
+ZPL_HD uint64_t guide_bin_min(int b, int sh) {
+  if (sh == kGuideUniform) return b < 2048 ? (uint64_t)b << 42 : (1ull << 53);
+  if (b < kGA) return (uint64_t)b << 44;
+  const int nb = kGBits + sh;
+  const int o = (b - kGA) >> nb;
+  const int s = ((1 << nb) - 1) - ((b - kGA) & ((1 << nb) - 1));
+  const uint64_t N = (1ull << nb) + (uint64_t)s + 1ull;
+  const int k = o + nb - 51;
+  const uint64_t emax = k >= 0 ? ((N - 1ull) >> k) : ((N << (-k)) - 1ull);
+  return (1ull << 53) - emax;
+}
+
+// ---------------------------------------------------------------------------
 // Tail sampler for U > T[kH].  Target on k >= m = kH + 1: p(k) ~ k^-a.
 // Proposal X = floor(Y), Y = m V^(-1/beta) (Pareto, beta = a - 1), so
 // P(X = k) ~ k^-beta - (k+1)^-beta; the ratio target/proposal is proportional
@@ -871,6 +960,19 @@ ZPL_HD int64_t dd_floor(DD y) {
   return X;
 }
 
+// The floor of Y = m0 V^(-1/beta) from a double-double evaluation, for the
+// proposals FP64 cannot decide (above 2^52 or within a relative 2^-44 of an
+// integer or of 2^63): false when Y >= 2^63 (the proposal is redrawn).  Out
+// of line: rare, and long (two double-double exponentials).
+static __host__ __device__ __noinline__ bool tail_floor_dd(double V, double beta, double m0,
+                                                           int64_t* X) {
+  const DD zd = dd_div_d(dd_log(V), -beta);
+  const DD Y = dd_mul_d(dd_exp(zd), m0);
+  if (Y.hi > 0x1p63 || (Y.hi == 0x1p63 && Y.lo >= 0.0)) return false;
+  *X = dd_floor(Y);
+  return true;
+}
+
 // Returns the accepted draw; ORs kFlagTailCapped into *flags if a proposal at
 // or above 2^63 was rejected.
 // Rejection tail on k >= m0 (m0 an integer below 2^53): kTailM for the pure
@@ -894,14 +996,9 @@ ZPL_HD int64_t tail_draw_from(double m0, double beta, double gm, uint32_t k0, ui
     if (y < 0x1p52 && y < two63 * (1.0 - 0x1p-40) && (y - fy) > tol &&
         (fy + 1.0 - y) > tol) {
       X = (int64_t)fy;
-    } else {
-      const DD zd = dd_div_d(dd_log(V), -beta);
-      const DD Y = dd_mul_d(dd_exp(zd), m0);
-      if (Y.hi > two63 || (Y.hi == two63 && Y.lo >= 0.0)) {
-        *flags |= kFlagTailCapped;
-        continue;
-      }
-      X = dd_floor(Y);
+    } else if (!tail_floor_dd(V, beta, m0, &X)) {
+      *flags |= kFlagTailCapped;
+      continue;
     }
     if (W * gm <= tail_g(beta, (double)X)) return X;
   }

@@ -92,6 +92,33 @@ void hm_zeta3_trunc_em(double s, uint32_t K, double* out) {
 void hm_moments012(double z, double* out) {
   moments012(z, out[0], out[1], out[2]);
 }
+int hm_guide_index(uint64_t m, int sh) { return guide_index(m, sh); }
+int hm_guide_refinement(uint64_t timax) { return guide_refinement(timax); }
+void hm_guide_index_many(const uint64_t* m, int64_t n, int sh, int32_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = guide_index(m[i], sh);
+}
+// The guide as the simulation builds it from a table T[0..kH): g[0..kGuide]
+// and the refinement; the same functions the guide kernel calls.
+int hm_guide_build(const double* T, uint16_t* g) {
+  const int sh = guide_layout(T);
+  for (int b = 0; b <= kGuide; ++b) {
+    int v = kH;
+    if (b < kGuide) {
+      const uint64_t mmin = guide_bin_min(b, sh);
+      int lo = 0, hi = kH;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (table_int(T[mid]) >= mmin)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      v = lo < kH ? lo + 1 : kH;
+    }
+    g[b] = (uint16_t)v;
+  }
+  return sh;
+}
 double hm_mle_trunc(double m, uint32_t K, uint32_t* flags) {
   return mle_alpha_trunc(m, K, g_ln.data(), flags);
 }

@@ -53,6 +53,13 @@ def hm(tmp_path_factory):
     L.hm_zeta3_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
     L.hm_zeta3_trunc_em.argtypes = [C.c_double, C.c_uint32, P(C.c_double)]
     L.hm_moments012.argtypes = [C.c_double, P(C.c_double)]
+    L.hm_guide_index.argtypes = [C.c_uint64, C.c_int]
+    L.hm_guide_index.restype = C.c_int
+    L.hm_guide_refinement.argtypes = [C.c_uint64]
+    L.hm_guide_refinement.restype = C.c_int
+    L.hm_guide_build.argtypes = [P(C.c_double), P(C.c_uint16)]
+    L.hm_guide_build.restype = C.c_int
+    L.hm_guide_index_many.argtypes = [P(C.c_uint64), C.c_int64, C.c_int, P(C.c_int32)]
     L.hm_mle_trunc.argtypes = [C.c_double, C.c_uint32, P(C.c_uint32)]
     L.hm_mle_trunc.restype = C.c_double
     for f, args in [("hm_mle_it", [C.c_double]), ("hm_mle_trunc_it", [C.c_double, C.c_uint32]),
@@ -485,3 +492,135 @@ def test_both_solvers_reach_the_cap_and_agree(hm, orc):
         ao, fo = orc.mle(m)
         assert it.value < 200 and orc.mle_last_iters() < 200, m
         assert f.value & 8 == 0 and fo & 8 == 0, m
+
+
+KH, KGUIDE = 4096, 256 + 52 * 64
+
+
+def _guide_tables(hm, orc):
+    """(label, T) for the guide checks: the library's pure-law tables over the
+    exponent range, the truncated law (uniform-like and steep) and the law with
+    a lower cutoff (the oracle's tables, which differ from the library's by a
+    few ulps at most; any table of increasing values serves)."""
+    out = []
+    for a in (1.01, 1.05, 1.2, 1.3, 1.4, 1.5, 1.75, 2.0, 2.5, 3.5, 8.0, 20.0, 64.0):
+        T = np.zeros(KH)
+        hm.hm_table(a, T.ctypes.data_as(C.POINTER(C.c_double)))
+        out.append(("pure %g" % a, T))
+    for g, K in ((0.25, 1000), (1.0, 4096), (3.0, 20), (-2.0, 4096)):
+        T = np.asarray(orc.tz_cdf_table(g, K), np.float64)  # 1..K; T[k] = 1 above K
+        out.append(("trunc %g K=%d" % (g, K), np.concatenate([T, np.ones(KH - T.size)])))
+    for a, xm in ((1.6, 500), (2.5, 10), (30.0, 3132)):
+        out.append(("cutoff %g xmin=%d" % (a, xm), np.asarray(orc.hz_cdf_table(a, xm), np.float64)))
+    return out
+
+
+def test_guide_bounds_and_brackets(hm, orc):
+    """The guide the kernels build (guide_refinement, guide_bin_min,
+    guide_index: the library's own code compiled for the host) on each table:
+    every entry in [1, kH] and non-decreasing; every uniform's bin index
+    inside [0, kGuide) (the simulation reads guide[b] and T[g[b] - 1] before
+    it knows whether the draw is a tail draw); and for every uniform not in
+    the tail, the drawn value min{k : floor(T[k] 2^53) >= m} lies in the
+    bracket [g[b], g[b + 1]].  Uniforms: 200,000 random odd m plus every table
+    value's integer and its neighbours, and the edges of both guide parts."""
+    rng = np.random.default_rng(12)
+    for label, T in _guide_tables(hm, orc):
+        T = np.ascontiguousarray(T, np.float64)
+        assert T.size == KH and np.all(np.diff(T) >= 0), label
+        g = np.zeros(KGUIDE + 1, np.uint16)
+        sh = hm.hm_guide_build(T.ctypes.data_as(C.POINTER(C.c_double)),
+                               g.ctypes.data_as(C.POINTER(C.c_uint16)))
+        assert 0 <= sh <= 4 or sh == 8, label
+        gi = g.astype(np.int64)
+        assert gi.min() >= 1 and gi.max() <= KH and np.all(np.diff(gi) >= 0), label
+        TI = (T * 2.0**53).astype(np.uint64)  # floor: T < 1 is exact after scaling
+        TI[T >= 1.0] = np.uint64(1 << 53)
+        timax = int(TI[-1])
+        ms = [rng.integers(1, 1 << 53, 200000, dtype=np.int64).astype(np.uint64) | np.uint64(1)]
+        near = (TI.astype(np.int64)[:, None] + np.arange(-2, 3)[None, :]).ravel()
+        near = near[(near >= 1) & (near < (1 << 53))].astype(np.uint64) | np.uint64(1)
+        # (a uniform's m is odd and below 2^53: timax may be 2^53, T = 1)
+        top = (1 << 53) - 1
+        edges = np.array([1, 3, (1 << 52) - 1, (1 << 52) + 1, (1 << 53) - 3, top,
+                          min(timax, top) | 1, max(min(timax, top) - 2, 1) | 1], np.uint64)
+        m = np.concatenate(ms + [near, edges])
+        idx = np.zeros(m.size, np.int32)
+        hm.hm_guide_index_many(m.ctypes.data_as(C.POINTER(C.c_uint64)), m.size, sh,
+                               idx.ctypes.data_as(C.POINTER(C.c_int32)))
+        assert idx.min() >= 0 and idx.max() < KGUIDE, label
+        lo, hi = gi[idx], gi[idx + 1]
+        body = m <= np.uint64(timax)
+        x = np.searchsorted(TI, m[body], side="left") + 1
+        assert np.all((lo[body] <= x) & (x <= hi[body])), (label, sh)
+        # the refinement leaves no uniform of the body in a clamped bin
+        if 0 < sh <= 4:
+            assert idx[body].max() < KGUIDE - 1, label
+        if sh == 8:  # the uniform layout uses bins 0..2047
+            assert idx.max() < 2048, label
+
+
+def test_guide_refinement_narrows_heavy_tails(hm):
+    """The refinement's purpose, on the library's tables: at alpha = 1.2 and
+    1.5 the share of body uniforms whose bracket is wider than two values
+    (deferred to a search) falls by more than half."""
+    rng = np.random.default_rng(3)
+    m = rng.integers(1, 1 << 53, 100000, dtype=np.int64).astype(np.uint64) | np.uint64(1)
+    for a, sh_expected in ((1.2, 4), (1.5, 3)):
+        T = np.zeros(KH)
+        hm.hm_table(a, T.ctypes.data_as(C.POINTER(C.c_double)))
+        g = np.zeros(KGUIDE + 1, np.uint16)
+        sh = hm.hm_guide_build(T.ctypes.data_as(C.POINTER(C.c_double)),
+                               g.ctypes.data_as(C.POINTER(C.c_uint16)))
+        assert sh == sh_expected
+        TI = (T * 2.0**53).astype(np.uint64)
+        body = m <= TI[-1]
+
+        def wide(s, gg):
+            idx = np.zeros(m.size, np.int32)
+            hm.hm_guide_index_many(m.ctypes.data_as(C.POINTER(C.c_uint64)), m.size, s,
+                                   idx.ctypes.data_as(C.POINTER(C.c_int32)))
+            w = gg.astype(np.int64)[idx + 1] - gg.astype(np.int64)[idx]
+            return np.mean(w[body] > 1)
+        # the same table's guide without refinement, built in Python
+        g0 = np.zeros(KGUIDE + 1, np.int64)
+        for b in range(KGUIDE):
+            if b < 256:
+                mmin = b << 44
+            else:
+                o, s_ = (b - 256) >> 6, 63 - ((b - 256) & 63)
+                N, k = 64 + s_ + 1, o + 6 - 51
+                emax = ((N - 1) >> k) if k >= 0 else ((N << (-k)) - 1)
+                mmin = (1 << 53) - emax
+            j = int(np.searchsorted(TI, np.uint64(mmin), side="left"))
+            g0[b] = j + 1 if j < KH else KH
+        g0[KGUIDE] = KH
+        assert wide(sh, g) < 0.5 * wide(0, g0), a
+
+
+def test_guide_uniform_layout_for_spread_bounded_support(hm, orc):
+    """The truncated law at a small exponent (nearly uniform on 1..K) takes
+    the uniform layout, and its share of deferred (wide-bracket) body uniforms
+    falls below 1 %, from above half with the log-scale layout; a steep
+    truncated law and every pure-law table keep the log-scale layout."""
+    rng = np.random.default_rng(4)
+    m = rng.integers(1, 1 << 53, 100000, dtype=np.int64).astype(np.uint64) | np.uint64(1)
+    for g_, K, uni in ((0.25, 1000, True), (0.5, 1000, True), (3.0, 1000, False)):
+        T = np.asarray(orc.tz_cdf_table(g_, K), np.float64)
+        T = np.concatenate([T, np.ones(KH - T.size)])
+        gg = np.zeros(KGUIDE + 1, np.uint16)
+        sh = hm.hm_guide_build(T.ctypes.data_as(C.POINTER(C.c_double)),
+                               gg.ctypes.data_as(C.POINTER(C.c_uint16)))
+        assert (sh == 8) == uni, (g_, K, sh)
+        if uni:
+            idx = np.zeros(m.size, np.int32)
+            hm.hm_guide_index_many(m.ctypes.data_as(C.POINTER(C.c_uint64)), m.size, sh,
+                                   idx.ctypes.data_as(C.POINTER(C.c_int32)))
+            w = gg.astype(np.int64)[idx + 1] - gg.astype(np.int64)[idx]
+            assert np.mean(w > 1) < 0.01, (g_, K)
+    for a in (1.01, 1.2, 2.5, 64.0):
+        T = np.zeros(KH)
+        hm.hm_table(a, T.ctypes.data_as(C.POINTER(C.c_double)))
+        gg = np.zeros(KGUIDE + 1, np.uint16)
+        assert hm.hm_guide_build(T.ctypes.data_as(C.POINTER(C.c_double)),
+                                 gg.ctypes.data_as(C.POINTER(C.c_uint16))) <= 4
