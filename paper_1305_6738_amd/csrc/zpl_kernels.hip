@@ -396,11 +396,18 @@ __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_
   int64_t C = 0;
   double D = 0.0;
   int p = 0;
+  // the list's first 64 entries, one per lane, in one round of loads; the
+  // values <= 16 (at most the first 16 entries) are then read across lanes
+  // instead of by a chain of dependent global loads
+  const int64_t hv = lane < len ? lv[lane] : INT64_MAX;
+  const uint32_t hc = lane < len ? lc[lane] : 0u;
 #pragma unroll
   for (int v = 1; v <= 16; ++v) {
-    if (p < len && lv[p] == (int64_t)v) {
+    const int64_t pv = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(uint32_t)(hv >> 32), p, 64) << 32) |
+                                 (uint32_t)__shfl((int)(uint32_t)hv, p, 64));
+    if (p < len && pv == (int64_t)v) {
       const double t2 = fabs(fma(suf[v - 1], iz, -(double)(n - C) * idn));
-      C += lc[p];
+      C += (uint32_t)__shfl((int)hc, p, 64);
       const double t1 = fabs(fma(suf[v], iz, -(double)(n - C) * idn));
       D = fmax(D, fmax(t1, t2));
       ++p;
@@ -417,8 +424,14 @@ __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_
     int64_t vprev = q0 == p16 ? 16 : lv[q0 - 1];
     double zprev = suf[16];
     bool have = q0 == p16;  // zprev is zeta(a, vprev + 1)
+    // the next entry is loaded before this one's arithmetic, so the load's
+    // latency overlaps it
+    int64_t v = lv[q0];
+    uint32_t cv = lc[q0];
     for (int q = q0; q < q1; ++q) {
-      const int64_t v = lv[q];
+      const int qn = q + 1 < q1 ? q + 1 : q;
+      const int64_t vn = lv[qn];
+      const uint32_t cn = lc[qn];
       const double zv = xrel ? survival_rel(E, v, xrel)
                              : (cut ? survival_next_cut(E, v, ln) : survival_next(E, v, ln));
       double zv1;
@@ -429,12 +442,14 @@ __device__ double ks_distance_wave(const int64_t* __restrict__ lv, const uint32_
       else
         zv1 = zv + (xrel ? pow_rel(E.s, v, xrel) : pow_neg(E.s, ln_value(v, ln)));
       const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
-      C += lc[q];
+      C += cv;
       const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
       D = fmax(D, fmax(t1, t2));
       zprev = zv;
       vprev = v;
       have = true;
+      v = vn;
+      cv = cn;
     }
   }
   return wave_max_f64(D);
@@ -726,20 +741,30 @@ __device__ __forceinline__ void mem_group(int64_t* g, int P, int k, int j1, int 
   const int p = 31 - __builtin_clz((unsigned)j1);
   const int low = p - G + 1;
   const int lowmask = (1 << low) - 1;
-  for (int q = lane; q < (P >> G); q += 64) {
-    const int b = ((q >> low) << (p + 1)) | (q & lowmask);
-    const bool up = (b & k) == 0;
-    int64_t v[NE];
+  // two groups per lane per step (P >> G is a multiple of 128 for P >= 1024),
+  // all their loads in flight before the compare-exchanges
+  for (int q = lane; q < (P >> G); q += 128) {
+    int b[2];
+    int64_t v[2][NE];
 #pragma unroll
-    for (int e = 0; e < NE; ++e) v[e] = g[b + (e << low)];
+    for (int h = 0; h < 2; ++h) {
+      const int qq = q + 64 * h;
+      b[h] = ((qq >> low) << (p + 1)) | (qq & lowmask);
 #pragma unroll
-    for (int sft = G - 1; sft >= 0; --sft) {
-#pragma unroll
-      for (int e = 0; e < NE; ++e)
-        if ((e & (1 << sft)) == 0) cmpx(v[e], v[e | (1 << sft)], up);
+      for (int e = 0; e < NE; ++e) v[h][e] = g[b[h] + (e << low)];
     }
 #pragma unroll
-    for (int e = 0; e < NE; ++e) g[b + (e << low)] = v[e];
+    for (int h = 0; h < 2; ++h) {
+      const bool up = (b[h] & k) == 0;
+#pragma unroll
+      for (int sft = G - 1; sft >= 0; --sft) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+          if ((e & (1 << sft)) == 0) cmpx(v[h][e], v[h][e | (1 << sft)], up);
+      }
+#pragma unroll
+      for (int e = 0; e < NE; ++e) g[b[h] + (e << low)] = v[h][e];
+    }
   }
 }
 
@@ -756,11 +781,16 @@ __device__ void wave_sort_global(int64_t* g, int P, int lane) {
     wave_sync_global();
     return;
   }
-  for (int base = 0; base < P; base += 512) {
-    int64_t v[8];
+  // two 512-value blocks per step (P >= 1024 holds an even number), both
+  // blocks' loads in flight together
+  for (int base = 0; base < P; base += 1024) {
+    int64_t v[8], w[8];
     block_load<8>(v, g + base, lane);
+    block_load<8>(w, g + base + 512, lane);
     block_sort<8>(v, base, lane);
+    block_sort<8>(w, base + 512, lane);
     block_store<8>(v, g + base, lane);
+    block_store<8>(w, g + base + 512, lane);
   }
   wave_sync_global();
   for (int k = 1024; k <= P; k <<= 1) {
@@ -776,11 +806,14 @@ __device__ void wave_sort_global(int64_t* g, int P, int lane) {
       wave_sync_global();
       j >>= G;
     }
-    for (int base = 0; base < P; base += 512) {
-      int64_t v[8];
+    for (int base = 0; base < P; base += 1024) {
+      int64_t v[8], w[8];
       block_load<8>(v, g + base, lane);
+      block_load<8>(w, g + base + 512, lane);
       block_passes<8>(v, base, k, 256, lane);
+      block_passes<8>(w, base + 512, k, 256, lane);
       block_store<8>(v, g + base, lane);
+      block_store<8>(w, g + base + 512, lane);
     }
     wave_sync_global();
   }
