@@ -84,30 +84,27 @@ __device__ __forceinline__ uint64_t m53(uint32_t hi, uint32_t lo) {
   return ((((uint64_t)hi) << 32 | (uint64_t)lo) >> 11) | 1ull;
 }
 
-// Packed guide entry: bracket low in bits 0..15, high in bits 16..31.
-// Returns the draw, or 0 when it must be deferred.  A bracket with lo == hi
-// always has TI[lo] >= m, so the result is lo when TI[lo] >= m, hi when the
-// bracket is two wide, else deferred; tail uniforms (m > TI[kH]) are
-// deferred.  Every m indexes a valid guide entry and lo >= 1.
-__device__ __forceinline__ int fast_select(uint32_t gg, uint64_t ti, uint64_t m, uint64_t timax) {
-  const int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
-  const int x = ti >= m ? lo : (hi == lo + 1 ? hi : 0);
-  return m > timax ? 0 : x;
+// Packed guide entry (guide_pack): the draw is lo when TI[lo] >= m (a
+// bracket [lo, lo] always has it); otherwise the high half, which is hi when
+// that is the answer, else >= kDeferred: the draw is deferred (a wider
+// bracket, or a tail uniform m > TI[kH], which never has TI[lo] >= m).
+// Every m indexes a valid guide entry and 1 <= lo <= kH.
+__device__ __forceinline__ int fast_select(uint32_t gg, uint64_t ti, uint64_t m) {
+  return ti >= m ? (int)(gg & 0xffffu) : (int)(gg >> 16);
 }
 
-__device__ __forceinline__ int fast_draw(uint64_t m, uint64_t timax, const uint64_t* __restrict__ T,
+__device__ __forceinline__ int fast_draw(uint64_t m, const uint64_t* __restrict__ T,
                                          const uint32_t* __restrict__ guide, int sh) {
   const uint32_t gg = guide[guide_index(m, sh)];
   uint64_t ti = T[(int)(gg & 0xffffu) - 1];
   asm volatile("" : "+v"(ti));  // keep the read unconditional (no divergent branch)
-  return fast_select(gg, ti, m, timax);
+  return fast_select(gg, ti, m);
 }
 
 // fast_draw for four draws at once, in phases (all guide reads, then all
 // table reads, then the selections) so that the reads of each phase are in
 // flight together: two LDS round trips per four draws instead of eight.
-__device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], uint64_t timax,
-                                           const uint64_t* __restrict__ T,
+__device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int sh,
                                            int (&x)[4]) {
   uint32_t gg[4];
@@ -118,14 +115,14 @@ __device__ __forceinline__ void fast_draw4(const uint64_t (&m)[4], uint64_t tima
   for (int d = 0; d < 4; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
   asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));  // reads stay unconditional
 #pragma unroll
-  for (int d = 0; d < 4; ++d) x[d] = fast_select(gg[d], t[d], m[d], timax);
+  for (int d = 0; d < 4; ++d) x[d] = fast_select(gg[d], t[d], m[d]);
 }
 
 // Full search of a deferred body draw.
 __device__ __forceinline__ int slow_search(uint64_t m, const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int sh) {
   const uint32_t gg = guide[guide_index(m, sh)];
-  int lo = (int)(gg & 0xffffu), hi = (int)(gg >> 16);
+  int lo = (int)(gg & 0xffffu), hi = (int)((gg >> 16) & (kDeferred - 1));
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (T[mid - 1] >= m)
@@ -889,15 +886,23 @@ struct SimLds {
   int unit;
 };
 
+// Out of line: inlined into the persistent kernels' cell switch it takes
+// registers from their hot loops.
+static __device__ __noinline__ uint32_t guide_pack_dev(const uint16_t* g, int b, int sh,
+                                                       uint64_t timax) {
+  return guide_pack(g, b, sh, timax);
+}
+
 // Stages the cell's table, as integers floor(F(k) 2^53), and packed guide
-// (g[b] | g[b+1] << 16) into LDS.
+// (guide_pack) into LDS.
 __device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
                                                  const double* __restrict__ Tg,
-                                                 const uint16_t* __restrict__ g, int tid,
-                                                 int nthreads) {
+                                                 const uint16_t* __restrict__ g,
+                                                 const DevCell& c, int tid, int nthreads) {
   for (int k = tid; k < kH; k += nthreads) T[k] = table_int(Tg[k]);
-  for (int b = tid; b < kGuide; b += nthreads)
-    guide[b] = (uint32_t)g[b] | ((uint32_t)g[b + 1] << 16);
+  const uint64_t timax = table_int(c.tmax);
+  const int sh = (int)c.gsh;
+  for (int b = tid; b < kGuide; b += nthreads) guide[b] = guide_pack_dev(g, b, sh, timax);
 }
 
 // ---------------------------------------------------------------------------
@@ -935,7 +940,8 @@ __device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qh, in
 }
 
 // Draw blocks per iteration of the lane form's loop (two draws each).
-constexpr int kLaneBlocks = 2;
+constexpr int kLaneBlocks = 2;  // four draws per lane and iteration
+static_assert(kLaneBlocks == 2, "the draw loop keeps four table reads in flight");
 
 __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int64_t rep0,
                                           int count, LaneRegion* L, int lane,
@@ -956,29 +962,57 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   // Deferred draws wait in a ring (head qh, qn entries, both wave-uniform).
   uint32_t qh = 0, qn = 0;
   const uint64_t timax = table_int(c.tmax);
-  for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
+  const int sh = (int)c.gsh;
+  const uint32_t n32 = (uint32_t)n;  // draw indexes are 32-bit
+  // The loop is software-pipelined: an iteration issues the guide reads of
+  // its uniforms, generates the next iteration's uniforms while they are in
+  // flight, issues the table reads, and computes the next guide indexes while
+  // those are in flight (one extra block of uniforms is generated at the end).
+  auto gen = [&](uint32_t j, uint64_t (&Uo)[2 * kLaneBlocks]) {
     // the round keys are recomputed per block with scalar adds rather than
     // kept live across the loop (where they would be spilled)
     uint32_t k0 = c.k0, k1 = c.k1;
     asm volatile("" : "+s"(k0), "+s"(k1));
-    uint64_t U[2 * kLaneBlocks];  // uniforms as 53-bit integers m
 #pragma unroll
     for (int b = 0; b < kLaneBlocks; ++b) {
       const Words4 w = philox4x32_10(j + (uint32_t)b, r, c.stream, 0u, k0, k1);
-      U[2 * b] = m53(w.w0, w.w1);
-      U[2 * b + 1] = m53(w.w2, w.w3);
+      Uo[2 * b] = m53(w.w0, w.w1);
+      Uo[2 * b + 1] = m53(w.w2, w.w3);
     }
+  };
+  uint64_t U[2 * kLaneBlocks];  // uniforms as 53-bit integers m
+  int gi[2 * kLaneBlocks];      // their guide bins
+  gen(0u, U);
+#pragma unroll
+  for (int d = 0; d < 2 * kLaneBlocks; ++d) gi[d] = guide_index(U[d], sh);
+  for (uint32_t j = 0; j < nblk; j += kLaneBlocks) {
+    uint32_t gg[2 * kLaneBlocks];
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) gg[d] = guide[gi[d]];
+    uint64_t Un[2 * kLaneBlocks];
+    gen(j + (uint32_t)kLaneBlocks, Un);
+    asm volatile("" : "+v"(Un[0]), "+v"(Un[1]), "+v"(Un[2]), "+v"(Un[3]));  // made here
+    uint64_t t[2 * kLaneBlocks];
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
+    __builtin_amdgcn_sched_barrier(0);  // the table reads issue before the index math
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) gi[d] = guide_index(Un[d], sh);
+    asm volatile("" : "+v"(gi[0]), "+v"(gi[1]), "+v"(gi[2]), "+v"(gi[3]));  // made here
+    asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));  // reads stay unconditional
     int x[2 * kLaneBlocks];
     bool def[2 * kLaneBlocks];
     bool big = false;
     int xf[2 * kLaneBlocks];
-    fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) xf[d] = fast_select(gg[d], t[d], U[d]);
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) {
-      const bool valid = active && (int64_t)(2u * j + (uint32_t)d) < n;
+      const bool valid = active && 2u * j + (uint32_t)d < n32;
       const int xd = xf[d];
-      x[d] = valid ? xd : -1;
-      def[d] = valid && xd == 0;
+      const bool drawn = xd < kDeferred;
+      x[d] = valid && drawn ? xd : -1;
+      def[d] = valid && !drawn;
       big = big || x[d] > kHLB;
       // own column, no branch: values outside 1..kHLB add zero to dword 0
       const bool col = x[d] >= 1 && x[d] <= kHLB;
@@ -998,6 +1032,8 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
       qn -= 64u;
     }
+#pragma unroll
+    for (int d = 0; d < 2 * kLaneBlocks; ++d) U[d] = Un[d];
   }
   if (qn > 0u) lane_drain(L, (int)qn, qh, rep0, c, T, guide, lane);
   wave_sync();
@@ -1093,6 +1129,7 @@ __device__ __forceinline__ void wave_drain(WaveRegion* L, int m, uint32_t qh, ui
 
 // Draw blocks per lane per iteration of the wave form's loop.
 constexpr int kWaveBlocks = 2;
+static_assert(kWaveBlocks == 2, "the draw loop keeps four table reads in flight");
 
 __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, int64_t r0,
                                            int nrep, WaveRegion* L, WaveSlot* slots,
@@ -1126,29 +1163,54 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
       uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
       const uint64_t timax = table_int(c.tmax);
-      for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
+      const int sh = (int)c.gsh;
+      const uint32_t n32 = (uint32_t)n;  // n <= 2^31
+      // software-pipelined as the lane form's loop
+      auto gen = [&](uint32_t j0, uint64_t (&Uo)[2 * kWaveBlocks]) {
         uint32_t k0 = c.k0, k1 = c.k1;  // round keys per block (see lane_wave)
         asm volatile("" : "+s"(k0), "+s"(k1));
-        uint64_t U[2 * kWaveBlocks];  // uniforms as 53-bit integers m
 #pragma unroll
         for (int b = 0; b < kWaveBlocks; ++b) {
           const Words4 w = philox4x32_10(j0 + 64u * (uint32_t)b + (uint32_t)lane, r, c.stream,
                                          0u, k0, k1);
-          U[2 * b] = m53(w.w0, w.w1);
-          U[2 * b + 1] = m53(w.w2, w.w3);
+          Uo[2 * b] = m53(w.w0, w.w1);
+          Uo[2 * b + 1] = m53(w.w2, w.w3);
         }
+      };
+      uint64_t U[2 * kWaveBlocks];  // uniforms as 53-bit integers m
+      int gi[2 * kWaveBlocks];      // their guide bins
+      gen(0u, U);
+#pragma unroll
+      for (int d = 0; d < 2 * kWaveBlocks; ++d) gi[d] = guide_index(U[d], sh);
+      for (uint32_t j0 = 0; j0 < nblk; j0 += 64u * kWaveBlocks) {
+        uint32_t gg[2 * kWaveBlocks];
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) gg[d] = guide[gi[d]];
+        uint64_t Un[2 * kWaveBlocks] = {1ull, 1ull, 1ull, 1ull};
+        if (j0 + 64u * kWaveBlocks < nblk) gen(j0 + 64u * kWaveBlocks, Un);  // none past the end
+        asm volatile("" : "+v"(Un[0]), "+v"(Un[1]), "+v"(Un[2]), "+v"(Un[3]));  // made here
+        uint64_t t[2 * kWaveBlocks];
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) t[d] = T[(int)(gg[d] & 0xffffu) - 1];
+        __builtin_amdgcn_sched_barrier(0);  // the table reads issue before the index math
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) gi[d] = guide_index(Un[d], sh);
+        asm volatile("" : "+v"(gi[0]), "+v"(gi[1]), "+v"(gi[2]), "+v"(gi[3]));  // made here
+        asm volatile("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));  // reads stay unconditional
         int x[2 * kWaveBlocks];
         bool def[2 * kWaveBlocks];
         bool big = false;
         int xf[2 * kWaveBlocks];
-        fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) xf[d] = fast_select(gg[d], t[d], U[d]);
 #pragma unroll
         for (int d = 0; d < 2 * kWaveBlocks; ++d) {
           const uint32_t i = 2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
-          const bool valid = (int64_t)i < n;
+          const bool valid = i < n32;
           const int xd = xf[d];
-          x[d] = valid ? xd : -1;
-          def[d] = valid && xd == 0;
+          const bool drawn = xd < kDeferred;
+          x[d] = valid && drawn ? xd : -1;
+          def[d] = valid && !drawn;
           big = big || x[d] > kHW;
           // values 1..3 are counted from ballots (the loop is wave-uniform);
           // the others add 1 to their bin, and lanes with nothing to add put
@@ -1156,6 +1218,9 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           c1 += (uint32_t)__popcll(__ballot(x[d] == 1));
           c2 += (uint32_t)__popcll(__ballot(x[d] == 2));
           c3 += (uint32_t)__popcll(__ballot(x[d] == 3));
+          // counted here: the twelve ballot masks of an iteration are not
+          // all kept live in scalar registers (they would be spilled)
+          asm volatile("" : "+s"(c1), "+s"(c2), "+s"(c3));
           const bool hb = x[d] > 3 && x[d] <= kHW;
           atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], hb ? 1u : 0u);
           xm = max(xm, x[d] <= kHW ? x[d] : 0);
@@ -1175,6 +1240,8 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
           qn -= 64u;
         }
+#pragma unroll
+        for (int d = 0; d < 2 * kWaveBlocks; ++d) U[d] = Un[d];
       }
       if (qn > 0u) wave_drain(L, (int)qn, qh, r, c, T, guide, fl, xm, lane);
       fl = wave_or_u32(fl);
@@ -1283,7 +1350,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_simulate(
     const DevCell c = cells[un.cell];
     if (un.cell != loaded) {
       load_cell_tables(L.T, L.guide, tables + (size_t)un.cell * kH,
-                       guides + (size_t)un.cell * (kGuide + 1), tid, kBlock);
+                       guides + (size_t)un.cell * (kGuide + 1), c, tid, kBlock);
       loaded = un.cell;
       __syncthreads();
     }
@@ -1466,15 +1533,16 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
         U[2 * b + 1] = m53(w.w2, w.w3);
       }
       int xf[2 * kWaveBlocks];
-      fast_draw4(U, timax, T, guide, (int)c.gsh, xf);
+      fast_draw4(U, T, guide, (int)c.gsh, xf);
       bool def[2 * kWaveBlocks];
 #pragma unroll
       for (int d = 0; d < 2 * kWaveBlocks; ++d) {
         const uint32_t i =
             2u * (j0 + 64u * (uint32_t)(d >> 1) + (uint32_t)lane) + (uint32_t)(d & 1);
         const bool valid = (int64_t)i < n;
-        def[d] = valid && xf[d] == 0;
-        heavy_put(W, gov, off + (int64_t)xf[d], valid && xf[d] != 0, ones, ovn, lane, below);
+        const bool drawn = xf[d] < kDeferred;
+        def[d] = valid && !drawn;
+        heavy_put(W, gov, off + (int64_t)xf[d], valid && drawn, ones, ovn, lane, below);
       }
       ring_append(W->ring, qh, qn, def, [&](int d) {
         return defer_entry(U[d], timax,
@@ -1535,7 +1603,7 @@ __global__ __launch_bounds__(64 * kHeavyWaves, 2) void k_heavy(
     const DevCell c = cells[un.cell];
     if (un.cell != loaded) {
       load_cell_tables(L.T, L.guide, tables + (size_t)un.cell * kH,
-                       guides + (size_t)un.cell * (kGuide + 1), tid, 64 * kHeavyWaves);
+                       guides + (size_t)un.cell * (kGuide + 1), c, tid, 64 * kHeavyWaves);
       loaded = un.cell;
       __syncthreads();
     }
@@ -1557,7 +1625,7 @@ __global__ __launch_bounds__(64 * kHeavyWaves, 2) void k_heavy(
     const DevCell c = cells[cell];
     if (cell != loaded) {
       load_cell_tables(L.T, L.guide, tables + (size_t)cell * kH,
-                       guides + (size_t)cell * (kGuide + 1), tid, 64 * kHeavyWaves);
+                       guides + (size_t)cell * (kGuide + 1), c, tid, 64 * kHeavyWaves);
       loaded = cell;
       __syncthreads();
     }
@@ -2307,9 +2375,9 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
                                               uint32_t* __restrict__ flags) {
   __shared__ uint64_t T[kH];
   __shared__ uint32_t guide[kGuide];
-  load_cell_tables(T, guide, tables, guides, (int)threadIdx.x, 256);
-  __syncthreads();
   const DevCell c = cells[0];
+  load_cell_tables(T, guide, tables, guides, c, (int)threadIdx.x, 256);
+  __syncthreads();
   const int64_t total = count * c.n;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -2320,8 +2388,8 @@ __global__ __launch_bounds__(256) void k_draws(const DevCell* __restrict__ cells
     const uint64_t m = (i & 1u) ? m53(w.w2, w.w3) : m53(w.w0, w.w1);
     const uint64_t timax = table_int(c.tmax);
     uint32_t fl = 0;
-    int64_t v = fast_draw(m, timax, T, guide, (int)c.gsh);
-    if (v != 0)
+    int64_t v = fast_draw(m, T, guide, (int)c.gsh);
+    if (v < kDeferred)
       v += c.xmin - 1;
     else
       v = resolve_entry_cut(defer_entry(m, timax, i, 0), rep, c, T, guide, fl);

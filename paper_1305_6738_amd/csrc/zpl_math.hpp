@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "zpl_exp2_table.hpp"
 #include "zpl_kernels.hpp"
 
 #define ZPL_HD __host__ __device__ __forceinline__
@@ -793,6 +794,13 @@ ZPL_HD DD dd_add(DD a, DD b) {
   s.lo += t.lo;
   return quick_two_sum(s.hi, s.lo);
 }
+// a + b when they do not cancel (|a + b| not far below max(|a|, |b|)):
+// absolute error about 2^-105 max(|a|, |b|).
+ZPL_HD DD dd_add_nc(DD a, DD b) {
+  DD s = two_sum(a.hi, b.hi);
+  s.lo += a.lo + b.lo;
+  return quick_two_sum(s.hi, s.lo);
+}
 ZPL_HD DD dd_mul(DD a, DD b) {
   DD p = two_prod(a.hi, b.hi);
   p.lo = fma(a.hi, b.lo, p.lo);
@@ -814,32 +822,49 @@ ZPL_HD DD dd_div_d(DD a, double b) {
   return dd_add(q, DD{q3, 0.0});
 }
 
-// exp of a double-double: a = k ln2 + r, r scaled by 2^-10, Taylor series to
-// the 11th power, then ten squarings of (1 + x) kept as x -> 2x + x^2.
+// exp of a double-double (|a| < 900): a = (64 q + j) ln2/64 + r with
+// 0 <= j < 64 and |r| <= ln2/128 (ln2/64 in three parts, the first short
+// enough for k ln2/64 to be exact), exp(a) = 2^q 2^(j/64) exp(r) with
+// 2^(j/64) from a double-double table.  exp(r) - 1 by Horner: the terms from
+// r^6/6! on (below 2^-54 of the sum) in FP64, the rest in double-double.
+// Every addition is between terms that do not cancel (the reduction's
+// correction k L2 is below 2^-28 and far from the result unless r itself is
+// that small, where only its absolute error counts).  Relative error about
+// 2^-104.
 ZPL_HD DD dd_exp(DD a) {
-  const DD ln2 = {0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56};
-  const double k = rint(a.hi / ln2.hi);
-  DD r = dd_add(a, dd_mul_d(ln2, -k));
-  r.hi *= 0x1p-10;
-  r.lo *= 0x1p-10;
-  // x = r + r^2/2! + ... + r^11/11!  (|r| < 3.4e-4)
-  DD term = r, x = r;
-  for (int j = 2; j <= 11; ++j) {
-    term = dd_div_d(dd_mul(term, r), (double)j);
-    x = dd_add(x, term);
-  }
-  for (int j = 0; j < 10; ++j) x = dd_add(dd_mul_d(x, 2.0), dd_mul(x, x));
-  DD e = dd_add(DD{1.0, 0.0}, x);
-  return DD{ldexp(e.hi, (int)k), ldexp(e.lo, (int)k)};
+  const double k = rint(a.hi * kInvLn2by64);
+  // a.hi - k L1 is exact: k L1 has at most 53 bits and lies within |r| of a.hi
+  DD r = two_sum(fma(-k, kLn2by64[0], a.hi), a.lo);
+  r = dd_add_nc(r, two_prod(-k, kLn2by64[1]));
+  r = quick_two_sum(r.hi, r.lo - k * kLn2by64[2]);
+  const double x = r.hi;
+  const double u =
+      1.0 / 720.0 +
+      x * (1.0 / 5040.0 +
+           x * (1.0 / 40320.0 + x * (1.0 / 362880.0 + x * (1.0 / 3628800.0 + x / 39916800.0))));
+  DD p = dd_add_nc(DD{kInvFact5Hi, kInvFact5Lo}, dd_mul_d(r, u));
+  p = dd_add_nc(DD{kInvFact4Hi, kInvFact4Lo}, dd_mul(r, p));
+  p = dd_add_nc(DD{kInvFact3Hi, kInvFact3Lo}, dd_mul(r, p));
+  p = dd_add_nc(DD{0.5, 0.0}, dd_mul(r, p));
+  const DD em1 = dd_add_nc(r, dd_mul(dd_mul(r, r), p));  // exp(r) - 1
+  const int ki = (int)k;
+  const int j = ki & 63;
+  const int q = (ki - j) / 64;
+  const DD t = {kExp2Hi[j], kExp2Lo[j]};
+  const DD e = dd_add_nc(t, dd_mul(t, em1));
+  return DD{ldexp(e.hi, q), ldexp(e.lo, q)};
 }
 
-// ln of a positive double as a double-double: one Newton step on exp.
+// ln of a positive double as a double-double: one Newton step on exp from
+// y = log(v), ln v = y + ln(1 + t) with t = v exp(-y) - 1 (|t| about the
+// error of y, so t - t^2/2 suffices; the square matters when |y| is large).
+// v exp(-y) is within 2^-40 of 1, so subtracting 1 from its high part is
+// exact.
 ZPL_HD DD dd_log(double v) {
   const double y = log(v);
-  // y1 = y + v exp(-y) - 1
-  const DD e = dd_exp(DD{-y, 0.0});
-  const DD t = dd_add(dd_mul_d(e, v), DD{-1.0, 0.0});
-  return dd_add(DD{y, 0.0}, t);
+  const DD p = dd_mul_d(dd_exp(DD{-y, 0.0}), v);
+  const DD t = two_sum(p.hi - 1.0, p.lo);
+  return dd_add_nc(DD{y, 0.0}, quick_two_sum(t.hi, t.lo - 0.5 * t.hi * t.hi));
 }
 
 // ---------------------------------------------------------------------------
@@ -927,6 +952,23 @@ ZPL_HD uint64_t guide_bin_min(int b, int sh) {
   const int k = o + nb - 51;
   const uint64_t emax = k >= 0 ? ((N - 1ull) >> k) : ((N << (-k)) - 1ull);
   return (1ull << 53) - emax;
+}
+
+// Packed guide entry of bin b for the simulation's fast path, from the guide
+// g[0..kGuide] (brackets [g[b], g[b + 1]]): the bracket low lo in bits 0..15;
+// bits 16..31 hold the bracket high hi when the bracket is exactly two wide
+// and the bin holds no tail uniform, else kDeferred | hi.  Bin b holds the m
+// in [guide_bin_min(b), guide_bin_min(b + 1)) (the last bin: up to 2^53), so
+// it may hold a tail uniform (m > timax) when that range reaches above timax.
+constexpr int kDeferred = 0x8000;
+static_assert(kH + 1 < kDeferred, "bracket bounds fit below the deferral mark");
+
+ZPL_HD uint32_t guide_pack(const uint16_t* g, int b, int sh, uint64_t timax) {
+  const uint32_t lo = g[b], hi = g[b + 1];
+  const uint64_t mend = b + 1 < kGuide ? guide_bin_min(b + 1, sh) : (1ull << 53);
+  const bool tail = mend - 1 > timax;
+  const uint32_t hw = (hi == lo + 1 && !tail) ? hi : ((uint32_t)kDeferred | hi);
+  return lo | (hw << 16);
 }
 
 // ---------------------------------------------------------------------------

@@ -94,6 +94,9 @@ void hm_moments012(double z, double* out) {
 }
 int hm_guide_index(uint64_t m, int sh) { return guide_index(m, sh); }
 int hm_guide_refinement(uint64_t timax) { return guide_refinement(timax); }
+void hm_guide_pack_all(const uint16_t* g, int sh, uint64_t timax, uint32_t* out) {
+  for (int b = 0; b < kGuide; ++b) out[b] = guide_pack(g, b, sh, timax);
+}
 void hm_guide_index_many(const uint64_t* m, int64_t n, int sh, int32_t* out) {
   for (int64_t i = 0; i < n; ++i) out[i] = guide_index(m[i], sh);
 }
@@ -126,5 +129,9 @@ void hm_dd_exp_log(double v, double* out) {
   DD l = dd_log(v);
   DD e = dd_exp(DD{v, 0.0});
   out[0] = l.hi; out[1] = l.lo; out[2] = e.hi; out[3] = e.lo;
+}
+void hm_dd_exp(double hi, double lo, double* out) {
+  DD e = dd_exp(DD{hi, lo});
+  out[0] = e.hi; out[1] = e.lo;
 }
 }

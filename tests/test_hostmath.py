@@ -40,6 +40,8 @@ def hm(tmp_path_factory):
     L.hm_S.argtypes = [P(C.c_int64), C.c_int64]
     L.hm_S.restype = C.c_double
     L.hm_dd_exp_log.argtypes = [C.c_double, P(C.c_double)]
+    L.hm_dd_exp.argtypes = [C.c_double, C.c_double, P(C.c_double)]
+    L.hm_guide_pack_all.argtypes = [P(C.c_uint16), C.c_int, C.c_uint64, P(C.c_uint32)]
     L.hm_hurwitz3.argtypes = [C.c_double, C.c_int64, P(C.c_double)]
     L.hm_mle_hz.argtypes = [C.c_double, C.c_int64, P(C.c_uint32)]
     L.hm_mle_hz.restype = C.c_double
@@ -115,6 +117,43 @@ def test_dd_exp_log_precision(hm):
                 E = mp.exp(mp.mpf(v))
                 got = mp.mpf(out[2]) + mp.mpf(out[3])
                 assert abs(got - E) <= E * mp.mpf(2) ** -100
+
+
+def test_dd_exp_every_table_entry(hm):
+    """dd_exp at double-double arguments (64 q + j) ln2/64 + r for every
+    table entry j, exponents q across the tail sampler's range and both
+    signs, and |r| up to the reduction bound ln2/128: relative error within
+    2^-102 of the 60-digit value."""
+    rng = np.random.default_rng(7)
+    out = np.zeros(2)
+    with mp.workdps(60):
+        c = mp.log(2) / 64
+        for j in range(64):
+            for q in (-1, 0, 1, -11, 9, 50, -57):
+                r = (rng.random() - 0.5) * float(c)
+                a = (64 * q + j) * c + mp.mpf(r)
+                hi = float(a)
+                lo = float(a - mp.mpf(hi))
+                hm.hm_dd_exp(hi, lo, _p(out, C.c_double))
+                E = mp.exp(mp.mpf(hi) + mp.mpf(lo))
+                got = mp.mpf(out[0]) + mp.mpf(out[1])
+                assert abs(got - E) <= E * mp.mpf(2) ** -102, (j, q, r)
+
+
+def test_dd_log_over_the_tail_uniforms(hm):
+    """dd_log at random odd multiples of 2^-53 (the sampler's V), including
+    the smallest: absolute error within 2^-100 |ln V| + 2^-104."""
+    rng = np.random.default_rng(11)
+    out = np.zeros(4)
+    ms = [1, 3, (1 << 53) - 1] + [int(x) | 1 for x in rng.integers(1, 1 << 53, 300)]
+    ms += [int(x) | 1 for x in rng.integers(1, 1 << 20, 100)]
+    for m in ms:
+        v = m * 2.0 ** -53
+        hm.hm_dd_exp_log(v, _p(out, C.c_double))
+        with mp.workdps(60):
+            L = mp.log(mp.mpf(v))
+            got = mp.mpf(out[0]) + mp.mpf(out[1])
+            assert abs(got - L) <= abs(L) * mp.mpf(2) ** -100 + mp.mpf(2) ** -104, m
 
 
 @pytest.mark.parametrize("alpha,ulps", [(1.05, 12), (1.2, 4), (1.5, 2), (2.5, 2), (3.5, 1),
@@ -558,6 +597,54 @@ def test_guide_bounds_and_brackets(hm, orc):
             assert idx[body].max() < KGUIDE - 1, label
         if sh == 8:  # the uniform layout uses bins 0..2047
             assert idx.max() < 2048, label
+
+
+def test_packed_guide_fast_path(hm, orc):
+    """The simulation's one-probe fast path on the packed guide (guide_pack,
+    the library's code compiled for the host): x = lo when TI[lo] >= m, else
+    the entry's high half, deferred when that is >= kDeferred.  For every
+    uniform of the bracket test's sets the result is the drawn value
+    min{k : TI[k] >= m} or deferred, and tail uniforms (m > TI[kH]) are always
+    deferred; and body uniforms with a bracket one or two values wide are
+    deferred only in the bin that straddles TI[kH]."""
+    rng = np.random.default_rng(21)
+    kdef = 0x8000
+    for label, T in _guide_tables(hm, orc):
+        T = np.ascontiguousarray(T, np.float64)
+        g = np.zeros(KGUIDE + 1, np.uint16)
+        sh = hm.hm_guide_build(T.ctypes.data_as(C.POINTER(C.c_double)),
+                               g.ctypes.data_as(C.POINTER(C.c_uint16)))
+        TI = (T * 2.0**53).astype(np.uint64)
+        TI[T >= 1.0] = np.uint64(1 << 53)
+        timax = int(TI[-1])
+        pk = np.zeros(KGUIDE, np.uint32)
+        hm.hm_guide_pack_all(g.ctypes.data_as(C.POINTER(C.c_uint16)), sh, timax,
+                             pk.ctypes.data_as(C.POINTER(C.c_uint32)))
+        ms = [rng.integers(1, 1 << 53, 100000, dtype=np.int64).astype(np.uint64) | np.uint64(1)]
+        near = TI[TI < (1 << 53)].astype(np.int64)
+        ms.append((np.concatenate([near - 1, near + 1, near + 3]).clip(1, (1 << 53) - 1)
+                   .astype(np.uint64) | np.uint64(1)))
+        ms.append(((1 << 53) - rng.integers(1, 1 << 40, 20000, dtype=np.int64))
+                  .astype(np.uint64) | np.uint64(1))
+        m = np.concatenate(ms)
+        idx = np.zeros(m.size, np.int32)
+        hm.hm_guide_index_many(m.ctypes.data_as(C.POINTER(C.c_uint64)), m.size, sh,
+                               idx.ctypes.data_as(C.POINTER(C.c_int32)))
+        e = pk[idx].astype(np.int64)
+        lo = e & 0xFFFF
+        hiw = e >> 16
+        x = np.where(TI[lo - 1] >= m, lo, hiw)
+        tail = m > np.uint64(timax)
+        assert np.all(x[tail] >= kdef), label
+        body = ~tail
+        want = np.searchsorted(TI, m[body], side="left") + 1
+        xb = x[body]
+        ok = xb < kdef
+        assert np.array_equal(xb[ok], want[ok]), label
+        # narrow brackets defer only in a bin that also holds tail uniforms
+        # (the one straddling TI[kH]): a small share of the body
+        width = g.astype(np.int64)[idx[body] + 1] - g.astype(np.int64)[idx[body]]
+        assert np.mean((width <= 1) & ~ok) < 1e-3, label
 
 
 def test_guide_refinement_narrows_heavy_tails(hm):
