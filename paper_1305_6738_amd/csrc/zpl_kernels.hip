@@ -859,8 +859,11 @@ __device__ __forceinline__ void ring_append(uint64_t* ring, uint32_t qh, uint32_
 // LDS of the simulation kernel: the cell's CDF table and packed guide, and one
 // region per wave (lane form or wave form).
 // ---------------------------------------------------------------------------
+static_assert(kHLB % 2 == 0, "two 16-bit counters per dword; value kHLB + 1 maps to the pad row");
 struct alignas(16) LaneRegion {
-  uint32_t hist[kHLB / 2 * 64];  // dword b of lane l at hist[b * 64 + l]
+  // dword b of lane l at hist[b * 64 + l]; row kHLB / 2 is a pad that takes
+  // the draw loop's no-op counts (never read)
+  uint32_t hist[(kHLB / 2 + 1) * 64];
   int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
   uint64_t ring[kRing];          // deferred draws
   uint32_t ovc[64];  // overflow count per lane (may exceed kCL)
@@ -868,7 +871,7 @@ struct alignas(16) LaneRegion {
 };
 
 struct alignas(16) WaveRegion {
-  uint32_t hist[kHW + 64];  // values 1..kHW; then one zero-increment slot per lane
+  uint32_t hist[kHW + 64];  // values 1..kHW; then one no-op pad slot per lane (never read)
   int64_t ov[kCW];
   uint64_t ring[kRing];     // deferred draws
   uint32_t ovc;
@@ -1014,10 +1017,10 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       x[d] = valid && drawn ? xd : -1;
       def[d] = valid && !drawn;
       big = big || x[d] > kHLB;
-      // own column, no branch: values outside 1..kHLB add zero to dword 0
-      const bool col = x[d] >= 1 && x[d] <= kHLB;
-      const int v = col ? x[d] - 1 : 0;
-      atomicAdd(&L->hist[(v >> 1) * 64 + lane], col ? 1u << ((v & 1) * 16) : 0u);
+      // own column, no branch: values outside 1..kHLB count into the pad row
+      const uint32_t xm1 = (uint32_t)(x[d] - 1);
+      const uint32_t v = xm1 < (uint32_t)kHLB ? xm1 : (uint32_t)kHLB;
+      atomicAdd(&L->hist[(v >> 1) * 64 + lane], 1u << ((v & 1u) * 16u));
     }
     if (__ballot(big) != 0ull) {  // values above the column (rare)
 #pragma unroll
@@ -1156,7 +1159,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       for (int k = lane; k < hi; k += 64) L->hist[k] = 0u;
       if (lane == 0) L->ovc = 0u;
       wave_sync();
-      int xm = 0;  // the lane's largest value counted in the histogram
+      int xm = 0;  // the lane's largest table value (clamped to kHW after the loop)
       // values 1..3 take most draws: counted per wave from ballots in
       // wave-uniform control flow (scalar counts, no LDS atomics and no
       // per-lane registers to sum across lanes afterwards)
@@ -1213,17 +1216,17 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           def[d] = valid && !drawn;
           big = big || x[d] > kHW;
           // values 1..3 are counted from ballots (the loop is wave-uniform);
-          // the others add 1 to their bin, and lanes with nothing to add put
-          // a zero into their own pad slot (no divergent branch)
+          // 4..kHW add 1 to their bin, and every other lane adds 1 to its own
+          // pad slot (no divergent branch; the pads are never read)
           c1 += (uint32_t)__popcll(__ballot(x[d] == 1));
           c2 += (uint32_t)__popcll(__ballot(x[d] == 2));
           c3 += (uint32_t)__popcll(__ballot(x[d] == 3));
           // counted here: the twelve ballot masks of an iteration are not
           // all kept live in scalar registers (they would be spilled)
           asm volatile("" : "+s"(c1), "+s"(c2), "+s"(c3));
-          const bool hb = x[d] > 3 && x[d] <= kHW;
-          atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], hb ? 1u : 0u);
-          xm = max(xm, x[d] <= kHW ? x[d] : 0);
+          const bool hb = (uint32_t)(x[d] - 4) < (uint32_t)(kHW - 3);
+          atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], 1u);
+          xm = max(xm, x[d]);  // values above kHW are clamped once, below
         }
         if (__ballot(big) != 0ull) {  // values above the histogram
 #pragma unroll
@@ -1247,7 +1250,7 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       fl = wave_or_u32(fl);
       // bins the list build reads: whole 256-bin blocks up to the largest
       // histogram value (every lane's xm is defined: set in converged code)
-      hi = ((int)wave_max_i64((int64_t)xm) + 255) & ~255;
+      hi = ((int)min(wave_max_i64((int64_t)xm), (int64_t)kHW) + 255) & ~255;
       hi = hi < 256 ? 256 : hi;
       wave_sync();
       if (lane == 0) {
@@ -1375,7 +1378,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_simulate(
 // replicate that overflowed the lane or wave form.
 // ---------------------------------------------------------------------------
 struct alignas(16) HeavyWave {
-  uint32_t hist[kHeavyHist + 64];  // values 1..kHeavyHist; then one zero-add pad slot per lane
+  uint32_t hist[kHeavyHist + 64];  // values 1..kHeavyHist; then one no-op pad slot per lane
   uint64_t ring[kRing];            // deferred draws (simulated replicates)
   uint32_t ones[64];  // per-lane count of values equal to 1 (the most frequent value)
   uint32_t ovc;
@@ -1462,7 +1465,7 @@ __device__ __forceinline__ void heavy_put(HeavyWave* W, int64_t* gov, int64_t v,
                                           uint64_t below) {
   ones += (uint32_t)__popcll(__ballot(valid && v == 1));
   const bool hb = valid && v >= 2 && v <= kHeavyHist;
-  atomicAdd(&W->hist[hb ? (int)v - 1 : kHeavyHist + lane], hb ? 1u : 0u);
+  atomicAdd(&W->hist[hb ? (int)v - 1 : kHeavyHist + lane], 1u);  // pads are never read
   const bool big = valid && v > kHeavyHist;
   const uint64_t mb = __ballot(big);
   if (mb != 0ull) {

@@ -886,7 +886,8 @@ ZPL_HD int guide_index(uint64_t m, int sh) {
   const uint32_t mh = (uint32_t)(m >> 32);
   const int ia = (int)(mh >> (uni ? 10 : 12));
   const uint32_t lim = uni ? (1u << 21) : (1u << 20);
-  const double e = (double)((1ull << 53) - m);
+  // e = 2^53 - m as a double, exactly: (2^53 - low word) - high word 2^32
+  const double e = fma(-(double)mh, 0x1p32, 0x1p53 - (double)(uint32_t)m);
   const int nb = kGBits + (uni ? 0 : sh);
   const int q = (int)((uint32_t)(__builtin_bit_cast(uint64_t, e) >> 32) >> (20 - nb));
   // bin = kGA + ((1021 - E) << nb) + (2^nb - 1 - s) for e = 2^(E-1023)(1.s...),
