@@ -142,11 +142,6 @@ __device__ __forceinline__ uint64_t defer_entry(uint64_t m, uint64_t timax, uint
   return m > timax ? ((1ull << 63) | o | i) : (o | m);
 }
 
-__device__ __noinline__ int64_t tail_draw_dev(double beta, double gm, uint32_t k0,
-                                              uint32_t k1, uint32_t i, uint32_t rep,
-                                              uint32_t stream, uint32_t* flags) {
-  return tail_draw(beta, gm, k0, k1, i, rep, stream, flags);
-}
 
 
 // ---------------------------------------------------------------------------
@@ -180,17 +175,36 @@ __device__ __forceinline__ double ks_distance(Src& src, const EmCoef& E,
   }
   double zprev = suf[16];
   int64_t vprev = 16;
-  int64_t v;
-  uint32_t c;
-  while (src.next_large(v, c)) {
-    const double zv = survival_next(E, v, ln);
-    const double zv1 = (v - 1 == vprev) ? zprev : zv + pow_neg(E.s, ln_value(v, ln));
+  // The table logarithms ln v and ln(v + 1) of each entry are read one entry
+  // ahead (at indexes clamped into the table; values past it take log), so
+  // their latency overlaps the previous entry's arithmetic.
+  constexpr int64_t kLnTop = (int64_t)kH + 1;
+  int64_t v = 0;
+  uint32_t c = 0;
+  bool have = src.next_large(v, c);
+  double lv = ln[v < kLnTop ? v : kLnTop], lv1 = ln[v < kLnTop ? v + 1 : kLnTop];
+  while (have) {
+    int64_t vn = 0;
+    uint32_t cn = 0;
+    const bool haven = src.next_large(vn, cn);
+    const double lvn = ln[vn < kLnTop ? vn : kLnTop];
+    const double lvn1 = ln[vn < kLnTop ? vn + 1 : kLnTop];
+    // survival_next and ln_value with the logarithms read ahead
+    const double q = (double)v + 1.0;
+    const double zv = hurwitz_tail(E, q, v < kLnTop ? lv1 : log(q));
+    const double zv1 =
+        (v - 1 == vprev) ? zprev : zv + pow_neg(E.s, v <= kLnTop ? lv : log((double)v));
     const double t2 = fabs(fma(zv1, iz, -(double)(n - C) * idn));
     C += c;
     const double t1 = fabs(fma(zv, iz, -(double)(n - C) * idn));
     D = fmax(D, fmax(t1, t2));
     zprev = zv;
     vprev = v;
+    v = vn;
+    c = cn;
+    lv = lvn;
+    lv1 = lvn1;
+    have = haven;
   }
   return D;
 }
@@ -821,7 +835,7 @@ __device__ __forceinline__ int64_t resolve_entry(uint64_t e, uint32_t rep, const
                                                  const uint32_t* __restrict__ guide,
                                                  uint32_t& fl) {
   if (e >> 63)
-    return tail_draw_dev(c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep, c.stream, &fl);
+    return tail_draw(c.beta, c.gm, c.k0, c.k1, (uint32_t)e, rep, c.stream, &fl);  // inline: no call in the draw loop
   return (int64_t)slow_search(e & ((1ull << 53) - 1), T, guide, (int)c.gsh);
 }
 
