@@ -884,8 +884,14 @@ struct alignas(16) LaneRegion {
   uint32_t fl[64];   // flags per lane
 };
 
+// Wave-form histogram layout: bins of values 1..kHW, one pad slot per lane
+// (the draw loop's no-op counts, never read), then three rows of per-lane
+// counts of the values 1, 2 and 3 (most draws: a lane counting into its own
+// slot never conflicts with another lane).
+constexpr int kWavePad = kHW;
+constexpr int kWaveOwn = kHW + 64;
 struct alignas(16) WaveRegion {
-  uint32_t hist[kHW + 64];  // values 1..kHW; then one no-op pad slot per lane (never read)
+  uint32_t hist[kHW + 64 + 3 * 64];
   int64_t ov[kCW];
   uint64_t ring[kRing];     // deferred draws
   uint32_t ovc;
@@ -1171,13 +1177,12 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
     while (done + q < nrep && q < 64 && used + (uint32_t)(kHW + kCW) <= (uint32_t)kListCap) {
       const uint32_t r = (uint32_t)(r0 + done + q);
       for (int k = lane; k < hi; k += 64) L->hist[k] = 0u;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) L->hist[kWaveOwn + k * 64 + lane] = 0u;
       if (lane == 0) L->ovc = 0u;
       wave_sync();
       int xm = 0;  // the lane's largest table value (clamped to kHW after the loop)
-      // values 1..3 take most draws: counted per wave from ballots in
-      // wave-uniform control flow (scalar counts, no LDS atomics and no
-      // per-lane registers to sum across lanes afterwards)
-      uint32_t c1 = 0, c2 = 0, c3 = 0, fl = 0;
+      uint32_t fl = 0;
       uint32_t qh = 0, qn = 0;  // deferred-draw ring, wave-uniform
       const uint64_t timax = table_int(c.tmax);
       const int sh = (int)c.gsh;
@@ -1229,17 +1234,12 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
           x[d] = valid && drawn ? xd : -1;
           def[d] = valid && !drawn;
           big = big || x[d] > kHW;
-          // values 1..3 are counted from ballots (the loop is wave-uniform);
-          // 4..kHW add 1 to their bin, and every other lane adds 1 to its own
-          // pad slot (no divergent branch; the pads are never read)
-          c1 += (uint32_t)__popcll(__ballot(x[d] == 1));
-          c2 += (uint32_t)__popcll(__ballot(x[d] == 2));
-          c3 += (uint32_t)__popcll(__ballot(x[d] == 3));
-          // counted here: the twelve ballot masks of an iteration are not
-          // all kept live in scalar registers (they would be spilled)
-          asm volatile("" : "+s"(c1), "+s"(c2), "+s"(c3));
-          const bool hb = (uint32_t)(x[d] - 4) < (uint32_t)(kHW - 3);
-          atomicAdd(&L->hist[hb ? x[d] - 1 : kHW + lane], 1u);
+          // 1..3 count into the lane's own row, 4..kHW into their bin, and
+          // every other lane adds 1 to its pad slot (no divergent branch)
+          const uint32_t xm1 = (uint32_t)(x[d] - 1);
+          const int slot = xm1 < 3u ? kWaveOwn + (int)xm1 * 64 + lane
+                                    : (xm1 < (uint32_t)kHW ? (int)xm1 : kWavePad + lane);
+          atomicAdd(&L->hist[slot], 1u);
           xm = max(xm, x[d]);  // values above kHW are clamped once, below
         }
         if (__ballot(big) != 0ull) {  // values above the histogram
@@ -1267,8 +1267,12 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
       hi = ((int)min(wave_max_i64((int64_t)xm), (int64_t)kHW) + 255) & ~255;
       hi = hi < 256 ? 256 : hi;
       wave_sync();
+      // the own rows' totals, read and summed in converged code
+      const uint32_t c1 = wave_sum_u32(L->hist[kWaveOwn + lane]);
+      const uint32_t c2 = wave_sum_u32(L->hist[kWaveOwn + 64 + lane]);
+      const uint32_t c3 = wave_sum_u32(L->hist[kWaveOwn + 128 + lane]);
       if (lane == 0) {
-        L->hist[0] += c1;
+        L->hist[0] += c1;  // drains count 1..3 into the bins themselves
         L->hist[1] += c2;
         L->hist[2] += c3;
       }
