@@ -2227,15 +2227,19 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
 
 // Slice `slice` of cell `cell` (blocks laid out cell-major, `slices` per
 // cell): values below each bracket are counted, values inside are appended
-// to the quantile's gather area at slots from its global counter.
+// to the quantile's gather area.  Per step of 256 x kSelUnroll values the
+// workgroup takes its slots with one atomic per quantile (a wave scan of the
+// threads' counts, then the four waves' totals), not one per wave and value.
 __global__ __launch_bounds__(256) void k_sel_gather(const double* __restrict__ D,
                                                    const DevCell* __restrict__ cells, int nq,
                                                    int slices, int64_t chunk,
                                                    SelMeta* __restrict__ meta,
                                                    uint64_t* __restrict__ gather, int64_t gcap) {
+  __shared__ uint32_t wtot[4][kSelQ];   // per wave, in-bracket values of the step
+  __shared__ uint32_t wbase[4][kSelQ];  // first slot of each wave's values
   const int cell = (int)(blockIdx.x / (unsigned)slices);
   const int slice = (int)(blockIdx.x % (unsigned)slices);
-  const int tid = (int)threadIdx.x, lane = tid & 63;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevCell c = cells[cell];
   const int64_t R = c.R;
   const int64_t ib = (int64_t)slice * chunk;
@@ -2259,29 +2263,51 @@ __global__ __launch_bounds__(256) void k_sel_gather(const double* __restrict__ D
       const int64_t i = i0 + u * 256 + tid;
       bv[u] = i < ie ? bits[i] : 0ull;
     }
+    uint32_t inm[kSelQ], incl[kSelQ], cnt[kSelQ];
 #pragma unroll
-    for (int u = 0; u < kSelUnroll; ++u) {
-      const bool valid = i0 + u * 256 + tid < ie;
-      const uint64_t b = bv[u];
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      inm[qq] = 0u;
+      cnt[qq] = 0u;
 #pragma unroll
-      for (int qq = 0; qq < kSelQ; ++qq) {
-        if (qq < nq) {
-          const bool bl = valid && b < lo[qq];
-          const bool in = valid && !bl && b <= hi[qq];
-          below[qq] += bl ? 1u : 0u;
-          const uint64_t m = __ballot(in);
-          if (m) {
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&M[qq].nb, (uint32_t)__popcll(m));
-            base = (uint32_t)__shfl((int)base, 0, 64);
-            if (in) {
-              const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below(lane));
-              if ((int64_t)slot < gcap) G[qq * gcap + slot] = b;
-            }
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const bool valid = i0 + u * 256 + tid < ie;
+        const uint64_t b = bv[u];
+        const bool bl = qq < nq && valid && b < lo[qq];
+        const bool in = qq < nq && valid && !bl && b <= hi[qq];
+        below[qq] += bl ? 1u : 0u;
+        inm[qq] |= in ? (1u << u) : 0u;
+        cnt[qq] += in ? 1u : 0u;
+      }
+      incl[qq] = wave_incl_scan_u32(cnt[qq], lane);
+      if (lane == 63) wtot[wave][qq] = incl[qq];
+    }
+    __syncthreads();
+    if (tid < kSelQ) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        wbase[w][tid] = t;
+        t += wtot[w][tid];
+      }
+      const uint32_t b = (tid < nq && t) ? atomicAdd(&M[tid].nb, t) : 0u;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) wbase[w][tid] += b;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kSelQ; ++qq) {
+      if (inm[qq]) {
+        uint32_t slot = wbase[wave][qq] + incl[qq] - cnt[qq];
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          if (inm[qq] & (1u << u)) {
+            if ((int64_t)slot < gcap) G[qq * gcap + slot] = bv[u];
+            ++slot;
           }
         }
       }
     }
+    __syncthreads();  // wtot and wbase are reused by the next step
   }
 #pragma unroll
   for (int qq = 0; qq < kSelQ; ++qq) {
