@@ -874,6 +874,8 @@ __device__ __forceinline__ void ring_append(uint64_t* ring, uint32_t qh, uint32_
 // region per wave (lane form or wave form).
 // ---------------------------------------------------------------------------
 static_assert(kHLB % 2 == 0, "two 16-bit counters per dword; value kHLB + 1 maps to the pad row");
+static_assert(64 * (2 * kLaneSpill + kCL) <= kListCap,
+              "the lane form's spill and sorted lists fit the wave's list scratch");
 struct alignas(16) LaneRegion {
   // dword b of lane l at hist[b * 64 + l]; row kHLB / 2 is a pad that takes
   // the draw loop's no-op counts (never read)
@@ -933,21 +935,27 @@ __device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
 // lane's histogram column; deferred draws from all lanes are resolved 64 at a
 // time by whichever lane picks them up, into the owner's column.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lane_insert(LaneRegion* L, int owner, int64_t x) {
+// The lane's larger values: entry p < kCL at L->ov[p * 64 + lane], entry
+// p >= kCL at spill[(p - kCL) * 64 + lane] (the wave's global scratch).
+__device__ __forceinline__ void lane_insert(LaneRegion* L, int64_t* spill, int owner, int64_t x) {
   if (x <= kHLB) {
     const int v = (int)x - 1;
     atomicAdd(&L->hist[(v >> 1) * 64 + owner], 1u << ((v & 1) * 16));
   } else {
     const uint32_t p = atomicAdd(&L->ovc[owner], 1u);
-    if (p < (uint32_t)kCL) L->ov[p * 64 + owner] = x;
+    if (p < (uint32_t)kCL)
+      L->ov[p * 64 + owner] = x;
+    else if (p < (uint32_t)(kCL + kLaneSpill))
+      spill[(p - kCL) * 64 + owner] = x;
   }
 }
 
 // Resolves ring entries [qh, qh + m) (one per lane) into the owners'
 // columns.  The leading wave_sync makes entries written by other lanes
 // visible; every caller is in wave-uniform control flow.
-__device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qh, int64_t rep0,
-                                           const DevCell& c, const uint64_t* __restrict__ T,
+__device__ __forceinline__ void lane_drain(LaneRegion* L, int64_t* spill, int m, uint32_t qh,
+                                           int64_t rep0, const DevCell& c,
+                                           const uint64_t* __restrict__ T,
                                            const uint32_t* __restrict__ guide, int lane) {
   wave_sync();
   if (lane < m) {
@@ -958,7 +966,7 @@ __device__ __forceinline__ void lane_drain(LaneRegion* L, int m, uint32_t qh, in
     uint32_t fl = 0;
     const int64_t x = resolve_entry(e, (uint32_t)(rep0 + owner), c, T, guide, fl);
     if (fl) atomicOr(&L->fl[owner], fl);
-    lane_insert(L, owner, x);
+    lane_insert(L, spill, owner, x);
   }
 }
 
@@ -972,7 +980,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
                                           const uint32_t* __restrict__ guide,
                                           const double* __restrict__ ln, const Outputs& out,
                                           uint64_t* esc_list, uint32_t* esc_count,
-                                          uint32_t esc_cap, uint32_t* err) {
+                                          uint32_t esc_cap, uint32_t* err, int64_t* spill) {
   const bool active = lane < count;
 #pragma unroll
   for (int b = 0; b < kHLB / 2; ++b) L->hist[b * 64 + lane] = 0u;
@@ -1045,25 +1053,25 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
     if (__ballot(big) != 0ull) {  // values above the column (rare)
 #pragma unroll
       for (int d = 0; d < 2 * kLaneBlocks; ++d)
-        if (x[d] > kHLB) lane_insert(L, lane, x[d]);
+        if (x[d] > kHLB) lane_insert(L, spill, lane, x[d]);
     }
     ring_append(L->ring, qh, qn, def, [&](int d) {
       return defer_entry(U[d], timax, 2u * j + (uint32_t)d, lane);
     }, lane);
     while (qn >= 64u) {
-      lane_drain(L, 64, qh, rep0, c, T, guide, lane);
+      lane_drain(L, spill, 64, qh, rep0, c, T, guide, lane);
       qh = qh + 64u >= (uint32_t)kRing ? qh + 64u - (uint32_t)kRing : qh + 64u;
       qn -= 64u;
     }
 #pragma unroll
     for (int d = 0; d < 2 * kLaneBlocks; ++d) U[d] = Un[d];
   }
-  if (qn > 0u) lane_drain(L, (int)qn, qh, rep0, c, T, guide, lane);
-  wave_sync();
+  if (qn > 0u) lane_drain(L, spill, (int)qn, qh, rep0, c, T, guide, lane);
+  wave_sync_global();  // other lanes' drains wrote to this lane's spill entries
   if (!active) return;
   const int oc = (int)L->ovc[lane];
   const uint32_t fl = L->fl[lane];
-  if (oc > kCL) {
+  if (oc > kCL + kLaneSpill) {
     const uint32_t slot = atomicAdd(esc_count, 1u);
     if (slot < esc_cap)
       esc_list[slot] = ((uint64_t)(uint32_t)cell_id << 32) | r;
@@ -1072,20 +1080,28 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
     return;
   }
   uint32_t* h = L->hist + lane;
-  int64_t* o = L->ov + lane;
-  // insertion sort of the (at most kCL) overflow values
-  for (int p = 1; p < oc; ++p) {
-    const int64_t v = o[p * 64];
-    int q = p - 1;
-    while (q >= 0 && o[q * 64] > v) {
-      o[(q + 1) * 64] = o[q * 64];
-      --q;
-    }
-    o[(q + 1) * 64] = v;
-  }
   U128 S = {0, 0};
   uint64_t fp = 0;
   int64_t xmax = 0;
+  // The larger values sorted into the scratch after the spill area: each
+  // goes to its rank (values below it, plus equal ones stored before it; no
+  // data-dependent moves), and the order-free sums are taken on the way.
+  const int64_t* o = L->ov + lane;
+  const int64_t* g = spill + lane;
+  int64_t* srt = spill + 64 * kLaneSpill + lane;  // entry p at srt[p * 64]
+  auto ovv = [&](int p) -> int64_t { return p < kCL ? o[p * 64] : g[(p - kCL) * 64]; };
+  for (int i = 0; i < oc; ++i) {
+    const int64_t v = ovv(i);
+    int rank = 0;
+    for (int j = 0; j < oc; ++j) {
+      const int64_t w = ovv(j);
+      rank += (w < v || (w == v && j < i)) ? 1 : 0;
+    }
+    srt[rank * 64] = v;
+    u128_add(S, ln_fixed(v, ln), 0);
+    fp += mix64((uint64_t)v);
+    xmax = v > xmax ? v : xmax;
+  }
   for (int b = 0; b < kHLB / 2; ++b) {
     const uint32_t wv = h[b * 64];
 #pragma unroll
@@ -1095,17 +1111,13 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       if (k) {
         u128_add_mul(S, k, ln_fixed(v, ln));
         fp += (uint64_t)k * mix64((uint64_t)v);
-        xmax = v;
+        xmax = v > xmax ? v : xmax;
       }
     }
   }
-  for (int p = 0; p < oc; ++p) {
-    const int64_t v = o[p * 64];
-    u128_add(S, ln_fixed(v, ln), 0);
-    fp += mix64((uint64_t)v);
-    xmax = v;
-  }
-  LaneSrc src{h, o, oc, 17, 0};
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the sorted list is read back
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  LaneSrc src{h, srt, oc, 17, 0};
   double a, D;
   uint32_t flags;
   finish_replicate(src, S, n, fl, ln, c.K, a, D, flags);
@@ -1380,7 +1392,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_simulate(
       const int nrep = (un.count - first) < 64 ? (un.count - first) : 64;
       if (c.mode == kModeLane)
         lane_wave(c, un.cell, un.r0 + first, nrep, &L.w[wave].lane, lane, L.T, L.guide, ln, out,
-                  esc_list, esc_count, esc_cap, err);
+                  esc_list, esc_count, esc_cap, err, lv);
       else
         wave_batch(c, un.cell, un.r0 + first, nrep, &L.w[wave].wave, slots, lv, lc, lane, L.T,
                    L.guide, ln, out, esc_list, esc_count, esc_cap, err);

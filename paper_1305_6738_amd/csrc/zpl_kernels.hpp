@@ -31,10 +31,13 @@ constexpr int kGuide = kGA + (kOctaves << kGBits);
 constexpr int kWaves = 8;
 constexpr int kBlock = 64 * kWaves;
 // Lane form: one replicate per lane; per-lane histogram of values 1..kHLB
-// (16-bit counters packed two per dword) plus a per-lane list of up to kCL
-// larger values.  A replicate with more is redone by the heavy form.
+// (16-bit counters packed two per dword) plus a per-lane list of the larger
+// values: the first kCL in LDS ...
 constexpr int kHLB = 48;
 constexpr int kCL = 8;
+// ... and kLaneSpill more per lane in the wave's global scratch (a replicate
+// with more than kCL + kLaneSpill is redone by the heavy form).
+constexpr int kLaneSpill = 120;
 // Wave form: one replicate per wave at a time; histogram of values 1..kHW
 // plus up to kCW larger values in LDS; finishes run one replicate per lane.
 constexpr int kHW = 1024;
