@@ -1050,10 +1050,23 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       const uint32_t v = xm1 < (uint32_t)kHLB ? xm1 : (uint32_t)kHLB;
       atomicAdd(&L->hist[(v >> 1) * 64 + lane], 1u << ((v & 1u) * 16u));
     }
-    if (__ballot(big) != 0ull) {  // values above the column (rare)
+    if (__ballot(big) != 0ull) {  // values above the column: one slot claim per lane
+      uint32_t nb = 0;
 #pragma unroll
-      for (int d = 0; d < 2 * kLaneBlocks; ++d)
-        if (x[d] > kHLB) lane_insert(L, spill, lane, x[d]);
+      for (int d = 0; d < 2 * kLaneBlocks; ++d) nb += x[d] > kHLB ? 1u : 0u;
+      if (nb) {
+        uint32_t p = atomicAdd(&L->ovc[lane], nb);
+#pragma unroll
+        for (int d = 0; d < 2 * kLaneBlocks; ++d) {
+          if (x[d] > kHLB) {
+            if (p < (uint32_t)kCL)
+              L->ov[p * 64 + lane] = x[d];
+            else if (p < (uint32_t)(kCL + kLaneSpill))
+              spill[(p - kCL) * 64 + lane] = x[d];
+            ++p;
+          }
+        }
+      }
     }
     ring_append(L->ring, qh, qn, def, [&](int d) {
       return defer_entry(U[d], timax, 2u * j + (uint32_t)d, lane);
@@ -1085,22 +1098,34 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   int64_t xmax = 0;
   // The larger values sorted into the scratch after the spill area: each
   // goes to its rank (values below it, plus equal ones stored before it; no
-  // data-dependent moves), and the order-free sums are taken on the way.
+  // data-dependent moves), eight values at a time against one pass over all
+  // of them (independent reads), and the order-free sums are taken on the way.
   const int64_t* o = L->ov + lane;
   const int64_t* g = spill + lane;
   int64_t* srt = spill + 64 * kLaneSpill + lane;  // entry p at srt[p * 64]
   auto ovv = [&](int p) -> int64_t { return p < kCL ? o[p * 64] : g[(p - kCL) * 64]; };
-  for (int i = 0; i < oc; ++i) {
-    const int64_t v = ovv(i);
-    int rank = 0;
+  for (int i0 = 0; i0 < oc; i0 += 8) {
+    int64_t v[8];
+    int rank[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      v[t] = i0 + t < oc ? ovv(i0 + t) : INT64_MAX;
+      rank[t] = 0;
+    }
     for (int j = 0; j < oc; ++j) {
       const int64_t w = ovv(j);
-      rank += (w < v || (w == v && j < i)) ? 1 : 0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) rank[t] += (w < v[t] || (w == v[t] && j < i0 + t)) ? 1 : 0;
     }
-    srt[rank * 64] = v;
-    u128_add(S, ln_fixed(v, ln), 0);
-    fp += mix64((uint64_t)v);
-    xmax = v > xmax ? v : xmax;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (i0 + t < oc) {
+        srt[rank[t] * 64] = v[t];
+        u128_add(S, ln_fixed(v[t], ln), 0);
+        fp += mix64((uint64_t)v[t]);
+        xmax = v[t] > xmax ? v[t] : xmax;
+      }
+    }
   }
   for (int b = 0; b < kHLB / 2; ++b) {
     const uint32_t wv = h[b * 64];
