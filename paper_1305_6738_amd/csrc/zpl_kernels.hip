@@ -882,7 +882,7 @@ struct alignas(16) LaneRegion {
   uint32_t hist[(kHLB / 2 + 1) * 64];
   int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
   uint64_t ring[kRing];          // deferred draws
-  uint32_t ovc[64];  // overflow count per lane (may exceed kCL)
+  uint32_t ovc[64];  // values the drains added to a lane's list (may exceed its room)
   uint32_t fl[64];   // flags per lane
 };
 
@@ -935,18 +935,26 @@ __device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
 // lane's histogram column; deferred draws from all lanes are resolved 64 at a
 // time by whichever lane picks them up, into the owner's column.
 // ---------------------------------------------------------------------------
-// The lane's larger values: entry p < kCL at L->ov[p * 64 + lane], entry
-// p >= kCL at spill[(p - kCL) * 64 + lane] (the wave's global scratch).
+// The lane's larger values take kLaneCap slots: slot s < kCL at
+// L->ov[s * 64 + lane], slot s >= kCL at spill[(s - kCL) * 64 + lane] (the
+// wave's global scratch).  The lane's own draws fill slots 0, 1, ... (a
+// register count); the drains, which resolve any lane's draws, fill slots
+// kLaneCap - 1, kLaneCap - 2, ... (an LDS count per owner).
+constexpr int kLaneCap = kCL + kLaneSpill;
+__device__ __forceinline__ void lane_slot_store(LaneRegion* L, int64_t* spill, int owner, int s,
+                                                int64_t x) {
+  if (s < kCL)
+    L->ov[s * 64 + owner] = x;
+  else
+    spill[(s - kCL) * 64 + owner] = x;
+}
 __device__ __forceinline__ void lane_insert(LaneRegion* L, int64_t* spill, int owner, int64_t x) {
   if (x <= kHLB) {
     const int v = (int)x - 1;
     atomicAdd(&L->hist[(v >> 1) * 64 + owner], 1u << ((v & 1) * 16));
   } else {
     const uint32_t p = atomicAdd(&L->ovc[owner], 1u);
-    if (p < (uint32_t)kCL)
-      L->ov[p * 64 + owner] = x;
-    else if (p < (uint32_t)(kCL + kLaneSpill))
-      spill[(p - kCL) * 64 + owner] = x;
+    if (p < (uint32_t)kLaneCap) lane_slot_store(L, spill, owner, kLaneCap - 1 - (int)p, x);
   }
 }
 
@@ -992,6 +1000,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   const uint32_t nblk = (uint32_t)((n + 1) >> 1);
   // Deferred draws wait in a ring (head qh, qn entries, both wave-uniform).
   uint32_t qh = 0, qn = 0;
+  int myc = 0;  // the lane's own values above the column
   const uint64_t timax = table_int(c.tmax);
   const int sh = (int)c.gsh;
   const uint32_t n32 = (uint32_t)n;  // draw indexes are 32-bit
@@ -1050,21 +1059,12 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       const uint32_t v = xm1 < (uint32_t)kHLB ? xm1 : (uint32_t)kHLB;
       atomicAdd(&L->hist[(v >> 1) * 64 + lane], 1u << ((v & 1u) * 16u));
     }
-    if (__ballot(big) != 0ull) {  // values above the column: one slot claim per lane
-      uint32_t nb = 0;
+    if (__ballot(big) != 0ull) {  // values above the column, into the lane's own slots
 #pragma unroll
-      for (int d = 0; d < 2 * kLaneBlocks; ++d) nb += x[d] > kHLB ? 1u : 0u;
-      if (nb) {
-        uint32_t p = atomicAdd(&L->ovc[lane], nb);
-#pragma unroll
-        for (int d = 0; d < 2 * kLaneBlocks; ++d) {
-          if (x[d] > kHLB) {
-            if (p < (uint32_t)kCL)
-              L->ov[p * 64 + lane] = x[d];
-            else if (p < (uint32_t)(kCL + kLaneSpill))
-              spill[(p - kCL) * 64 + lane] = x[d];
-            ++p;
-          }
+      for (int d = 0; d < 2 * kLaneBlocks; ++d) {
+        if (x[d] > kHLB) {
+          if (myc < kLaneCap) lane_slot_store(L, spill, lane, myc, x[d]);
+          ++myc;
         }
       }
     }
@@ -1082,9 +1082,10 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   if (qn > 0u) lane_drain(L, spill, (int)qn, qh, rep0, c, T, guide, lane);
   wave_sync_global();  // other lanes' drains wrote to this lane's spill entries
   if (!active) return;
-  const int oc = (int)L->ovc[lane];
+  const int od = (int)L->ovc[lane];
+  const int oc = myc + od;
   const uint32_t fl = L->fl[lane];
-  if (oc > kCL + kLaneSpill) {
+  if (oc > kLaneCap) {
     const uint32_t slot = atomicAdd(esc_count, 1u);
     if (slot < esc_cap)
       esc_list[slot] = ((uint64_t)(uint32_t)cell_id << 32) | r;
@@ -1100,10 +1101,14 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   // goes to its rank (values below it, plus equal ones stored before it; no
   // data-dependent moves), eight values at a time against one pass over all
   // of them (independent reads), and the order-free sums are taken on the way.
+  // Value q of the lane: its own slots 0..myc-1, then the drains' slots.
   const int64_t* o = L->ov + lane;
   const int64_t* g = spill + lane;
   int64_t* srt = spill + 64 * kLaneSpill + lane;  // entry p at srt[p * 64]
-  auto ovv = [&](int p) -> int64_t { return p < kCL ? o[p * 64] : g[(p - kCL) * 64]; };
+  auto ovv = [&](int q) -> int64_t {
+    const int sl = q < myc ? q : kLaneCap - od + (q - myc);
+    return sl < kCL ? o[sl * 64] : g[(sl - kCL) * 64];
+  };
   for (int i0 = 0; i0 < oc; i0 += 8) {
     int64_t v[8];
     int rank[8];
@@ -1112,6 +1117,7 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
       v[t] = i0 + t < oc ? ovv(i0 + t) : INT64_MAX;
       rank[t] = 0;
     }
+#pragma unroll 4
     for (int j = 0; j < oc; ++j) {
       const int64_t w = ovv(j);
 #pragma unroll
