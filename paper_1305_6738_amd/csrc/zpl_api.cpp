@@ -313,10 +313,10 @@ struct Plan {
 // overflows its per-lane list, the wave form only where the LDS overflow
 // area almost surely holds a replicate's large values.
 bool form_eligible(uint32_t m, double alpha, int64_t n, uint32_t K = 0) {
-  if (m == kModeLane) {  // values above the column: kCL in LDS, kLaneSpill more in scratch
+  if (m == kModeLane) {  // values above the column: kLaneCap slots in scratch
     if (n > 65535) return false;
     const double mu = (double)n * tail_prob(alpha, kHLB, K);
-    return mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)(kCL + kLaneSpill);
+    return mu + 8.0 * std::sqrt(mu) + 8.0 <= (double)kLaneCap;
   }
   if (m == kModeWave) {
     const double mu = (double)n * tail_prob(alpha, kHW, K);

@@ -719,25 +719,37 @@ __device__ __forceinline__ void block_store(const int64_t (&v)[E], int64_t* a, i
   for (int t = 0; t < E; ++t) a[lane + 64 * t] = v[t];
 }
 
-// Ascending bitonic sort of a[0..P) (P a power of two, 128..512) by one wave,
-// entirely in registers (P / 64 values per lane); a is LDS or global memory,
-// read once and written once by the calling wave.
-__device__ __forceinline__ void wave_sort_small(int64_t* a, int P, int lane) {
+// Ascending bitonic sort of a[0..nv) padded to P (a power of two, 128..512)
+// by one wave, entirely in registers (P / 64 values per lane; positions from
+// nv on count as INT64_MAX and are neither read nor written); a is LDS or
+// global memory, read once and written once by the calling wave.
+template <int E>
+__device__ __forceinline__ void block_load_n(int64_t (&v)[E], const int64_t* a, int nv, int lane) {
+#pragma unroll
+  for (int t = 0; t < E; ++t) v[t] = lane + 64 * t < nv ? a[lane + 64 * t] : INT64_MAX;
+}
+template <int E>
+__device__ __forceinline__ void block_store_n(const int64_t (&v)[E], int64_t* a, int nv, int lane) {
+#pragma unroll
+  for (int t = 0; t < E; ++t)
+    if (lane + 64 * t < nv) a[lane + 64 * t] = v[t];
+}
+__device__ __forceinline__ void wave_sort_small(int64_t* a, int P, int nv, int lane) {
   if (P == 128) {
     int64_t v[2];
-    block_load<2>(v, a, lane);
+    block_load_n<2>(v, a, nv, lane);
     block_sort<2>(v, 0, lane);
-    block_store<2>(v, a, lane);
+    block_store_n<2>(v, a, nv, lane);
   } else if (P == 256) {
     int64_t v[4];
-    block_load<4>(v, a, lane);
+    block_load_n<4>(v, a, nv, lane);
     block_sort<4>(v, 0, lane);
-    block_store<4>(v, a, lane);
+    block_store_n<4>(v, a, nv, lane);
   } else {
     int64_t v[8];
-    block_load<8>(v, a, lane);
+    block_load_n<8>(v, a, nv, lane);
     block_sort<8>(v, 0, lane);
-    block_store<8>(v, a, lane);
+    block_store_n<8>(v, a, nv, lane);
   }
 }
 
@@ -788,7 +800,7 @@ __device__ __forceinline__ void mem_group(int64_t* g, int P, int k, int j1, int 
 // array takes 7 round trips through memory instead of 78 passes.
 __device__ void wave_sort_global(int64_t* g, int P, int lane) {
   if (P <= 512) {
-    wave_sort_small(g, P, lane);
+    wave_sort_small(g, P, P, lane);
     wave_sync_global();
     return;
   }
@@ -874,13 +886,12 @@ __device__ __forceinline__ void ring_append(uint64_t* ring, uint32_t qh, uint32_
 // region per wave (lane form or wave form).
 // ---------------------------------------------------------------------------
 static_assert(kHLB % 2 == 0, "two 16-bit counters per dword; value kHLB + 1 maps to the pad row");
-static_assert(64 * (2 * kLaneSpill + kCL) <= kListCap,
-              "the lane form's spill and sorted lists fit the wave's list scratch");
+static_assert(64 * 2 * kLaneCap <= kListCap,
+              "the lane form's value slots and sorted lists fit the wave's list scratch");
 struct alignas(16) LaneRegion {
   // dword b of lane l at hist[b * 64 + l]; row kHLB / 2 is a pad that takes
   // the draw loop's no-op counts (never read)
   uint32_t hist[(kHLB / 2 + 1) * 64];
-  int64_t ov[kCL * 64];          // overflow entry p of lane l at ov[p * 64 + l]
   uint64_t ring[kRing];          // deferred draws
   uint32_t ovc[64];  // values the drains added to a lane's list (may exceed its room)
   uint32_t fl[64];   // flags per lane
@@ -910,6 +921,7 @@ struct SimLds {
   WaveLds w[kWaves];
   int unit;
 };
+static_assert(sizeof(SimLds) <= 160 * 1024, "the simulation kernel's LDS fits one compute unit");
 
 // Out of line: inlined into the persistent kernels' cell switch it takes
 // registers from their hot loops.
@@ -935,18 +947,13 @@ __device__ __forceinline__ void load_cell_tables(uint64_t* T, uint32_t* guide,
 // lane's histogram column; deferred draws from all lanes are resolved 64 at a
 // time by whichever lane picks them up, into the owner's column.
 // ---------------------------------------------------------------------------
-// The lane's larger values take kLaneCap slots: slot s < kCL at
-// L->ov[s * 64 + lane], slot s >= kCL at spill[(s - kCL) * 64 + lane] (the
-// wave's global scratch).  The lane's own draws fill slots 0, 1, ... (a
-// register count); the drains, which resolve any lane's draws, fill slots
-// kLaneCap - 1, kLaneCap - 2, ... (an LDS count per owner).
-constexpr int kLaneCap = kCL + kLaneSpill;
+// The lane's larger values take kLaneCap slots of the wave's global scratch,
+// slot s of lane l at spill[s * 64 + l].  The lane's own draws fill slots
+// 0, 1, ... (a register count); the drains, which resolve any lane's draws,
+// fill slots kLaneCap - 1, kLaneCap - 2, ... (an LDS count per owner).
 __device__ __forceinline__ void lane_slot_store(LaneRegion* L, int64_t* spill, int owner, int s,
                                                 int64_t x) {
-  if (s < kCL)
-    L->ov[s * 64 + owner] = x;
-  else
-    spill[(s - kCL) * 64 + owner] = x;
+  spill[s * 64 + owner] = x;
 }
 __device__ __forceinline__ void lane_insert(LaneRegion* L, int64_t* spill, int owner, int64_t x) {
   if (x <= kHLB) {
@@ -1102,12 +1109,10 @@ __device__ __forceinline__ void lane_wave(const DevCell& c, int32_t cell_id, int
   // data-dependent moves), eight values at a time against one pass over all
   // of them (independent reads), and the order-free sums are taken on the way.
   // Value q of the lane: its own slots 0..myc-1, then the drains' slots.
-  const int64_t* o = L->ov + lane;
   const int64_t* g = spill + lane;
-  int64_t* srt = spill + 64 * kLaneSpill + lane;  // entry p at srt[p * 64]
+  int64_t* srt = spill + 64 * kLaneCap + lane;  // entry p at srt[p * 64]
   auto ovv = [&](int q) -> int64_t {
-    const int sl = q < myc ? q : kLaneCap - od + (q - myc);
-    return sl < kCL ? o[sl * 64] : g[(sl - kCL) * 64];
+    return g[(q < myc ? q : kLaneCap - od + (q - myc)) * 64];
   };
   for (int i0 = 0; i0 < oc; i0 += 8) {
     int64_t v[8];
@@ -1340,10 +1345,8 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         wave_sync();
       } else if (oc > 64u) {
         const int P = next_pow2((int)oc);
-        for (int k = (int)oc + lane; k < P; k += 64) L->ov[k] = INT64_MAX;
-        wave_sync();
         static_assert(kCW <= 512, "the wave form's overflow is sorted in registers");
-        wave_sort_small(L->ov, P, lane);  // one LDS read and one write per value
+        wave_sort_small(L->ov, P, (int)oc, lane);  // one LDS read and one write per value
         wave_sync();
       }
       const Summary s = build_list(L->hist, hi, L->ov, (int)oc, lv + used, lc + used, lane,
@@ -1389,7 +1392,10 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
 // LDS when the cell changes.  Lane-form units give one replicate to each
 // lane; wave-form units give 64 replicates to each wave.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock, 1) void k_simulate(
+// Three waves per SIMD: the twelve waves' LDS regions and the shared table
+// fit one workgroup per compute unit, and the register budget is 168 per lane.
+static_assert(kBlock == 768, "twelve waves per workgroup, one workgroup per compute unit");
+__global__ __launch_bounds__(kBlock, 3) void k_simulate(
     const DevCell* __restrict__ cells, const double* __restrict__ tables,
     const uint16_t* __restrict__ guides, const double* __restrict__ ln,
     const Unit* __restrict__ units, int n_units, uint32_t* queue, Outputs out,

@@ -28,20 +28,18 @@ constexpr int kGuide = kGA + (kOctaves << kGBits);
 
 // Simulation kernel geometry: 8 wave64 per workgroup share the CDF table and
 // the guide in LDS.
-constexpr int kWaves = 8;
+constexpr int kWaves = 12;  // three per SIMD
 constexpr int kBlock = 64 * kWaves;
 // Lane form: one replicate per lane; per-lane histogram of values 1..kHLB
-// (16-bit counters packed two per dword) plus a per-lane list of the larger
-// values: the first kCL in LDS ...
+// (16-bit counters packed two per dword) plus a per-lane list of up to
+// kLaneCap larger values in the wave's global scratch (a replicate with more
+// is redone by the heavy form).
 constexpr int kHLB = 48;
-constexpr int kCL = 8;
-// ... and kLaneSpill more per lane in the wave's global scratch (a replicate
-// with more than kCL + kLaneSpill is redone by the heavy form).
-constexpr int kLaneSpill = 120;
+constexpr int kLaneCap = 128;
 // Wave form: one replicate per wave at a time; histogram of values 1..kHW
 // plus up to kCW larger values in LDS; finishes run one replicate per lane.
 constexpr int kHW = 1024;
-constexpr int kCW = 512;
+constexpr int kCW = 248;
 // Compact (value, count) list capacity per wave for deferred finishes.
 constexpr int kListCap = 16 * (kHW + kCW);
 // Heavy form: 4 wave64 per workgroup, values above kHeavyHist in per-wave
