@@ -133,6 +133,21 @@ def test_extreme_exponents(ctx, orc, form):
     assert np.sum(g["flags"][600:1300] & 1) > 600  # all-ones replicates at alpha = 8, 20
 
 
+def test_wave_overflow_escalation(ctx, orc):
+    """Forced into the wave form, replicates whose values above the 1,024-bin
+    histogram exceed its 248-entry LDS area are redone by the heavy form:
+    alpha = 1.3, n = 3000 has about 320 such values per replicate (every
+    replicate escalates), alpha = 1.5, n = 10^4 about 240 (about a third do);
+    every replicate against the oracle."""
+    cells = [(1.3, 3000, 64, 11, 60), (1.5, 10000, 64, 11, 61)]
+    say("wave overflow escalation")
+    g = run_cells(ctx, cells, form="wave")
+    lo = 0
+    for cell in cells:
+        compare_cell(orc, g, lo, cell)
+        lo += cell[2]
+
+
 def test_forms_and_launches_bit_identical(ctx):
     """Same replicate, same bits: lane / wave / heavy forms, plain vs batched
     launches and hipGraph replay all give identical outputs."""

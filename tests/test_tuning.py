@@ -48,11 +48,13 @@ def test_table_picks_cheapest_form():
 
 
 def test_table_respects_eligibility():
-    # lane cheapest everywhere, but at alpha = 1.5, n = 1e4 a replicate has
-    # about 1,100 values above 48 (lane ineligible) and about 240 above 1024
-    # (wave still eligible)
+    # lane cheapest everywhere, but at alpha = 1.5, n = 4000 a replicate has
+    # about 440 values above 48 (lane ineligible: 128 slots) and about 96
+    # above 1024 (wave eligible: 248 entries); at n = 1e4, about 240 above
+    # 1024 (wave ineligible too)
     t = grid([1.5, 3.5], [10, 100000], lambda a, n: (1.0, 2.0, 3.0))
-    assert plan_forms([(1.5, 10000, R, 1, 0)], t) == ["wave"]
+    assert plan_forms([(1.5, 4000, R, 1, 0)], t) == ["wave"]
+    assert plan_forms([(1.5, 10000, R, 1, 0)], t) == ["heavy"]
     assert plan_forms([(1.2, 10000, R, 1, 0)], t) == ["heavy"]
     assert plan_forms([(3.0, 70000, R, 1, 0)], t) == ["wave"]  # n > 65535
 
