@@ -719,10 +719,31 @@ __device__ __forceinline__ void block_store(const int64_t (&v)[E], int64_t* a, i
   for (int t = 0; t < E; ++t) a[lane + 64 * t] = v[t];
 }
 
-// Ascending bitonic sort of a[0..nv) padded to P (a power of two, 128..512)
-// by one wave, entirely in registers (P / 64 values per lane; positions from
-// nv on count as INT64_MAX and are neither read nor written); a is LDS or
-// global memory, read once and written once by the calling wave.
+// Ascending bitonic sort of a[0..P) (P a power of two, 128..512) by one wave,
+// entirely in registers (P / 64 values per lane); a is LDS or global memory,
+// read once and written once by the calling wave.
+__device__ __forceinline__ void wave_sort_small(int64_t* a, int P, int lane) {
+  if (P == 128) {
+    int64_t v[2];
+    block_load<2>(v, a, lane);
+    block_sort<2>(v, 0, lane);
+    block_store<2>(v, a, lane);
+  } else if (P == 256) {
+    int64_t v[4];
+    block_load<4>(v, a, lane);
+    block_sort<4>(v, 0, lane);
+    block_store<4>(v, a, lane);
+  } else {
+    int64_t v[8];
+    block_load<8>(v, a, lane);
+    block_sort<8>(v, 0, lane);
+    block_store<8>(v, a, lane);
+  }
+}
+
+// The same for a[0..nv) padded to P: positions from nv on count as INT64_MAX
+// and are neither read nor written (the wave form's LDS area holds fewer
+// than P entries).
 template <int E>
 __device__ __forceinline__ void block_load_n(int64_t (&v)[E], const int64_t* a, int nv, int lane) {
 #pragma unroll
@@ -734,22 +755,17 @@ __device__ __forceinline__ void block_store_n(const int64_t (&v)[E], int64_t* a,
   for (int t = 0; t < E; ++t)
     if (lane + 64 * t < nv) a[lane + 64 * t] = v[t];
 }
-__device__ __forceinline__ void wave_sort_small(int64_t* a, int P, int nv, int lane) {
+__device__ __forceinline__ void wave_sort_small_n(int64_t* a, int P, int nv, int lane) {
   if (P == 128) {
     int64_t v[2];
     block_load_n<2>(v, a, nv, lane);
     block_sort<2>(v, 0, lane);
     block_store_n<2>(v, a, nv, lane);
-  } else if (P == 256) {
+  } else {
     int64_t v[4];
     block_load_n<4>(v, a, nv, lane);
     block_sort<4>(v, 0, lane);
     block_store_n<4>(v, a, nv, lane);
-  } else {
-    int64_t v[8];
-    block_load_n<8>(v, a, nv, lane);
-    block_sort<8>(v, 0, lane);
-    block_store_n<8>(v, a, nv, lane);
   }
 }
 
@@ -800,7 +816,7 @@ __device__ __forceinline__ void mem_group(int64_t* g, int P, int k, int j1, int 
 // array takes 7 round trips through memory instead of 78 passes.
 __device__ void wave_sort_global(int64_t* g, int P, int lane) {
   if (P <= 512) {
-    wave_sort_small(g, P, P, lane);
+    wave_sort_small(g, P, lane);
     wave_sync_global();
     return;
   }
@@ -1345,8 +1361,8 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         wave_sync();
       } else if (oc > 64u) {
         const int P = next_pow2((int)oc);
-        static_assert(kCW <= 512, "the wave form's overflow is sorted in registers");
-        wave_sort_small(L->ov, P, (int)oc, lane);  // one LDS read and one write per value
+        static_assert(kCW <= 256, "the wave form's overflow is sorted in registers");
+        wave_sort_small_n(L->ov, P, (int)oc, lane);  // one LDS read and one write per value
         wave_sync();
       }
       const Summary s = build_list(L->hist, hi, L->ov, (int)oc, lv + used, lc + used, lane,
