@@ -119,9 +119,13 @@ struct zpl_ctx {
   // context's GPU (looked up once, at creation)
   int64_t* noalloc_scratch = nullptr;
   // scratch, grow-only
-  DevBuf cells, tables, guides, units, hunits, queues, esc, esc_cnt, err, list_v, list_c,
-      wslots, heavy, dbuf, gather, qnum, qden, qout, fit_x, fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d,
-      scan;
+  // plan: the cells, then (simulation calls) the units, heavy units and the
+  // quantile numerators and denominators, uploaded with one copy; ctr: the
+  // work queues, escalation count and error word, cleared with one fill,
+  // then the quantile results, so that error word and quantiles come back
+  // with one copy (layout: PlanLayout)
+  DevBuf plan, ctr, tables, guides, esc, list_v, list_c, wslots, heavy, dbuf, gather, fit_x,
+      fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d, scan;
   // pinned host staging
   void* pin = nullptr;
   size_t pin_bytes = 0;
@@ -131,9 +135,9 @@ struct zpl_ctx {
   bool graph_valid = false;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<char> graph_key;
-  // The plan buffers (cells, units, hunits, qnum, qden) are rewritten by
-  // every call; plan_gen counts the uploads, and a replay re-uploads its
-  // plan when another call wrote the buffers after it (graph_plan_gen).
+  // The plan buffer is rewritten by every call; plan_gen counts the uploads,
+  // and a replay re-uploads its plan when another call wrote the buffer
+  // after it (graph_plan_gen).
   uint64_t plan_gen = 0, graph_plan_gen = 0;
   uint32_t esc_cap = 0;
   // optional per-kernel timing of the last non-graph simulation
@@ -141,6 +145,7 @@ struct zpl_ctx {
   bool timing = false;
   bool timed = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t err_off = 0;  // byte offset of the last simulation's error word in ctr
   Tuning tune;  // measured form costs (empty: built-in rule)
 };
 
@@ -530,25 +535,53 @@ int64_t heavy_stride(int64_t max_n) {
   return 2 * half;
 }
 
+// Byte offsets of a simulation call's parts in the plan and ctr buffers.
+// plan: cells | units | heavy units | q_num | q_den, each part 256-byte
+// aligned.  ctr (32-bit words): the work queues (nc + 8, rounded up to even),
+// the escalation count (4), the error word (4), then the nc * n_q quantile
+// results (doubles), so that [error word .. quantiles] is contiguous.
+struct PlanLayout {
+  size_t units = 0, hunits = 0, qnum = 0, qden = 0, plan_bytes = 0;
+  int ctr_words = 0;           // words cleared before each run
+  size_t esc = 0, err = 0, qout = 0, ctr_bytes = 0;
+};
+
+PlanLayout plan_layout(const Plan& P, int n_q) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t nc = P.cells.size();
+  PlanLayout L;
+  L.units = up(sizeof(DevCell) * nc);
+  L.hunits = L.units + up(sizeof(Unit) * P.units.size());
+  L.qnum = L.hunits + up(sizeof(Unit) * P.hunits.size());
+  L.qden = L.qnum + up(sizeof(uint32_t) * (size_t)n_q);
+  L.plan_bytes = L.qden + sizeof(uint32_t) * (size_t)n_q;
+  const size_t qw = (nc + 8 + 1) & ~(size_t)1;
+  L.esc = sizeof(uint32_t) * qw;
+  L.err = L.esc + sizeof(uint32_t) * 4;
+  L.qout = L.err + sizeof(uint32_t) * 4;
+  L.ctr_words = (int)(qw + 8);
+  L.ctr_bytes = L.qout + sizeof(double) * nc * (size_t)n_q;
+  return L;
+}
+
 struct Launch {
   int sim_grid = 0;
   int heavy_grid = 0;
   int64_t hstride = 0;
   int64_t gcap = 0;
   int64_t maxR = 1;
+  PlanLayout lay;
 };
 
 // Grows every scratch buffer the plan needs.
 zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L) {
   const int nc = (int)P.cells.size();
-  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell) * nc));
+  L.lay = plan_layout(P, n_q);
+  ZPL_TRY(ensure(c, c->plan, L.lay.plan_bytes));
+  ZPL_TRY(ensure(c, c->ctr, L.lay.ctr_bytes));
+  c->err_off = L.lay.err;
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * (size_t)kH * nc));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (size_t)(kGuide + 1) * nc));
-  ZPL_TRY(ensure(c, c->units, sizeof(Unit) * std::max<size_t>(1, P.units.size())));
-  ZPL_TRY(ensure(c, c->hunits, sizeof(Unit) * std::max<size_t>(1, P.hunits.size())));
-  ZPL_TRY(ensure(c, c->queues, sizeof(uint32_t) * (size_t)(nc + 8)));
-  ZPL_TRY(ensure(c, c->esc_cnt, sizeof(uint32_t) * 4));
-  ZPL_TRY(ensure(c, c->err, sizeof(uint32_t) * 4));
   // escalation list: a slot for every lane/wave replicate (each escalates at
   // most once), so it cannot overflow below 2^31 such replicates
   const uint32_t esc_cap =
@@ -569,9 +602,6 @@ zpl_status prepare(zpl_ctx* c, const Plan& P, int n_q, bool need_dbuf, Launch& L
   L.heavy_grid = hg;
   ZPL_TRY(ensure(c, c->heavy, sizeof(int64_t) * (size_t)hg * kHeavyWaves * L.hstride));
   if (need_dbuf) ZPL_TRY(ensure(c, c->dbuf, sizeof(double) * (size_t)P.total_R));
-  ZPL_TRY(ensure(c, c->qnum, sizeof(uint32_t) * std::max(n_q, 1)));
-  ZPL_TRY(ensure(c, c->qden, sizeof(uint32_t) * std::max(n_q, 1)));
-  ZPL_TRY(ensure(c, c->qout, sizeof(double) * std::max(nc * n_q, 1)));
   // bracket gather: at most ~12% of a cell's replicates fall in a bracket
   int64_t maxR = 1;
   for (const DevCell& d : P.cells) maxR = std::max(maxR, d.R);
@@ -592,16 +622,17 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
   auto mark = [&](int k) -> hipError_t {
     return timed ? hipEventRecord(c->ev[k], s) : hipSuccess;
   };
-  DevCell* dcells = (DevCell*)c->cells.p;
-  uint32_t* queues = (uint32_t*)c->queues.p;
-  HIP_TRY(launch_fill_u32(queues, nc + 8, 0u, s));
-  HIP_TRY(launch_fill_u32((uint32_t*)c->esc_cnt.p, 4, 0u, s));
-  HIP_TRY(launch_fill_u32((uint32_t*)c->err.p, 4, 0u, s));
+  char* plan = (char*)c->plan.p;
+  char* ctr = (char*)c->ctr.p;
+  DevCell* dcells = (DevCell*)plan;
+  uint32_t* queues = (uint32_t*)ctr;
+  uint32_t* escc = (uint32_t*)(ctr + L.lay.esc);
+  uint32_t* err = (uint32_t*)(ctr + L.lay.err);
+  HIP_TRY(launch_fill_u32(queues, L.lay.ctr_words, 0u, s));
   HIP_TRY(mark(0));
   HIP_TRY(launch_tables(dcells, nc, (double*)c->tables.p, (uint16_t*)c->guides.p, c->ln, s));
   HIP_TRY(mark(1));
-  const Unit* units = (const Unit*)c->units.p;
-  uint32_t* escc = (uint32_t*)c->esc_cnt.p;
+  const Unit* units = (const Unit*)(plan + L.lay.units);
   if (launch == ZPL_LAUNCH_PLAIN) {
     for (int i = 0; i < nc; ++i) {
       const int b = P.cell_unit_begin[i], e = P.cell_unit_end[i];
@@ -611,36 +642,40 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
                               (const uint16_t*)c->guides.p, c->ln, units + b, e - b,
                               queues + 8 + i, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
                               (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p, c->wslots.p,
-                              (uint32_t*)c->err.p, s));
+                              err, s));
     }
   } else {
     HIP_TRY(launch_simulate(L.sim_grid, dcells, (const double*)c->tables.p,
                             (const uint16_t*)c->guides.p, c->ln, units, (int)P.units.size(),
                             queues + 0, out, (uint64_t*)c->esc.p, escc, c->esc_cap,
                             (int64_t*)c->list_v.p, (uint32_t*)c->list_c.p, c->wslots.p,
-                            (uint32_t*)c->err.p, s));
+                            err, s));
   }
   HIP_TRY(mark(2));
   HIP_TRY(launch_heavy(L.heavy_grid, dcells, (const double*)c->tables.p,
-                       (const uint16_t*)c->guides.p, c->ln, (const Unit*)c->hunits.p,
+                       (const uint16_t*)c->guides.p, c->ln, (const Unit*)(plan + L.lay.hunits),
                        (int)P.hunits.size(), (const uint64_t*)c->esc.p, escc, c->esc_cap,
                        queues + 2, out, (int64_t*)c->heavy.p, L.hstride, s));
   HIP_TRY(mark(3));
   if (n_q > 0 && Dsel)
-    HIP_TRY(launch_select(Dsel, dcells, nc, n_q, (const uint32_t*)c->qnum.p,
-                          (const uint32_t*)c->qden.p, (double*)c->qout.p,
+    HIP_TRY(launch_select(Dsel, dcells, nc, n_q, (const uint32_t*)(plan + L.lay.qnum),
+                          (const uint32_t*)(plan + L.lay.qden), (double*)(ctr + L.lay.qout),
                           (uint64_t*)c->gather.p, L.gcap, L.maxR, c->n_cu, s));
   HIP_TRY(mark(4));
   return ZPL_OK;
 }
 
-zpl_status check_err_word(zpl_ctx* c, hipStream_t s) {
-  uint32_t e = 0;
-  HIP_TRY(hipMemcpyAsync(&e, c->err.p, sizeof e, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+zpl_status err_word_status(uint32_t e) {
   if (e & kErrEscOverflow)
     return fail(ZPL_ENOMEM, "escalation list overflow (too many replicates exceeded their form's capacity)");
   return ZPL_OK;
+}
+
+zpl_status check_err_word(zpl_ctx* c, hipStream_t s) {
+  uint32_t e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, (char*)c->ctr.p + c->err_off, sizeof e, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return err_word_status(e);
 }
 
 // Simulation of a plan with outputs; shared by zpl_simulate_cells and the
@@ -686,29 +721,29 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
   }
   put(&out, sizeof out);
   put(&s, sizeof s);
+  // the plan itself: it also depends on the tuning table and the device
+  put(P.cells.data(), sizeof(DevCell) * P.cells.size());
+  put(P.units.data(), sizeof(Unit) * P.units.size());
+  put(P.hunits.data(), sizeof(Unit) * P.hunits.size());
   const bool replay = o.use_graph && o.launch == ZPL_LAUNCH_BATCHED && c->graph_valid &&
                       c->graph_key == key;
+  // pinned staging: the plan upload, then (from dl_off) the error word and
+  // the quantiles on their way back
+  const PlanLayout& Y = L.lay;
+  const size_t dl_off = (Y.plan_bytes + 255) & ~(size_t)255;
+  const size_t dl_bytes = need_sel ? Y.ctr_bytes - Y.err : 0;
+  ZPL_TRY(ensure_pinned(c, dl_off + dl_bytes));
+  char* pin = (char*)c->pin;
   if (!replay || c->plan_gen != c->graph_plan_gen) {
-    // upload the plan
-    const size_t bc = sizeof(DevCell) * P.cells.size(), bu = sizeof(Unit) * P.units.size(),
-                 bh = sizeof(Unit) * P.hunits.size(), bq = sizeof(uint32_t) * (size_t)n_q;
-    ZPL_TRY(ensure_pinned(c, bc + bu + bh + 2 * bq + 64));
     HIP_TRY(hipStreamSynchronize(s));  // the staging area may still be in use
-    char* pin = (char*)c->pin;
-    std::memcpy(pin, P.cells.data(), bc);
-    std::memcpy(pin + bc, P.units.data(), bu);
-    std::memcpy(pin + bc + bu, P.hunits.data(), bh);
+    std::memcpy(pin, P.cells.data(), sizeof(DevCell) * P.cells.size());
+    std::memcpy(pin + Y.units, P.units.data(), sizeof(Unit) * P.units.size());
+    std::memcpy(pin + Y.hunits, P.hunits.data(), sizeof(Unit) * P.hunits.size());
     if (n_q) {
-      std::memcpy(pin + bc + bu + bh, q_num, bq);
-      std::memcpy(pin + bc + bu + bh + bq, q_den, bq);
+      std::memcpy(pin + Y.qnum, q_num, sizeof(uint32_t) * n_q);
+      std::memcpy(pin + Y.qden, q_den, sizeof(uint32_t) * n_q);
     }
-    HIP_TRY(hipMemcpyAsync(c->cells.p, pin, bc, hipMemcpyHostToDevice, s));
-    if (bu) HIP_TRY(hipMemcpyAsync(c->units.p, pin + bc, bu, hipMemcpyHostToDevice, s));
-    if (bh) HIP_TRY(hipMemcpyAsync(c->hunits.p, pin + bc + bu, bh, hipMemcpyHostToDevice, s));
-    if (n_q) {
-      HIP_TRY(hipMemcpyAsync(c->qnum.p, pin + bc + bu + bh, bq, hipMemcpyHostToDevice, s));
-      HIP_TRY(hipMemcpyAsync(c->qden.p, pin + bc + bu + bh + bq, bq, hipMemcpyHostToDevice, s));
-    }
+    HIP_TRY(hipMemcpyAsync(c->plan.p, pin, Y.plan_bytes, hipMemcpyHostToDevice, s));
     ++c->plan_gen;
   }
   const double* Dsel = need_sel ? out.D : nullptr;
@@ -747,9 +782,14 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
     c->timed = c->timing;
   }
   if (need_sel) {
-    HIP_TRY(hipMemcpyAsync(quantiles, c->qout.p, sizeof(double) * (size_t)n_cells * n_q,
-                           hipMemcpyDeviceToHost, s));
-    ZPL_TRY(check_err_word(c, s));
+    // error word and quantiles in one copy to pinned memory
+    HIP_TRY(hipMemcpyAsync(pin + dl_off, (char*)c->ctr.p + Y.err, dl_bytes, hipMemcpyDeviceToHost,
+                           s));
+    HIP_TRY(hipStreamSynchronize(s));
+    uint32_t e;
+    std::memcpy(&e, pin + dl_off, sizeof e);
+    ZPL_TRY(err_word_status(e));
+    std::memcpy(quantiles, pin + dl_off + (Y.qout - Y.err), sizeof(double) * (size_t)n_cells * n_q);
   }
   return ZPL_OK;
 }
@@ -1379,10 +1419,10 @@ void zpl_destroy(zpl_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   if (c->graph_valid) (void)hipGraphExecDestroy(c->graph_exec);
-  DevBuf* bufs[] = {&c->cells, &c->tables, &c->guides, &c->units, &c->hunits, &c->queues,
-                    &c->esc, &c->esc_cnt, &c->err, &c->list_v, &c->list_c, &c->wslots, &c->heavy, &c->gather,
-                    &c->dbuf, &c->qnum, &c->qden, &c->qout, &c->fit_x, &c->fit_ptrs,
-                    &c->fit_ns, &c->fit_out, &c->fit_st, &c->count, &c->boot_d, &c->scan};
+  DevBuf* bufs[] = {&c->plan,   &c->ctr,      &c->tables, &c->guides, &c->esc,
+                    &c->list_v, &c->list_c,   &c->wslots, &c->heavy,  &c->gather,
+                    &c->dbuf,   &c->fit_x,    &c->fit_ptrs, &c->fit_ns, &c->fit_out,
+                    &c->fit_st, &c->count,    &c->boot_d, &c->scan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->ln) (void)hipFree(c->ln);
@@ -1839,18 +1879,18 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmi
   zpl_cell z = {alpha, n, count, seed, stream_id, kmax, xmin};
   Plan P;
   ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha, kmax and xmin
-  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
+  ZPL_TRY(ensure(c, c->plan, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
   ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
-  HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->plan.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
   ++c->plan_gen;
-  HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
+  HIP_TRY(launch_tables((DevCell*)c->plan.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
                         c->ln, s));
   HIP_TRY(launch_fill_u32(flags_out, (int)count, 0u, s));
-  HIP_TRY(launch_draws((const DevCell*)c->cells.p, (const double*)c->tables.p,
+  HIP_TRY(launch_draws((const DevCell*)c->plan.p, (const double*)c->tables.p,
                        (const uint16_t*)c->guides.p, rep_lo, count, x_out, flags_out,
                        count * n, s));
   return ZPL_OK;
@@ -1865,15 +1905,15 @@ zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmin, 
   zpl_cell z = {alpha, 1, 1, 0, 0, kmax, xmin};
   Plan P;
   ZPL_TRY(make_plan(&z, 1, ZPL_FORM_HEAVY, P));  // validates alpha, kmax and xmin
-  ZPL_TRY(ensure(c, c->cells, sizeof(DevCell)));
+  ZPL_TRY(ensure(c, c->plan, sizeof(DevCell)));
   ZPL_TRY(ensure(c, c->tables, sizeof(double) * kH));
   ZPL_TRY(ensure(c, c->guides, sizeof(uint16_t) * (kGuide + 1)));
   ZPL_TRY(ensure_pinned(c, sizeof(DevCell)));
   HIP_TRY(hipStreamSynchronize(s));
   std::memcpy(c->pin, &P.cells[0], sizeof(DevCell));
-  HIP_TRY(hipMemcpyAsync(c->cells.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->plan.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
   ++c->plan_gen;
-  HIP_TRY(launch_tables((DevCell*)c->cells.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
+  HIP_TRY(launch_tables((DevCell*)c->plan.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
                         c->ln, s));
   HIP_TRY(hipMemcpyAsync(T_out, c->tables.p, sizeof(double) * kH, hipMemcpyDeviceToDevice, s));
   return ZPL_OK;

@@ -104,3 +104,24 @@ def test_graph_replay_after_other_calls(ctx):
     for _ in range(3):
         assert same(outputs(ctx, A, use_graph=True), eager_a)
     assert same(outputs(ctx, B), eager_b)
+
+
+def test_graph_replay_after_tuning_change(ctx):
+    """A captured graph is tied to its plan: after the tuning table changes
+    the forms (and so the units), the next graph call must capture anew."""
+    from paper_1305_6738_amd import plan_forms
+    A = [(2.5, 200, 100000, 21, 0), (3.0, 60, 50000, 21, 1)]
+    ctx.set_tuning(None)
+    eager = outputs(ctx, A)
+    for f, name in [(0, "lane"), (2, "heavy"), (1, "wave")]:
+        cost = [5.0, 5.0, 5.0]
+        cost[f] = 1.0
+        t = [{"alpha": a, "n": n, "ns_per_replicate": cost} for a in (1.5, 3.5)
+             for n in (10, 100000)]
+        ctx.set_tuning(t)
+        forms = plan_forms(A, t)
+        say("graph under tuning toward", name, forms)
+        assert forms == [name, name]
+        assert same(outputs(ctx, A, use_graph=True), eager), name
+        assert same(outputs(ctx, A, use_graph=True), eager), name  # replay
+    ctx.set_tuning(None)
