@@ -86,8 +86,10 @@ def progress(msg):
 
 PROFILE = ROOT / "profiles" / "k_simulate_table_n1000.md"
 HEAVY_PROFILE = ROOT / "profiles" / "k_heavy_heavy_tail.md"
+# the device code's sources and the build script (its compiler flags)
 KERNEL_SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
-                  "paper_1305_6738_amd/csrc/zpl_math.hpp"]
+                  "paper_1305_6738_amd/csrc/zpl_math.hpp", "paper_1305_6738_amd/csrc/zpl_exp2_table.hpp",
+                  "paper_1305_6738_amd/_build.py"]
 
 
 def kernel_source_hash():

@@ -17,8 +17,10 @@ COPY_MIB = 256
 NOMINAL_HZ = 2.4e9
 N_CU, SIMD_PER_CU = 256, 4
 STEPS = 5  # the timed steps of profile.sh's bench command
+# the device code's sources and the build script (its compiler flags)
 SOURCES = ["paper_1305_6738_amd/csrc/zpl_kernels.hip", "paper_1305_6738_amd/csrc/zpl_kernels.hpp",
-           "paper_1305_6738_amd/csrc/zpl_math.hpp"]
+           "paper_1305_6738_amd/csrc/zpl_math.hpp", "paper_1305_6738_amd/csrc/zpl_exp2_table.hpp",
+           "paper_1305_6738_amd/_build.py"]
 
 
 def source_hash():
