@@ -2044,20 +2044,23 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // bit patterns as unsigned integers orders the values.  Up to kSelQ quantiles
 // at a time, in three launches:
 //   1. k_sel_bracket (a workgroup per cell): a sample of kSelSample values at
-//      fixed positions is sorted in LDS, and each quantile takes the sample
-//      values 5 standard deviations of the sample rank around its expected
-//      position as a bracket [lo, hi];
+//      fixed positions is sorted (each wave's 256 values in registers, the
+//      stages across waves in LDS), and each quantile takes the sample values
+//      5 standard deviations of the sample rank around its expected position
+//      as a bracket [lo, hi];
 //   2. k_sel_gather (many workgroups per cell, each a slice of D): counts the
 //      values below each bracket and gathers the values inside it into global
 //      scratch, through per-(cell, quantile) counters;
 //   3. k_sel_finish (a workgroup per cell): the rank k - below is selected
 //      exactly among the gathered values by radix selection (11-bit digits),
-//      the quantiles side by side.
+//      the quantiles side by side, each from registers when its gathered
+//      values fit (kSelRegs per thread), else re-read from scratch per digit.
 // If rank k falls outside its bracket, or the bracket overflows its scratch,
 // the radix selection runs over all of D instead.  Both give the same element.
 // ---------------------------------------------------------------------------
-constexpr int kSelSample = 2048;
+constexpr int kSelSample = 4096;
 constexpr int kSelUnroll = 8;
+constexpr int kSelRegs = 24;  // gathered values per thread of a quantile group held in registers
 static_assert(kHW % 256 == 0 && kHeavyHist % 256 == 0, "build_list reads 256 bins per step");
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
@@ -2067,26 +2070,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
     if (lane >= d) v += o;
   }
   return v;
-}
-
-// Ascending bitonic sort of a[0..P) (P a power of two) by the whole block.
-__device__ void block_bitonic_u64(uint64_t* a, int P) {
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = (int)threadIdx.x; i < P; i += (int)blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t x = a[i], y = a[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
 }
 
 struct SelLds {
@@ -2197,6 +2180,14 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
     L.gmask[g] = m;
     L.gkrem[g] = kg;
   }
+  // the group's values in registers when they fit (loaded once for all digits)
+  const bool inreg = actg && cnt <= (int64_t)256 * kSelRegs;
+  uint64_t rv[kSelRegs];
+#pragma unroll
+  for (int u = 0; u < kSelRegs; ++u) {
+    const int64_t i = (int64_t)u * 256 + gt;
+    rv[u] = inreg && i < cnt ? src[i] : 0ull;
+  }
   __syncthreads();
   uint32_t* hist = L.u.hist[g];
   for (int p = 0; maxtop - 11 * p >= 0; ++p) {
@@ -2208,7 +2199,14 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
     if (on)
       for (int b = gt; b < 2048; b += 256) hist[b] = 0u;
     __syncthreads();
-    if (on) {
+    if (on && inreg) {
+      const uint64_t pre = L.gprefix[g], msk = L.gmask[g];
+#pragma unroll
+      for (int u = 0; u < kSelRegs; ++u) {
+        const int64_t i = (int64_t)u * 256 + gt;
+        if (i < cnt && (rv[u] & msk) == pre) atomicAdd(&hist[(rv[u] >> sh) & dm], 1u);
+      }
+    } else if (on) {
       const uint64_t pre = L.gprefix[g], msk = L.gmask[g];
       for (int64_t i0 = 0; i0 < cnt; i0 += 256 * kSelUnroll) {
         uint64_t bv[kSelUnroll];
@@ -2270,10 +2268,45 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
   const DevCell c = cells[cell];
   const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
   const int64_t R = c.R;
-  for (int t = tid; t < kSelSample; t += 1024)
-    sample[t] = bits[(int64_t)(((uint64_t)t * (uint64_t)R) / kSelSample)];
+  // Bitonic sort of the sample, element t held by wave t / 256 (lane t % 64,
+  // slot (t / 64) % 4): the stages with j < 256 run in registers
+  // (block_passes), those with j >= 256 in LDS, one pair per thread.  The
+  // register passes compare signed values, so the bit patterns are stored
+  // with the top bit flipped (unsigned order = signed order of the flips).
+  constexpr int kE = 4;
+  static_assert(kSelSample == 1024 / 64 * 64 * kE, "16 waves x 256 sample values");
+  const int lane = tid & 63, base = (tid >> 6) * 64 * kE;
+  const uint64_t flip = 1ull << 63;
+  int64_t v[kE];
+#pragma unroll
+  for (int t = 0; t < kE; ++t) {
+    const uint64_t pos = (uint64_t)(base + lane + 64 * t);
+    v[t] = (int64_t)(bits[(int64_t)((pos * (uint64_t)R) / kSelSample)] ^ flip);
+  }
+  block_sort<kE>(v, base, lane);  // stages k <= 256
+  for (int k = 128 * kE; k <= kSelSample; k <<= 1) {
+#pragma unroll
+    for (int t = 0; t < kE; ++t) sample[base + lane + 64 * t] = (uint64_t)v[t];
+    __syncthreads();
+    for (int j = k >> 1; j >= 64 * kE; j >>= 1) {
+      for (int h = tid; h < kSelSample / 2; h += 1024) {
+        const int i = ((h & ~(j - 1)) << 1) | (h & (j - 1));  // bit j of i clear
+        const int64_t x = (int64_t)sample[i], y = (int64_t)sample[i | j];
+        if ((x > y) == ((i & k) == 0)) {
+          sample[i] = (uint64_t)y;
+          sample[i | j] = (uint64_t)x;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < kE; ++t) v[t] = (int64_t)sample[base + lane + 64 * t];
+    block_passes<kE>(v, base, k, 32 * kE, lane);  // stages j < 256
+    __syncthreads();  // every wave has read sample before the next stores
+  }
+#pragma unroll
+  for (int t = 0; t < kE; ++t) sample[base + lane + 64 * t] = (uint64_t)v[t] ^ flip;
   __syncthreads();
-  block_bitonic_u64(sample, kSelSample);
   if (tid < nq) {
     const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
     const double qf = (double)k / (double)R;
