@@ -402,7 +402,7 @@ def main(argv=None):
                          "traffic that scales the profiler's FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         return 2
 
