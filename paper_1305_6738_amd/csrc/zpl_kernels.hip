@@ -2044,10 +2044,13 @@ __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
 // bit patterns as unsigned integers orders the values.  Up to kSelQ quantiles
 // at a time, in three launches:
 //   1. k_sel_bracket (a workgroup per cell): a sample of kSelSample values at
-//      fixed positions is sorted (each wave's 256 values in registers, the
-//      stages across waves in LDS), and each quantile takes the sample values
-//      5 standard deviations of the sample rank around its expected position
-//      as a bracket [lo, hi];
+//      fixed positions; each quantile brackets the sample values 5 standard
+//      deviations of the sample rank around its expected position.  Instead of
+//      sorting the sample, a histogram of the 11 bits below the sample's common
+//      high bits (with each bin's smallest and largest value) locates the bins
+//      of those two ranks; the bracket [lo, hi] runs from the smallest value of
+//      the lower bin to the largest of the upper (it contains the two sample
+//      values, and is a single value when one value fills the bin);
 //   2. k_sel_gather (many workgroups per cell, each a slice of D): counts the
 //      values below each bracket and gathers the values inside it into global
 //      scratch, through per-(cell, quantile) counters;
@@ -2262,64 +2265,119 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
                                                      int nq, const uint32_t* __restrict__ qnum,
                                                      const uint32_t* __restrict__ qden,
                                                      SelMeta* __restrict__ meta) {
-  __shared__ uint64_t sample[kSelSample];
+  constexpr int kSpt = kSelSample / 1024;  // sample values per thread
+  __shared__ uint32_t cnt[2048];
+  __shared__ unsigned long long bmin[2048], bmax[2048];
+  __shared__ uint64_t wor[16], wand[16];
+  __shared__ int bin_of[2 * kSelQ];
+  __shared__ uint64_t sample[kSelSample];  // for the exact order statistics (rare case)
+  __shared__ SelLds L;
   const int cell = (int)blockIdx.x;
-  const int tid = (int)threadIdx.x;
+  const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const DevCell c = cells[cell];
   const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
   const int64_t R = c.R;
-  // Bitonic sort of the sample, element t held by wave t / 256 (lane t % 64,
-  // slot (t / 64) % 4): the stages with j < 256 run in registers
-  // (block_passes), those with j >= 256 in LDS, one pair per thread.  The
-  // register passes compare signed values, so the bit patterns are stored
-  // with the top bit flipped (unsigned order = signed order of the flips).
-  constexpr int kE = 4;
-  static_assert(kSelSample == 1024 / 64 * 64 * kE, "16 waves x 256 sample values");
-  const int lane = tid & 63, base = (tid >> 6) * 64 * kE;
-  const uint64_t flip = 1ull << 63;
-  int64_t v[kE];
+  uint64_t x[kSpt];
+  uint64_t o = 0ull, an = ~0ull;
 #pragma unroll
-  for (int t = 0; t < kE; ++t) {
-    const uint64_t pos = (uint64_t)(base + lane + 64 * t);
-    v[t] = (int64_t)(bits[(int64_t)((pos * (uint64_t)R) / kSelSample)] ^ flip);
-  }
-  block_sort<kE>(v, base, lane);  // stages k <= 256
-  for (int k = 128 * kE; k <= kSelSample; k <<= 1) {
-#pragma unroll
-    for (int t = 0; t < kE; ++t) sample[base + lane + 64 * t] = (uint64_t)v[t];
-    __syncthreads();
-    for (int j = k >> 1; j >= 64 * kE; j >>= 1) {
-      for (int h = tid; h < kSelSample / 2; h += 1024) {
-        const int i = ((h & ~(j - 1)) << 1) | (h & (j - 1));  // bit j of i clear
-        const int64_t x = (int64_t)sample[i], y = (int64_t)sample[i | j];
-        if ((x > y) == ((i & k) == 0)) {
-          sample[i] = (uint64_t)y;
-          sample[i | j] = (uint64_t)x;
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < kE; ++t) v[t] = (int64_t)sample[base + lane + 64 * t];
-    block_passes<kE>(v, base, k, 32 * kE, lane);  // stages j < 256
-    __syncthreads();  // every wave has read sample before the next stores
+  for (int t = 0; t < kSpt; ++t) {
+    const uint64_t pos = (uint64_t)(tid + 1024 * t);
+    x[t] = bits[(int64_t)((pos * (uint64_t)R) / kSelSample)];
+    sample[pos] = x[t];
+    o |= x[t];
+    an &= x[t];
   }
 #pragma unroll
-  for (int t = 0; t < kE; ++t) sample[base + lane + 64 * t] = (uint64_t)v[t] ^ flip;
+  for (int m = 32; m > 0; m >>= 1) {
+    o |= shfl_xor_u64(o, m);
+    an &= shfl_xor_u64(an, m);
+  }
+  if (lane == 0) {
+    wor[wave] = o;
+    wand[wave] = an;
+  }
+  for (int b = tid; b < 2048; b += 1024) {
+    cnt[b] = 0u;
+    bmin[b] = ~0ull;
+    bmax[b] = 0ull;
+  }
   __syncthreads();
-  if (tid < nq) {
-    const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
+  o = 0ull;
+  an = ~0ull;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    o |= wor[w];
+    an &= wand[w];
+  }
+  // the sample's common high bits, then an 11-bit digit below them
+  const uint64_t diff = o ^ an;
+  const int top = diff ? 63 - __clzll((long long)diff) : 0;
+  const int sh = top > 10 ? top - 10 : 0;
+#pragma unroll
+  for (int t = 0; t < kSpt; ++t) {
+    const int d = (int)((x[t] >> sh) & 2047u);
+    atomicAdd(&cnt[d], 1u);
+    atomicMin(&bmin[d], (unsigned long long)x[t]);
+    atomicMax(&bmax[d], (unsigned long long)x[t]);
+  }
+  __syncthreads();
+  // sample ranks a = p - dl and b = p + dl of each quantile, as in the sorted
+  // sample; the bin holding rank r is the first whose running count exceeds r
+  auto ranks = [&](int q, int64_t& a, int64_t& b) {
+    const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + q]) / qden[q0 + q]);
     const double qf = (double)k / (double)R;
     const int64_t p = (int64_t)(qf * kSelSample);
     const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
-    const int64_t a = p - dl, b = p + dl;
-    SelMeta m;
-    m.lo = a <= 0 ? 0ull : sample[a];
-    m.hi = b >= kSelSample - 1 ? ~0ull : sample[b];
-    m.below = 0ull;
-    m.nb = 0u;
-    m.pad = 0u;
-    meta[(size_t)cell * kSelQ + tid] = m;
+    a = p - dl;
+    b = p + dl;
+  };
+  if (wave == 0) {
+    uint32_t sum = 0;
+    for (int t = 0; t < 32; ++t) sum += cnt[lane * 32 + t];
+    const uint32_t incl = wave_incl_scan_u32(sum, lane);
+    for (int r = 0; r < 2 * nq; ++r) {
+      int64_t a, b;
+      ranks(r >> 1, a, b);
+      int64_t rk = (r & 1) ? b : a;
+      rk = rk < 0 ? 0 : (rk > kSelSample - 1 ? kSelSample - 1 : rk);
+      const uint64_t hit = __ballot((int64_t)incl > rk);
+      const int owner = __ffsll((long long)hit) - 1;
+      if (lane == owner) {
+        int64_t kk = rk - (int64_t)(incl - sum);
+        int d = lane * 32;
+        while ((int64_t)cnt[d] <= kk) {
+          kk -= cnt[d];
+          ++d;
+        }
+        bin_of[r] = d;
+      }
+    }
+  }
+  __syncthreads();
+  // The bracket holds [sample[a], sample[b]]: the smallest value of a's bin
+  // and the largest of b's.  When both ranks fall in one bin that holds more
+  // than one value, sample[a] and sample[b] themselves are selected (radix
+  // selection over the sample), so that a value filling ranks a..b (an atom
+  // of D) still gives lo = hi.
+  for (int q = 0; q < nq; ++q) {
+    int64_t a, b;
+    ranks(q, a, b);
+    const int ba = bin_of[2 * q], bb = bin_of[2 * q + 1];
+    uint64_t lo = a <= 0 ? 0ull : (uint64_t)bmin[ba];
+    uint64_t hi = b >= kSelSample - 1 ? ~0ull : (uint64_t)bmax[bb];
+    if (a > 0 && b < kSelSample - 1 && ba == bb && bmin[ba] != bmax[ba]) {
+      lo = radix_select(L, sample, kSelSample, a, 63, 0ull);
+      hi = radix_select(L, sample, kSelSample, b, 63, 0ull);
+    }
+    if (tid == 0) {
+      SelMeta m;
+      m.lo = lo;
+      m.hi = hi;
+      m.below = 0ull;
+      m.nb = 0u;
+      m.pad = 0u;
+      meta[(size_t)cell * kSelQ + q] = m;
+    }
   }
 }
 
