@@ -628,9 +628,12 @@ zpl_status enqueue_run(zpl_ctx* c, const Plan& P, int launch, const Launch& L, O
   uint32_t* queues = (uint32_t*)ctr;
   uint32_t* escc = (uint32_t*)(ctr + L.lay.esc);
   uint32_t* err = (uint32_t*)(ctr + L.lay.err);
-  HIP_TRY(launch_fill_u32(queues, L.lay.ctr_words, 0u, s));
+  bool any_trunc = false;
+  for (const DevCell& d : P.cells) any_trunc = any_trunc || d.K != 0u;
   HIP_TRY(mark(0));
-  HIP_TRY(launch_tables(dcells, nc, (double*)c->tables.p, (uint16_t*)c->guides.p, c->ln, s));
+  // the table kernel also clears the counters
+  HIP_TRY(launch_tables(dcells, nc, (double*)c->tables.p, (uint16_t*)c->guides.p, c->ln, s,
+                        any_trunc, queues, L.lay.ctr_words));
   HIP_TRY(mark(1));
   const Unit* units = (const Unit*)(plan + L.lay.units);
   if (launch == ZPL_LAUNCH_PLAIN) {
@@ -1888,7 +1891,7 @@ zpl_status zpl_sample_draws(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmi
   HIP_TRY(hipMemcpyAsync(c->plan.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
   ++c->plan_gen;
   HIP_TRY(launch_tables((DevCell*)c->plan.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
-                        c->ln, s));
+                        c->ln, s, z.kmax != 0));
   HIP_TRY(launch_fill_u32(flags_out, (int)count, 0u, s));
   HIP_TRY(launch_draws((const DevCell*)c->plan.p, (const double*)c->tables.p,
                        (const uint16_t*)c->guides.p, rep_lo, count, x_out, flags_out,
@@ -1914,7 +1917,7 @@ zpl_status zpl_cdf_table(zpl_ctx* c, double alpha, uint32_t kmax, int64_t xmin, 
   HIP_TRY(hipMemcpyAsync(c->plan.p, c->pin, sizeof(DevCell), hipMemcpyHostToDevice, s));
   ++c->plan_gen;
   HIP_TRY(launch_tables((DevCell*)c->plan.p, 1, (double*)c->tables.p, (uint16_t*)c->guides.p,
-                        c->ln, s));
+                        c->ln, s, z.kmax != 0));
   HIP_TRY(hipMemcpyAsync(T_out, c->tables.p, sizeof(double) * kH, hipMemcpyDeviceToDevice, s));
   return ZPL_OK;
 }

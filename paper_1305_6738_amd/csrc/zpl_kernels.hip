@@ -1924,7 +1924,11 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_table(const DevCell* __restrict__ cells,
                                               double* __restrict__ tables,
-                                              const double* __restrict__ ln) {
+                                              const double* __restrict__ ln,
+                                              uint32_t* __restrict__ zero, int n_zero) {
+  // the first block also clears the simulation's counters (one launch fewer)
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int i = (int)threadIdx.x; i < n_zero; i += (int)blockDim.x) zero[i] = 0u;
   const int cell = (int)blockIdx.y;
   const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x) + 1;
   if (k > kH || cells[cell].K != 0u) return;
@@ -2620,14 +2624,17 @@ hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t s) {
 }
 
 hipError_t launch_tables(DevCell* cells, int n_cells, double* tables, uint16_t* guides,
-                         const double* ln, hipStream_t s) {
+                         const double* ln, hipStream_t s, bool any_trunc, uint32_t* zero,
+                         int n_zero) {
   if (n_cells <= 0) return hipSuccess;
-  k_table<<<dim3(kH / 256, n_cells), 256, 0, s>>>(cells, tables, ln);
+  k_table<<<dim3(kH / 256, n_cells), 256, 0, s>>>(cells, tables, ln, zero, n_zero);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_table_trunc<<<n_cells, 1024, 0, s>>>(cells, tables, ln);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (any_trunc) {
+    k_table_trunc<<<n_cells, 1024, 0, s>>>(cells, tables, ln);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   k_guide<<<dim3((kGuide + 1 + 255) / 256, n_cells), 256, 0, s>>>(cells, tables, guides);
   return hipGetLastError();
 }

@@ -9,8 +9,11 @@ namespace zpl {
 
 hipError_t launch_ln_table(double* ln, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int n, uint32_t v, hipStream_t s);
+// CDF tables (the truncated law's only when any_trunc: a cell with K > 0)
+// and packed guides; the first table block also zeroes zero[0..n_zero).
 hipError_t launch_tables(DevCell* cells, int n_cells, double* tables, uint16_t* guides,
-                         const double* ln, hipStream_t s);
+                         const double* ln, hipStream_t s, bool any_trunc = true,
+                         uint32_t* zero = nullptr, int n_zero = 0);
 hipError_t launch_simulate(int grid, const DevCell* cells, const double* tables,
                            const uint16_t* guides, const double* ln, const Unit* units,
                            int n_units, uint32_t* queue, Outputs out, uint64_t* esc_list,
