@@ -121,9 +121,9 @@ struct zpl_ctx {
   // scratch, grow-only
   // plan: the cells, then (simulation calls) the units, heavy units and the
   // quantile numerators and denominators, uploaded with one copy; ctr: the
-  // work queues, escalation count and error word, cleared with one fill,
-  // then the quantile results, so that error word and quantiles come back
-  // with one copy (layout: PlanLayout)
+  // work queues, escalation count and error word, cleared by the table
+  // kernel, then the quantile results, so that error word and quantiles come
+  // back with one copy (layout: PlanLayout)
   DevBuf plan, ctr, tables, guides, esc, list_v, list_c, wslots, heavy, dbuf, gather, fit_x,
       fit_ptrs, fit_ns, fit_out, fit_st, count, boot_d, scan;
   // pinned host staging
