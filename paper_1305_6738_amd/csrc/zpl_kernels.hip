@@ -1365,8 +1365,9 @@ __device__ __forceinline__ void wave_batch(const DevCell& c, int32_t cell_id, in
         wave_sort_small_n(L->ov, P, (int)oc, lane);  // one LDS read and one write per value
         wave_sync();
       }
-      const Summary s = build_list(L->hist, hi, L->ov, (int)oc, lv + used, lc + used, lane,
-                                   ln, n, out.fp != nullptr || out.xmax != nullptr);
+      Summary s;
+      [[clang::always_inline]] s = build_list(L->hist, hi, L->ov, (int)oc, lv + used, lc + used,
+                                              lane, ln, n, out.fp != nullptr || out.xmax != nullptr);
       if (lane == 0) {
         WaveSlot sl;
         sl.S = s.S;
@@ -1482,8 +1483,12 @@ struct GlobalSync {
 // Histogram/overflow fill, sort, compact list and finish of one replicate by
 // one wave.  fill(sink, flags) calls sink(x) for every value.
 // K = 0: the pure law; K > 0: the truncated law on 1..K (values above K are
-// invalid, like values below 1).
-template <class Fill>
+// invalid, like values below 1).  kInlineList: the list build is inlined (the
+// fit kernels; out of line, with the histogram reached through a flat
+// pointer, a fit has been seen to return a wrong estimate); else the
+// compiler decides (the heavy kernel keeps it out of line, which spares its
+// registers, and passes every test).
+template <bool kInlineList, class Fill>
 __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int64_t* lv,
                            uint32_t* lc, const double* __restrict__ ln, uint32_t K, bool want_fp,
                            double& a, double& D, uint32_t& flags, uint64_t& fp, int64_t& xmax,
@@ -1531,7 +1536,13 @@ __device__ void heavy_core(HeavyWave* W, int64_t n, Fill fill, int64_t* gov, int
     wave_sync_global();
     wave_sort_global(gov, P, lane);
   }
-  const Summary s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, want_fp);
+  Summary s;
+  if constexpr (kInlineList) {
+    [[clang::always_inline]] s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n,
+                                            want_fp);
+  } else {
+    s = build_list(W->hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, want_fp);
+  }
   wave_sync_global();
   finish_replicate_wave(lv, lc, s.len, s.S, n, fl, ln, lane, K, a, D, flags, xmin);
   fp = s.fp;
@@ -1652,7 +1663,7 @@ __device__ void heavy_replicate(HeavyWave* W, const uint64_t* __restrict__ T,
   uint64_t fp;
   int64_t xmax;
   bool ok;
-  heavy_core(W, n, fill, gov, lv, lc, ln, c.K, out.fp != nullptr || out.xmax != nullptr, a, D,
+  heavy_core<false>(W, n, fill, gov, lv, lc, ln, c.K, out.fp != nullptr || out.xmax != nullptr, a, D,
              flags, fp, xmax, ok, c.xmin);
   if (lane == 0) write_outputs(out, c.out_off + rep, D, a, flags, fp, xmax);
   wave_sync_global();
@@ -1810,7 +1821,8 @@ __global__ __launch_bounds__(64 * kFitWaves) void k_fit_block(
     if (lane == 0) status_out[0] = kErrBadValue;
     return;
   }
-  const Summary sm = build_list(W.hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, false);
+  Summary sm;
+  [[clang::always_inline]] sm = build_list(W.hist, kHeavyHist, gov, oc, lv, lc, lane, ln, n, false);
   wave_sync_global();
   double a = 0.0, D = 0.0;
   uint32_t flags = 0;
@@ -1871,7 +1883,7 @@ __global__ __launch_bounds__(64) void k_fit_scan(const int64_t* __restrict__ x, 
     uint64_t fp;
     int64_t xmax;
     bool ok;
-    heavy_core(&W, (int64_t)cnt, fill, gov, lv, lc, ln, 0u, false, a, D, flags, fp, xmax, ok,
+    heavy_core<true>(&W, (int64_t)cnt, fill, gov, lv, lc, ln, 0u, false, a, D, flags, fp, xmax, ok,
                xmin);
     if (lane == 0) {
       ahat_out[cand] = a;
@@ -1907,7 +1919,7 @@ __global__ __launch_bounds__(64) void k_fit(const int64_t* const* __restrict__ x
     uint64_t fp;
     int64_t xmax;
     bool ok;
-    heavy_core(&W, n, fill, gov, lv, lc, ln, K, false, a, D, flags, fp, xmax, ok);
+    heavy_core<true>(&W, n, fill, gov, lv, lc, ln, K, false, a, D, flags, fp, xmax, ok);
     if (lane == 0) {
       ahat_out[set] = a;
       D_out[set] = D;
