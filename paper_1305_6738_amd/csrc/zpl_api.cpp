@@ -484,35 +484,66 @@ zpl_status make_plan(const zpl_cell* cells, int n_cells, int form, Plan& P,
   // lane (64 in these units) in the lane form.  Weighing by count instead
   // sent each wave-form cell's last, partial unit to the end of the queue,
   // where it ran as long as a full one on an otherwise idle device.
-  std::vector<std::pair<double, Unit>> tmp;
+  // Every unit of a cell but the last holds kBlock replicates, so a cell's
+  // units take at most two weights: the order is built from at most two runs
+  // of units per cell (sorted by weight, then cell; a run keeps ascending
+  // replicates), not by sorting the units themselves.
+  struct Run {
+    double w;
+    int cell;
+    int64_t r_begin, r_end;  // units start at r_begin, r_begin + kBlock, ... < r_end
+  };
+  std::vector<Run> runs;
+  size_t n_units = 0;
   for (int i = 0; i < n_cells; ++i) {
     const DevCell& d = P.cells[i];
-    const int per = d.mode == kModeHeavy ? 8 : kBlock;
+    const int64_t r0 = rlo ? rlo[i] : 0;
+    if (d.mode == kModeHeavy) {
+      for (int64_t r = 0; r < d.R; r += 8) {
+        Unit u;
+        u.cell = i;
+        u.r0 = r0 + r;
+        u.count = (int32_t)std::min<int64_t>(8, d.R - r);
+        P.hunits.push_back(u);
+      }
+      continue;
+    }
+    if (d.R <= 0) continue;
     double w = d.K ? (double)d.n + 8.6 * (double)d.K : (double)d.n;
     if (tune && !tune->empty()) {
       const double v = d.K ? trunc_cost(d.n, d.K) : tuned_cost(*tune, (int)d.mode, d.alpha, d.n);
       if (v > 0.0) w = v;
     }
-    const int64_t r0 = rlo ? rlo[i] : 0;
-    for (int64_t r = 0; r < d.R; r += per) {
-      Unit u;
-      u.cell = i;
-      u.r0 = r0 + r;
-      u.count = (int32_t)std::min<int64_t>(per, d.R - r);
-      if (d.mode == kModeHeavy)
-        P.hunits.push_back(u);
-      else
-        tmp.push_back({w * (d.mode == kModeLane ? 64.0 : (double)std::min<int32_t>(u.count, 64)),
-                       u});
+    auto weight = [&](int64_t count) {
+      return w * (d.mode == kModeLane ? 64.0 : (double)std::min<int64_t>(count, 64));
+    };
+    const int64_t r_last = (d.R - 1) / kBlock * kBlock;
+    const double w_last = weight(d.R - r_last);
+    if (r_last > 0 && weight(kBlock) != w_last) {
+      runs.push_back({weight(kBlock), i, 0, r_last});
+      runs.push_back({w_last, i, r_last, d.R});
+    } else {
+      runs.push_back({w_last, i, 0, d.R});
     }
+    n_units += (size_t)((d.R + kBlock - 1) / kBlock);
   }
   // longest units first; ties by cell so a workgroup tends to keep its table
-  std::stable_sort(tmp.begin(), tmp.end(), [](const auto& a, const auto& b) {
-    if (a.first != b.first) return a.first > b.first;
-    return a.second.cell < b.second.cell;
+  std::sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) {
+    if (a.w != b.w) return a.w > b.w;
+    return a.cell < b.cell;
   });
-  P.units.reserve(tmp.size());
-  for (auto& t : tmp) P.units.push_back(t.second);
+  P.units.reserve(n_units);
+  for (const Run& g : runs) {
+    const DevCell& d = P.cells[g.cell];
+    const int64_t r0 = rlo ? rlo[g.cell] : 0;
+    for (int64_t r = g.r_begin; r < g.r_end; r += kBlock) {
+      Unit u;
+      u.cell = g.cell;
+      u.r0 = r0 + r;
+      u.count = (int32_t)std::min<int64_t>(kBlock, d.R - r);
+      P.units.push_back(u);
+    }
+  }
   return ZPL_OK;
 }
 
@@ -709,8 +740,10 @@ zpl_status run_cells(zpl_ctx* c, const zpl_cell* cells, int n_cells, const uint3
   ZPL_TRY(prepare(c, P, n_q, need_dbuf, L));
   if (need_dbuf) out.D = (double*)c->dbuf.p;
   // graph key: everything the captured launches depend on
+  const bool graphed = o.use_graph && o.launch == ZPL_LAUNCH_BATCHED;
   std::vector<char> key;
   auto put = [&](const void* p, size_t b) {
+    if (!graphed) return;
     const char* q = (const char*)p;
     key.insert(key.end(), q, q + b);
   };

@@ -2091,6 +2091,31 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
   return v;
 }
 
+// The bin of a 2048-bin histogram that holds rank kk (0-based: the first bin
+// whose running count exceeds kk), found by one whole wave.  `sum` is the
+// lane's total of bins 32 lane .. 32 lane + 31 and `incl` the inclusive scan
+// of those totals across the wave.  The lane owning the rank is found from a
+// ballot; its 32 bins are then scanned across lanes 0..31 (one LDS read per
+// lane instead of a walk of up to 32 dependent reads).  Returns the bin, and
+// in rem the rank inside it, identical on every lane; -1 when kk is not below
+// the histogram's total (then rem is kk).
+__device__ __forceinline__ int rank_bin(const uint32_t* hist, uint32_t incl, uint32_t sum,
+                                        int64_t kk, int lane, int64_t& rem,
+                                        uint32_t* bin_count = nullptr) {
+  rem = kk;
+  const uint64_t hit = __ballot((int64_t)incl > kk);
+  if (hit == 0ull) return -1;
+  const int owner = __ffsll((long long)hit) - 1;
+  const int64_t base = (int64_t)(uint32_t)__shfl((int)(incl - sum), owner, 64);
+  const uint32_t h = lane < 32 ? hist[owner * 32 + lane] : 0u;
+  const uint32_t s = wave_incl_scan_u32(h, lane);  // lanes 32..63 add zeros
+  const uint64_t hit2 = __ballot(lane < 32 && base + (int64_t)s > kk);
+  const int j = __ffsll((long long)hit2) - 1;
+  rem = kk - base - (int64_t)(uint32_t)__shfl((int)(s - h), j, 64);
+  if (bin_count) *bin_count = (uint32_t)__shfl((int)h, j, 64);
+  return owner * 32 + j;
+}
+
 struct SelLds {
   struct {
     uint32_t hist[kSelQ][2048];  // one per quantile group; the block-wide select uses [0]
@@ -2099,6 +2124,7 @@ struct SelLds {
   int64_t krem;
   uint64_t gprefix[kSelQ], gmask[kSelQ];
   int64_t gkrem[kSelQ];
+  int gstate[kSelQ];  // per group: 0 digits to select, 1 a single value left, 2 done
 };
 
 // Exact radix selection (11-bit digits) of rank k of bits[0..R), block-wide.
@@ -2140,16 +2166,9 @@ __device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, i
       uint32_t sum = 0;
       for (int t = 0; t < 32; ++t) sum += L.u.hist[0][lane * 32 + t];
       const uint32_t incl = wave_incl_scan_u32(sum, lane);
-      const int64_t kk0 = L.krem;
-      const uint64_t hit = __ballot((int64_t)incl > kk0);
-      const int owner = __ffsll((long long)hit) - 1;
-      if (lane == owner) {
-        int64_t kk = kk0 - (int64_t)(incl - sum);
-        int d = lane * 32;
-        while ((int64_t)L.u.hist[0][d] <= kk) {
-          kk -= L.u.hist[0][d];
-          ++d;
-        }
+      int64_t kk;
+      const int d = rank_bin(L.u.hist[0], incl, sum, L.krem, lane, kk);
+      if (lane == 0 && d >= 0) {
         L.krem = kk;
         L.prefix = pre | ((uint64_t)d << sh);
         L.mask = msk | ((uint64_t)dm << sh);
@@ -2164,9 +2183,11 @@ __device__ uint64_t radix_select(SelLds& L, const uint64_t* __restrict__ bits, i
 // 256g..256g+255 of the 1024-thread block) selects rank k[g] of its own
 // array a[g][0..n[g]), whose values share the bits above top[g] with
 // common[g]; groups with act[g] false idle.  Same digits, same result as
-// radix_select, with the quantiles' passes running side by side.  Every
-// barrier is reached by the whole block: the loop runs over the longest
-// digit sequence and finished groups idle through the rest.
+// radix_select, with the quantiles' passes running side by side.  When the
+// bin holding the rank has a single value and digits remain, the next pass
+// instead finds that value (the only one matching the prefix so far) and the
+// group is done.  Every barrier is reached by the whole block: the loop runs
+// until no group has a pass left, finished groups idling.
 __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ],
                                     const int64_t (&n)[kSelQ], const int64_t (&k)[kSelQ],
                                     const int (&top)[kSelQ], const uint64_t (&common)[kSelQ],
@@ -2198,6 +2219,7 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
     L.gprefix[g] = comg & m;
     L.gmask[g] = m;
     L.gkrem[g] = kg;
+    L.gstate[g] = actg ? 0 : 2;
   }
   // the group's values in registers when they fit (loaded once for all digits)
   const bool inreg = actg && cnt <= (int64_t)256 * kSelRegs;
@@ -2211,7 +2233,9 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
   uint32_t* hist = L.u.hist[g];
   for (int p = 0; maxtop - 11 * p >= 0; ++p) {
     const int hb = topg - 11 * p;
-    const bool on = actg && hb >= 0;
+    const int st = L.gstate[g];
+    const bool on = actg && hb >= 0 && st == 0;
+    const bool find = actg && st == 1;
     const int width = hb + 1 < 11 ? hb + 1 : 11;
     const int sh = hb + 1 - width;
     const uint32_t dm = on ? (1u << width) - 1u : 0u;
@@ -2240,28 +2264,48 @@ __device__ void radix_select_groups(SelLds& L, const uint64_t* const (&a)[kSelQ]
           if (i < cnt && (bv[u] & msk) == pre) atomicAdd(&hist[(bv[u] >> sh) & dm], 1u);
         }
       }
+    } else if (find) {  // exactly one value matches: it is the result
+      const uint64_t pre = L.gprefix[g], msk = L.gmask[g];
+      if (inreg) {
+#pragma unroll
+        for (int u = 0; u < kSelRegs; ++u) {
+          const int64_t i = (int64_t)u * 256 + gt;
+          if (i < cnt && (rv[u] & msk) == pre) L.gprefix[g] = rv[u];
+        }
+      } else {
+        for (int64_t i = gt; i < cnt; i += 256) {
+          const uint64_t v = src[i];
+          if ((v & msk) == pre) L.gprefix[g] = v;
+        }
+      }
     }
     __syncthreads();
     if (on && scanner) {
       uint32_t sum = 0;
       for (int t = 0; t < 32; ++t) sum += hist[lane * 32 + t];
       const uint32_t incl = wave_incl_scan_u32(sum, lane);
-      const int64_t kk0 = L.gkrem[g];
-      const uint64_t hit = __ballot((int64_t)incl > kk0);
-      const int owner = __ffsll((long long)hit) - 1;
-      if (lane == owner) {
-        int64_t kk = kk0 - (int64_t)(incl - sum);
-        int d = lane * 32;
-        while ((int64_t)hist[d] <= kk) {
-          kk -= hist[d];
-          ++d;
-        }
+      int64_t kk;
+      uint32_t nbin = 0;
+      const int d = rank_bin(hist, incl, sum, L.gkrem[g], lane, kk, &nbin);
+      if (lane == 0 && d >= 0) {
         L.gkrem[g] = kk;
         L.gprefix[g] = L.gprefix[g] | ((uint64_t)d << sh);
         L.gmask[g] = L.gmask[g] | ((uint64_t)dm << sh);
+        if (nbin == 1u && sh > 0) L.gstate[g] = 1;
       }
     }
+    if (find && gt == 0) {
+      L.gmask[g] = ~0ull;
+      L.gstate[g] = 2;
+    }
     __syncthreads();
+    // another pass only while some group has digits or its single value left
+    bool more = false;
+#pragma unroll
+    for (int q = 0; q < kSelQ; ++q)
+      if (act[q] && (L.gstate[q] == 1 || (L.gstate[q] == 0 && top[q] - 11 * (p + 1) >= 0)))
+        more = true;
+    if (!more) break;
   }
 #pragma unroll
   for (int q = 0; q < kSelQ; ++q) res[q] = L.gprefix[q];
@@ -2286,6 +2330,7 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
   __shared__ unsigned long long bmin[2048], bmax[2048];
   __shared__ uint64_t wor[16], wand[16];
   __shared__ int bin_of[2 * kSelQ];
+  __shared__ int64_t rank_ab[2 * kSelQ];  // sample ranks a, b of each quantile
   __shared__ uint64_t sample[kSelSample];  // for the exact order statistics (rare case)
   __shared__ SelLds L;
   const int cell = (int)blockIdx.x;
@@ -2293,6 +2338,16 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
   const DevCell c = cells[cell];
   const uint64_t* bits = reinterpret_cast<const uint64_t*>(D + c.out_off);
   const int64_t R = c.R;
+  // sample ranks a = p - dl and b = p + dl of each quantile, as in the sorted
+  // sample (published by the first barrier below)
+  if (tid < nq) {
+    const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + tid]) / qden[q0 + tid]);
+    const double qf = (double)k / (double)R;
+    const int64_t p = (int64_t)(qf * kSelSample);
+    const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
+    rank_ab[2 * tid] = p - dl;
+    rank_ab[2 * tid + 1] = p + dl;
+  }
   uint64_t x[kSpt];
   uint64_t o = 0ull, an = ~0ull;
 #pragma unroll
@@ -2337,36 +2392,17 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
     atomicMax(&bmax[d], (unsigned long long)x[t]);
   }
   __syncthreads();
-  // sample ranks a = p - dl and b = p + dl of each quantile, as in the sorted
-  // sample; the bin holding rank r is the first whose running count exceeds r
-  auto ranks = [&](int q, int64_t& a, int64_t& b) {
-    const int64_t k = (int64_t)(((uint64_t)R * qnum[q0 + q]) / qden[q0 + q]);
-    const double qf = (double)k / (double)R;
-    const int64_t p = (int64_t)(qf * kSelSample);
-    const int64_t dl = (int64_t)(5.0 * sqrt((double)kSelSample * qf * (1.0 - qf))) + 8;
-    a = p - dl;
-    b = p + dl;
-  };
+  // the bin holding sample rank r is the first whose running count exceeds r
   if (wave == 0) {
     uint32_t sum = 0;
     for (int t = 0; t < 32; ++t) sum += cnt[lane * 32 + t];
     const uint32_t incl = wave_incl_scan_u32(sum, lane);
     for (int r = 0; r < 2 * nq; ++r) {
-      int64_t a, b;
-      ranks(r >> 1, a, b);
-      int64_t rk = (r & 1) ? b : a;
+      int64_t rk = rank_ab[r];
       rk = rk < 0 ? 0 : (rk > kSelSample - 1 ? kSelSample - 1 : rk);
-      const uint64_t hit = __ballot((int64_t)incl > rk);
-      const int owner = __ffsll((long long)hit) - 1;
-      if (lane == owner) {
-        int64_t kk = rk - (int64_t)(incl - sum);
-        int d = lane * 32;
-        while ((int64_t)cnt[d] <= kk) {
-          kk -= cnt[d];
-          ++d;
-        }
-        bin_of[r] = d;
-      }
+      int64_t kk;
+      const int d = rank_bin(cnt, incl, sum, rk, lane, kk);  // the sample holds 4096 > rk
+      if (lane == 0) bin_of[r] = d;
     }
   }
   __syncthreads();
@@ -2376,8 +2412,7 @@ __global__ __launch_bounds__(1024) void k_sel_bracket(const double* __restrict__
   // selection over the sample), so that a value filling ranks a..b (an atom
   // of D) still gives lo = hi.
   for (int q = 0; q < nq; ++q) {
-    int64_t a, b;
-    ranks(q, a, b);
+    const int64_t a = rank_ab[2 * q], b = rank_ab[2 * q + 1];
     const int ba = bin_of[2 * q], bb = bin_of[2 * q + 1];
     uint64_t lo = a <= 0 ? 0ull : (uint64_t)bmin[ba];
     uint64_t hi = b >= kSelSample - 1 ? ~0ull : (uint64_t)bmax[bb];

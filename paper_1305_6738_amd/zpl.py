@@ -210,7 +210,12 @@ class CellSpec:
     xmin: int = 0  # 0 or 1: none; else the pure law on k >= xmin
 
 
-def _cells(cells: Sequence) -> C.Array:
+def cell_array(cells: Sequence) -> C.Array:
+    """The cells (CellSpec, dict or tuple each) as a zpl_cell array.  Every
+    call that takes cells also takes such an array as it is, so a caller that
+    repeats a call converts its cells once."""
+    if isinstance(cells, C.Array) and cells._type_ is Cell:
+        return cells
     arr = (Cell * len(cells))()
     for i, c in enumerate(cells):
         if isinstance(c, dict):
@@ -220,6 +225,9 @@ def _cells(cells: Sequence) -> C.Array:
         arr[i] = Cell(float(c.alpha), int(c.n), int(c.replicates), int(c.seed), int(c.stream),
                       int(c.kmax), int(c.xmin))
     return arr
+
+
+_cells = cell_array
 
 
 class Context:

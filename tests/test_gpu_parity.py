@@ -307,3 +307,22 @@ def test_quantiles_with_atoms_and_extremes(ctx, orc):
         lo += cell[2]
     # the paper's atoms: Table 1, N = 10, gamma = 3.5: q.90 = .0819
     assert round(q[0, 0], 4) == 0.0819
+
+
+def test_quantiles_beyond_the_register_budget(ctx, orc):
+    """Middle ranks of large cells: the bracket holds more values than the
+    finishing selection keeps in registers (it re-reads them from memory),
+    and with many distinct D values the rank's bin soon holds one value."""
+    qs = [(1, 2), (1, 3), (2, 3), (9, 10), (0, 1), (399999, 400000)]
+    cells = [(2.5, 100, 400000, 7, 0), (1.9, 300, 250001, 8, 1), (3.0, 2, 20000, 9, 2)]
+    R = sum(c[2] for c in cells)
+    d = torch.zeros(R, dtype=torch.float64, device="cuda")
+    say("quantiles beyond the register budget")
+    q = ctx.simulate_cells(cells, quantiles=qs, d_out=d)
+    D = d.cpu().numpy()
+    lo = 0
+    for ci, cell in enumerate(cells):
+        Dc = D[lo:lo + cell[2]]
+        for qi, (a, b) in enumerate(qs):
+            assert q[ci, qi] == orc.quantile(Dc, a, b), (cell, a, b)
+        lo += cell[2]

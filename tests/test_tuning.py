@@ -9,7 +9,7 @@ import math
 
 import pytest
 
-from paper_1305_6738_amd import ZplError, load_tuning, plan_forms, save_tuning
+from paper_1305_6738_amd import ZplError, cell_array, load_tuning, plan_forms, save_tuning
 from inputs import table_slice
 
 
@@ -162,3 +162,13 @@ def test_few_long_replicates_spread_over_the_device():
     t = grid([2.5, 3.0], [10000, 100000], lambda a, n: (-1.0, 208.0, 545.0))
     assert plan_forms([(2.65, 98000, 2500, 1, 0)], t) == ["heavy"]
     assert plan_forms([(2.65, 98000, 10 ** 6, 1, 0)], t) == ["wave"]
+
+
+def test_cell_array_is_taken_as_it_is():
+    # a converted zpl_cell array passes through unchanged and plans the same
+    cells = table_slice(n=1000, R=1000) + [{"alpha": 1.3, "n": 10**4, "replicates": 5}]
+    arr = cell_array(cells)
+    assert cell_array(arr) is arr
+    assert len(arr) == len(cells)
+    assert arr[-1].alpha == 1.3 and arr[-1].n == 10**4 and arr[-1].replicates == 5
+    assert plan_forms(arr) == plan_forms(cells)
