@@ -2516,12 +2516,19 @@ __global__ __launch_bounds__(256) void k_sel_gather(const double* __restrict__ D
     }
     __syncthreads();  // wtot and wbase are reused by the next step
   }
+  // values below each bracket: one atomic per workgroup and quantile (a cell's
+  // counters share a cache line, which every workgroup of the cell updates)
 #pragma unroll
   for (int qq = 0; qq < kSelQ; ++qq) {
-    if (qq < nq) {
-      const uint32_t w = wave_sum_u32(below[qq]);
-      if (lane == 0 && w) atomicAdd(&M[qq].below, (unsigned long long)w);
-    }
+    const uint32_t w = wave_sum_u32(below[qq]);
+    if (lane == 0) wtot[wave][qq] = w;
+  }
+  __syncthreads();
+  if (tid < nq) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) t += wtot[w][tid];
+    if (t) atomicAdd(&M[tid].below, (unsigned long long)t);
   }
 }
 
